@@ -1,0 +1,355 @@
+"""ctypes binding of the FP64 C oracle (test infrastructure only).
+
+The oracle state is a dict of numpy arrays owned here; the C functions work
+on pointers into them.  ``OracleState.as_gpu_state()`` gives the same state
+in the library's single-precision layout, for injection into the HIP path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle_fsne.so")
+
+__all__ = ["build_oracle", "lib", "Hyper", "OracleState", "philox4x32_10", "coin", "E_next",
+           "calibrate", "exact_P", "exact_cost", "exact_grad", "knn_exact", "hd_dist2",
+           "num_threads"]
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile the C oracle with gcc into oracle/liboracle_fsne.so."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    src = os.path.join(_HERE, "fsne_oracle.c")
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-Wall", "-shared",
+           "-fPIC", "-o", tmp, src, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _State(C.Structure):
+    _fields_ = [("N", C.c_int64), ("D", C.c_int32), ("d", C.c_int32), ("K_hd", C.c_int32),
+                ("K_ld", C.c_int32), ("xdtype", C.c_int32), ("seed", C.c_uint64),
+                ("X", C.c_void_p), ("Y", C.c_void_p), ("V", C.c_void_p),
+                ("hd_idx", C.c_void_p), ("hd_d2", C.c_void_p), ("ld_idx", C.c_void_p),
+                ("beta", C.c_void_p), ("m", C.c_void_p), ("r", C.c_void_p),
+                ("invS", C.c_void_p), ("P", C.c_void_p), ("flags", C.c_void_p),
+                ("E", C.c_void_p), ("t", C.c_void_p)]
+
+
+class _Hp(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("perplexity", C.c_double), ("lr", C.c_double),
+                ("momentum", C.c_double), ("attr", C.c_double), ("rep", C.c_double),
+                ("n_neg", C.c_int32), ("hd_mode", C.c_int32), ("e_smooth", C.c_float),
+                ("p_min", C.c_float)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("fired", C.c_int32), ("n_new", C.c_int64), ("Z", C.c_double),
+                ("E", C.c_float), ("t", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build_oracle()
+        L = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        L.fsneo_philox4x32_10.argtypes = [P, P, P]
+        L.fsneo_coin.argtypes = [C.c_float, C.c_uint32, C.c_uint64, C.c_int32, C.c_float]
+        L.fsneo_coin.restype = C.c_int
+        L.fsneo_E_next.argtypes = [C.c_float, C.c_int64, C.c_int64, C.c_float]
+        L.fsneo_E_next.restype = C.c_float
+        L.fsneo_calibrate.argtypes = [P, C.c_int32, C.c_double, P]
+        L.fsneo_calibrate.restype = C.c_int
+        L.fsneo_hd_dist2.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64]
+        L.fsneo_hd_dist2.restype = C.c_double
+        L.fsneo_init.argtypes = [C.POINTER(_State), C.POINTER(_Hp)]
+        L.fsneo_init.restype = C.c_int
+        L.fsneo_step.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.POINTER(_Stats), P, P, P]
+        L.fsneo_step.restype = C.c_int
+        L.fsneo_hd_refine_point.argtypes = [C.POINTER(_State), C.c_int64, C.c_uint32, P, P, P]
+        L.fsneo_psym_row.argtypes = [C.POINTER(_State), C.c_int64, P]
+        L.fsneo_ld_refine_grad_point.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int64,
+                                                 C.c_uint32, P, P, P, P, P, P]
+        L.fsneo_point_step.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int64, C.c_int32,
+                                       P, P, P, P, P, P, P, P, P]
+        L.fsneo_point_step.restype = C.c_int
+        L.fsneo_exact_P.argtypes = [P, C.c_int32, C.c_int64, C.c_int32, C.c_double, P, P]
+        L.fsneo_exact_cost.argtypes = [P, P, C.c_int64, C.c_int32, C.c_double]
+        L.fsneo_exact_cost.restype = C.c_double
+        L.fsneo_exact_grad.argtypes = [P, P, C.c_int64, C.c_int32, C.c_double, P]
+        L.fsneo_knn_exact.argtypes = [P, C.c_int32, C.c_int64, C.c_int32, P, C.c_int64,
+                                      C.c_int32, P, P]
+        L.fsneo_insert.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int64, P]
+        L.fsneo_insert.restype = C.c_int
+        L.fsneo_drift.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P, C.c_int64, P]
+        L.fsneo_drift.restype = C.c_int
+        L.fsneo_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def num_threads() -> int:
+    return lib().fsneo_num_threads()
+
+
+class Hyper:
+    """Hyperparameters of the step (same fields as the library's)."""
+
+    def __init__(self, alpha=1.0, perplexity=10.0, lr=100.0, momentum=0.5, attr=1.0, rep=1.0,
+                 n_neg=8, hd_mode=0, e_smooth=0.1, p_min=0.05):
+        self.alpha, self.perplexity, self.lr, self.momentum = alpha, perplexity, lr, momentum
+        self.attr, self.rep, self.n_neg, self.hd_mode = attr, rep, n_neg, hd_mode
+        self.e_smooth, self.p_min = e_smooth, p_min
+
+    def c(self) -> _Hp:
+        return _Hp(self.alpha, self.perplexity, self.lr, self.momentum, self.attr, self.rep,
+                   int(self.n_neg), int(self.hd_mode), float(self.e_smooth), float(self.p_min))
+
+    def copy(self, **kw):
+        h = Hyper(**self.__dict__)
+        for k, v in kw.items():
+            setattr(h, k, v)
+        return h
+
+
+def _xprep(X):
+    """X as passed to C: float32 rows, or uint16 bfloat16 bit patterns."""
+    X = np.ascontiguousarray(X)
+    if X.dtype == np.float32:
+        return X, 0
+    if X.dtype == np.uint16:
+        return X, 1
+    raise TypeError("X must be float32 or uint16 (bfloat16 bits)")
+
+
+class OracleState:
+    """The oracle's full iteration state (double precision)."""
+
+    def __init__(self, X, d, K_hd, K_ld, seed, Y0, capacity=None):
+        self.X, self.xdtype = _xprep(X)
+        N, D = self.X.shape
+        cap = N if capacity is None else capacity
+        if cap > N:
+            Xc = np.zeros((cap, D), dtype=self.X.dtype)
+            Xc[:N] = self.X
+            self.X = Xc
+        self.N, self.D, self.d, self.K_hd, self.K_ld, self.seed = N, D, d, K_hd, K_ld, seed
+        self.cap = cap
+        self.Y = np.zeros((cap, d), dtype=np.float64)
+        self.Y[:N] = np.asarray(Y0, dtype=np.float64)
+        self.V = np.zeros((cap, d), dtype=np.float64)
+        self.hd_idx = np.zeros((cap, K_hd), dtype=np.int32)
+        self.hd_d2 = np.zeros((cap, K_hd), dtype=np.float64)
+        self.ld_idx = np.zeros((cap, K_ld), dtype=np.int32)
+        self.beta = np.zeros(cap)
+        self.m = np.zeros(cap)
+        self.r = np.zeros(cap)
+        self.invS = np.zeros(cap)
+        self.P = np.zeros((cap, K_hd))
+        self.flags = np.zeros(cap, dtype=np.uint8)
+        self.E = np.ones(1, dtype=np.float32)
+        self.t = np.zeros(1, dtype=np.uint32)
+
+    def cstate(self) -> _State:
+        return _State(self.N, self.D, self.d, self.K_hd, self.K_ld, self.xdtype, self.seed,
+                      self.X.ctypes.data, self.Y.ctypes.data, self.V.ctypes.data,
+                      self.hd_idx.ctypes.data, self.hd_d2.ctypes.data, self.ld_idx.ctypes.data,
+                      self.beta.ctypes.data, self.m.ctypes.data, self.r.ctypes.data,
+                      self.invS.ctypes.data, self.P.ctypes.data, self.flags.ctypes.data,
+                      self.E.ctypes.data, self.t.ctypes.data)
+
+    # -- the method ---------------------------------------------------------
+    def init(self, hp: Hyper):
+        s = self.cstate()
+        rc = lib().fsneo_init(C.byref(s), C.byref(hp.c()))
+        if rc != 0:
+            raise ValueError(f"fsneo_init failed ({rc})")
+        return self
+
+    def step(self, hp: Hyper, want_partials=False):
+        s = self.cstate()
+        st = _Stats()
+        N, d = self.N, self.d
+        A = R = Zh = None
+        if want_partials:
+            A = np.zeros((N, d))
+            R = np.zeros((N, d))
+            Zh = np.zeros(N)
+        rc = lib().fsneo_step(C.byref(s), C.byref(hp.c()), C.byref(st),
+                              None if A is None else _p(A), None if R is None else _p(R),
+                              None if Zh is None else _p(Zh))
+        if rc != 0:
+            raise RuntimeError(f"fsneo_step failed ({rc})")
+        out = dict(fired=st.fired, n_new=st.n_new, Z=st.Z, E=st.E, t=st.t)
+        if want_partials:
+            out.update(A=A, R=R, Zh=Zh)
+        return out
+
+    def point_step(self, hp: Hyper, i: int, fired: int):
+        """Next-iteration outputs of point i alone (sampled checks at large N)."""
+        K, Kl, d = self.K_hd, self.K_ld, self.d
+        hi = np.zeros(K, np.int32)
+        hd = np.zeros(K)
+        fl = np.zeros(1, np.uint8)
+        rec = np.zeros(4)
+        P = np.zeros(K)
+        ld = np.zeros(Kl, np.int32)
+        A = np.zeros(d)
+        R = np.zeros(d)
+        Zh = np.zeros(1)
+        s = self.cstate()
+        rc = lib().fsneo_point_step(C.byref(s), C.byref(hp.c()), int(i), int(fired), _p(hi),
+                                    _p(hd), _p(fl), _p(rec), _p(P), _p(ld), _p(A), _p(R), _p(Zh))
+        if rc != 0:
+            raise RuntimeError("fsneo_point_step failed")
+        return dict(hd_idx=hi, hd_d2=hd, flag=int(fl[0]), rec=rec, P=P, ld_idx=ld, A=A, R=R,
+                    Zh=float(Zh[0]))
+
+    def hd_refine_point(self, i, t=None):
+        K = self.K_hd
+        hi = np.zeros(K, np.int32)
+        hd = np.zeros(K)
+        ch = np.zeros(1, np.uint8)
+        s = self.cstate()
+        lib().fsneo_hd_refine_point(C.byref(s), int(i), int(self.t[0] if t is None else t),
+                                    _p(hi), _p(hd), _p(ch))
+        return hi, hd, int(ch[0])
+
+    def ld_refine_grad_point(self, hp: Hyper, i, t=None):
+        """LD phase of point i against the current HD lists and P (no HD phase)."""
+        Kl, d = self.K_ld, self.d
+        ld = np.zeros(Kl, np.int32)
+        A = np.zeros(d)
+        R = np.zeros(d)
+        Zh = np.zeros(1)
+        s = self.cstate()
+        lib().fsneo_ld_refine_grad_point(C.byref(s), C.byref(hp.c()), int(i),
+                                         int(self.t[0] if t is None else t),
+                                         _p(self.hd_idx), _p(self.P), _p(ld), _p(A), _p(R),
+                                         _p(Zh))
+        return ld, A, R, float(Zh[0])
+
+    def psym_row(self, i):
+        out = np.zeros(self.K_hd)
+        s = self.cstate()
+        lib().fsneo_psym_row(C.byref(s), int(i), _p(out))
+        return out
+
+    def insert(self, hp: Hyper, Xnew, Ynew):
+        Xnew, _ = _xprep(Xnew)
+        n = Xnew.shape[0]
+        if self.N + n > self.cap:
+            raise ValueError("capacity exceeded")
+        self.X[self.N:self.N + n] = Xnew
+        Yn = np.ascontiguousarray(Ynew, dtype=np.float64)
+        s = self.cstate()
+        lib().fsneo_insert(C.byref(s), C.byref(hp.c()), n, _p(Yn))
+        self.N += n
+
+    def drift(self, hp: Hyper, ids, Xnew, Ynew=None):
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        Xnew, _ = _xprep(Xnew)
+        self.X[ids] = Xnew
+        Yn = None if Ynew is None else np.ascontiguousarray(Ynew, dtype=np.float64)
+        s = self.cstate()
+        lib().fsneo_drift(C.byref(s), C.byref(hp.c()), _p(ids), ids.size,
+                          None if Yn is None else _p(Yn))
+
+    # -- views --------------------------------------------------------------
+    def live(self, name):
+        return getattr(self, name)[: self.N]
+
+    def as_gpu_state(self):
+        """The state in the library's layout (single precision, records packed)."""
+        N = self.N
+        rec = np.stack([self.beta[:N], self.m[:N], self.r[:N], self.invS[:N]], axis=1)
+        return dict(
+            Y=self.Y[:N].astype(np.float32), V=self.V[:N].astype(np.float32),
+            hd_idx=self.hd_idx[:N].copy(), hd_d2=self.hd_d2[:N].astype(np.float32),
+            ld_idx=self.ld_idx[:N].copy(), rec=rec.astype(np.float32),
+            P=self.P[:N].astype(np.float32), flags=self.flags[:N].copy(),
+            E=float(self.E[0]), t=int(self.t[0]))
+
+    def copy(self):
+        o = OracleState.__new__(OracleState)
+        for k, v in self.__dict__.items():
+            o.__dict__[k] = v.copy() if isinstance(v, np.ndarray) else v
+        return o
+
+
+# -- free functions ----------------------------------------------------------
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().fsneo_philox4x32_10(_p(c), _p(k), _p(o))
+    return o
+
+
+def coin(E, t, seed, hd_mode=0, p_min=0.05):
+    return lib().fsneo_coin(float(E), int(t), int(seed), int(hd_mode), float(p_min))
+
+
+def E_next(E, n_new, N, lam=0.1):
+    return lib().fsneo_E_next(float(E), int(n_new), int(N), float(lam))
+
+
+def calibrate(d2, perplexity):
+    d2 = np.ascontiguousarray(d2, dtype=np.float64)
+    out = np.zeros(4)
+    noroot = lib().fsneo_calibrate(_p(d2), d2.size, float(perplexity), _p(out))
+    return out, bool(noroot)
+
+
+def hd_dist2(X, a, b):
+    X, xdt = _xprep(X)
+    return lib().fsneo_hd_dist2(_p(X), xdt, X.shape[1], int(a), int(b))
+
+
+def exact_P(X, perplexity):
+    X, xdt = _xprep(X)
+    N = X.shape[0]
+    P = np.zeros((N, N))
+    beta = np.zeros(N)
+    lib().fsneo_exact_P(_p(X), xdt, N, X.shape[1], float(perplexity), _p(P), _p(beta))
+    return P, beta
+
+
+def exact_cost(P, Y, alpha):
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    return lib().fsneo_exact_cost(_p(P), _p(Y), Y.shape[0], Y.shape[1], float(alpha))
+
+
+def exact_grad(P, Y, alpha):
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    G = np.zeros_like(Y)
+    lib().fsneo_exact_grad(_p(P), _p(Y), Y.shape[0], Y.shape[1], float(alpha), _p(G))
+    return G
+
+
+def knn_exact(X, queries, K):
+    X, xdt = _xprep(X)
+    q = np.ascontiguousarray(queries, dtype=np.int64)
+    idx = np.zeros((q.size, K), dtype=np.int32)
+    d2 = np.zeros((q.size, K))
+    lib().fsneo_knn_exact(_p(X), xdt, X.shape[0], X.shape[1], _p(q), q.size, int(K), _p(idx),
+                          _p(d2))
+    return idx, d2
