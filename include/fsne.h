@@ -1,0 +1,189 @@
+/*
+ * fsne.h -- C ABI of the MI355X (gfx950) FUnc-SNE step library, libfsne.so.
+ *
+ * FUnc-SNE (Lambert, Couplet, Verleysen, Lee, "FUnc-SNE: A flexible, Fast, and
+ * Unconstrained algorithm for neighbour embeddings") embeds N points x_i of
+ * R^D into R^d.  One iteration interleaves three things that the paper
+ * describes in Sec. 3:
+ *   - refinement of approximate HD and LD K-nearest-neighbour lists from
+ *     candidates (neighbours of neighbours, cross-space feeds, random
+ *     draws); the HD refinement runs with probability 0.05 + 0.95 E, E the
+ *     smoothed fraction of points that gained HD neighbours;
+ *   - the variable-tailed gradient of eqs. (4)-(6): attraction over the HD
+ *     neighbours' affinities p_ij (eq. (1)), repulsion over HD and LD
+ *     neighbours plus negative samples, normalised by Z;
+ *   - a momentum update of the embedding.
+ *
+ * Conventions
+ *   - Every call returns an fsne_status; no exception or abort crosses the
+ *     ABI.  fsne_last_error() gives the message of the last failing call on
+ *     a context.
+ *   - The caller owns every pointer it passes.  "device" pointers are HIP
+ *     device memory of the current device; "host" pointers are ordinary CPU
+ *     memory.  Each argument says which it is.
+ *   - Work is queued on the context's HIP stream.  fsne_step is asynchronous;
+ *     the get_* calls synchronise the stream before they return.
+ *   - A context is not thread-safe: calls on one context must not overlap.
+ *   - Layouts are row-major: point i's row of an N x W array starts at i*W.
+ *   - N <= 2^31 - 1; K_hd, K_ld <= 64; d <= 64; n_neg <= 64.
+ */
+#ifndef FSNE_H
+#define FSNE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsne_ctx fsne_ctx;
+typedef struct fsne_mlp fsne_mlp;
+
+typedef enum {
+    FSNE_OK = 0,
+    FSNE_EINVAL = -1,     /* an argument is out of range; nothing was changed    */
+    FSNE_ENOMEM = -2,     /* device allocation failed or capacity exceeded       */
+    FSNE_EHIP = -3,       /* a HIP runtime call failed                           */
+    FSNE_ESTATE = -4,     /* the context is not in a state that allows the call  */
+    FSNE_ENONFINITE = -5  /* the embedding holds a NaN or infinity               */
+} fsne_status;
+
+typedef enum { FSNE_F32 = 0, FSNE_BF16 = 1 } fsne_dtype;
+
+/* Hyperparameters; all may change between steps (fsne_set_hyperparams). */
+typedef struct fsne_hparams {
+    float alpha;        /* tail parameter of eq. (4), > 0; 1 is t-SNE             */
+    float perplexity;   /* perplexity of eq. (1), 1 < perplexity < K_hd            */
+    float lr;           /* learning rate of the gradient step, >= 0                */
+    float momentum;     /* momentum of the update, in [0, 1)                       */
+    float attr;         /* attraction scale (early exaggeration), >= 0             */
+    float rep;          /* repulsion scale, >= 0                                   */
+    int32_t n_neg;      /* negative samples per point and iteration, 0..64         */
+    int32_t hd_mode;    /* 0: HD refinement by the coin, 1: every iteration, 2: never */
+    int32_t dist_mode;  /* HD candidate distances: 0 FP32 direct, 1 BF16 MFMA screen
+                           with FP32 re-rank (requires BF16 X)                       */
+    float e_smooth;     /* smoothing weight lambda of E, in (0, 1]                 */
+    float p_min;        /* refinement probability floor (0.05 in the paper)        */
+    float rerank_margin;/* BF16 screen keeps candidates with d2~ <= r_i (1+margin)  */
+} fsne_hparams;
+
+/* Host-side view of the iteration state for checkpoints and checks.  Every
+ * pointer is host memory of the stated size, or NULL to skip that field. */
+typedef struct fsne_state_view {
+    float *Y;           /* N x d embedding                                         */
+    float *V;           /* N x d velocity                                          */
+    int32_t *hd_idx;    /* N x K_hd HD lists, sorted by (d2, index)                */
+    float *hd_d2;       /* N x K_hd squared HD distances of the lists              */
+    int32_t *ld_idx;    /* N x K_ld LD lists                                       */
+    float *rec;         /* N x 4 per-point {beta, m, r, invS}: beta = 1/(2 sigma^2),
+                           m and r the smallest and largest d2 of the HD list,
+                           invS = 1/sum_k exp(-beta (d2_k - m))                      */
+    float *P;           /* N x K_hd symmetrised affinities aligned with hd_idx     */
+    uint8_t *flags;     /* N: 1 where the last HD refinement changed the list      */
+    float *A;           /* N x d attraction partials of the last step (get only)   */
+    float *R;           /* N x d repulsion partials of the last step (get only)    */
+    float *Zh;          /* N per-point normaliser partials of the last step (get)  */
+    float *E;           /* scalar: smoothed fraction E                             */
+    uint32_t *t;        /* scalar: iteration counter                               */
+} fsne_state_view;
+
+typedef struct fsne_stats {
+    int64_t N;          /* live points                                             */
+    uint32_t t;         /* iterations done                                         */
+    float E;            /* smoothed fraction of points that gained HD neighbours   */
+    int32_t next_fire;  /* whether iteration t refines the HD lists                */
+    int32_t last_fired; /* whether iteration t-1 refined them                      */
+    int32_t n_new;      /* points whose HD list changed in the last refinement     */
+    float Z;            /* normaliser of the last iteration                        */
+    int32_t nonfinite;  /* 1 if a NaN/inf reached the embedding                    */
+} fsne_stats;
+
+/* Fill *hp with the defaults: alpha 1, perplexity 10, lr 100, momentum 0.5,
+ * attr 1, rep 1, n_neg 16, hd_mode 0, dist_mode 0, e_smooth 0.1, p_min 0.05,
+ * rerank_margin 2^-6.  Returns FSNE_EINVAL if hp is NULL. */
+fsne_status fsne_default_hparams(fsne_hparams *hp);
+
+/* Create a context and its initial state (Sec. 3: optimisation starts right
+ * after allocation, with random neighbour lists).
+ *   X         N x D points, FP32 or BF16 (bit patterns) per xdtype; host memory
+ *             unless x_on_device = 1, in which case it is device memory that
+ *             must outlive the context (it is read, never written).
+ *   Y0        N x d initial embedding, host memory (NULL: all zeros).
+ *   d, K_hd, K_ld  embedding dimension and list lengths:
+ *             1 <= d <= 64, 2 <= K_hd <= 64, 1 <= K_ld <= 64, K_hd, K_ld < N.
+ *   seed      key of the Philox4x32-10 draws (candidates, negatives, coin).
+ *   hp        hyperparameters, or NULL for the defaults.
+ *   stream    hipStream_t to run on, or NULL for a stream the context owns.
+ *   capacity  rows reserved for fsne_insert_points (>= N).
+ * Initial lists: for point i, the first K distinct other points from draws
+ * (i, 0, stream, s), s = 0, 1, ...; HD lists sorted; all points calibrated to
+ * the perplexity; V = 0; E = 1; t = 0.
+ * Errors: FSNE_EINVAL (bad sizes or hyperparameters), FSNE_ENOMEM, FSNE_EHIP. */
+fsne_status fsne_init(fsne_ctx **out, const void *X, int64_t N, int32_t D, int32_t xdtype,
+                      const float *Y0, int32_t d, int32_t K_hd, int32_t K_ld, uint64_t seed,
+                      const fsne_hparams *hp, int32_t x_on_device, void *stream,
+                      int64_t capacity);
+
+/* Run n_iters iterations (Sec. 3), asynchronously on the context stream.
+ * Per iteration: [if the coin fires] HD refinement + recalibration of changed
+ * points + affinities; LD refinement + gradient partials; Z; momentum update;
+ * E and the next coin.  Errors: FSNE_EINVAL (n_iters < 0), FSNE_EHIP. */
+fsne_status fsne_step(fsne_ctx *ctx, int32_t n_iters);
+
+/* Replace the hyperparameters.  A perplexity change recalibrates every point
+ * and recomputes the affinities before the next step (Sec. 3: HD-side
+ * hyperparameters change on the fly).  Errors: FSNE_EINVAL. */
+fsne_status fsne_set_hyperparams(fsne_ctx *ctx, const fsne_hparams *hp);
+fsne_status fsne_get_hyperparams(const fsne_ctx *ctx, fsne_hparams *hp);
+
+/* Copy the N x d embedding to out (host memory, or device memory if
+ * out_on_device = 1).  Synchronises.  Errors: FSNE_EINVAL, FSNE_EHIP. */
+fsne_status fsne_get_Y(fsne_ctx *ctx, float *out, int32_t out_on_device);
+
+/* Copy the current lists: which = 0 HD (idx N x K_hd, dist2 N x K_hd may be
+ * NULL), which = 1 LD (idx N x K_ld; dist2 must be NULL).  Host memory.
+ * Synchronises.  Errors: FSNE_EINVAL, FSNE_EHIP. */
+fsne_status fsne_get_knn(fsne_ctx *ctx, int32_t which, int32_t *idx, float *dist2);
+
+/* Copy the state to / from host memory (checkpoint, resume, checks).  set
+ * reads every non-NULL field except A, R, Zh and recomputes the coin of the
+ * next iteration from E and t.  Synchronises.  Errors: FSNE_EINVAL, FSNE_EHIP. */
+fsne_status fsne_get_state(fsne_ctx *ctx, const fsne_state_view *s);
+fsne_status fsne_set_state(fsne_ctx *ctx, const fsne_state_view *s);
+
+/* Statistics of the last iteration.  Synchronises.  Returns FSNE_ENONFINITE
+ * (with *st filled) if the embedding holds a NaN or infinity. */
+fsne_status fsne_get_stats(fsne_ctx *ctx, fsne_stats *st);
+
+/* Wait for the context's queued work.  Errors: FSNE_EHIP. */
+fsne_status fsne_sync(fsne_ctx *ctx);
+
+/* Dynamic data (Sec. 3 on online use; Sec. 5).  Insert n new points (host
+ * X rows of the context's dtype, host Yinit n x d or NULL for zeros): they
+ * take indices N..N+n-1, get random lists, calibration and V = 0; every
+ * point's affinities are recomputed for the new N.  Errors: FSNE_ENOMEM
+ * (beyond capacity), FSNE_EINVAL, FSNE_EHIP. */
+fsne_status fsne_insert_points(fsne_ctx *ctx, const void *Xnew, int64_t n, const float *Yinit);
+
+/* Replace the HD coordinates of n existing points (host ids, host rows).
+ * Their velocity is reset; Yinit (host n x d, or NULL to keep y) replaces
+ * their embedding.  Every HD list entry that pairs with a moved point gets
+ * its new distance; affected lists are re-sorted, flagged and recalibrated;
+ * affinities are recomputed.  Errors: FSNE_EINVAL, FSNE_EHIP. */
+fsne_status fsne_drift_points(fsne_ctx *ctx, const int64_t *ids, const void *Xnew, int64_t n,
+                              const float *Yinit);
+
+/* Scale the embedding down by factor (> 0): Y <- Y / factor, V <- V / factor
+ * (Sec. 3, the "implosion" control).  Errors: FSNE_EINVAL, FSNE_EHIP. */
+fsne_status fsne_implode(fsne_ctx *ctx, float factor);
+
+/* Destroy the context and free its device memory (NULL is accepted). */
+void fsne_destroy(fsne_ctx *ctx);
+
+/* Message of the last failing call on ctx (never NULL). */
+const char *fsne_last_error(const fsne_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

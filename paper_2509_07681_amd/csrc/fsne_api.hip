@@ -1,0 +1,606 @@
+// C ABI of libfsne.so (declared in include/fsne.h): context, device state,
+// argument checks, and the launch sequence of one FUnc-SNE iteration.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fsne.h"
+#include "fsne_kernels.h"
+
+using fsne::Hyper;
+using fsne::Scalars;
+using fsne::StepArgs;
+
+struct fsne_ctx {
+  int64_t N = 0, cap = 0;
+  int32_t D = 0, d = 0, DP = 0, Kh = 0, Kl = 0, xdtype = 0;
+  uint64_t seed = 0;
+  fsne_hparams hp{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* X = nullptr;
+  bool own_X = false;
+  float* xnorm = nullptr;
+  float *Y = nullptr, *V = nullptr, *A = nullptr, *R = nullptr, *Zh = nullptr, *P = nullptr;
+  float* zpart = nullptr;
+  int32_t* fpart = nullptr;
+  int32_t* hd_idx[2] = {nullptr, nullptr};
+  float* hd_d2[2] = {nullptr, nullptr};
+  int32_t* ld_idx[2] = {nullptr, nullptr};
+  float4* rec = nullptr;
+  uint8_t* flags = nullptr;
+  uint8_t* moved = nullptr;
+  Scalars* sc = nullptr;
+  std::string err;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+const char* kNoCtx = "null context";
+
+fsne_status fail(fsne_ctx* c, fsne_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+fsne_status hip_fail(fsne_ctx* c, hipError_t e, const char* where) {
+  return fail(c, FSNE_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr)                                  \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+int pad_dim(int d) {
+  int p = 2;
+  while (p < d) p <<= 1;
+  return p;
+}
+
+Hyper make_hyper(const fsne_ctx* c) {
+  Hyper h{};
+  const fsne_hparams& p = c->hp;
+  h.alpha = p.alpha;
+  h.inv_alpha = 1.0f / p.alpha;
+  h.lr = p.lr;
+  h.momentum = p.momentum;
+  h.attr = p.attr;
+  h.rep = p.rep;
+  h.perplexity = p.perplexity;
+  h.ln_perp = logf(p.perplexity);
+  h.e_smooth = p.e_smooth;
+  h.p_min = p.p_min;
+  h.margin = p.rerank_margin;
+  h.n_neg = p.n_neg;
+  h.hd_mode = p.hd_mode;
+  h.dist_mode = p.dist_mode;
+  h.key0 = (uint32_t)c->seed;
+  h.key1 = (uint32_t)(c->seed >> 32);
+  return h;
+}
+
+StepArgs make_args(const fsne_ctx* c) {
+  StepArgs a{};
+  a.X = c->X;
+  a.xnorm = c->xnorm;
+  a.xdtype = c->xdtype;
+  a.xvec_ok = (((uintptr_t)c->X) & 15u) == 0;
+  a.N = (int32_t)c->N;
+  a.D = c->D;
+  a.d = c->d;
+  a.DP = c->DP;
+  a.Kh = c->Kh;
+  a.Kl = c->Kl;
+  a.h = make_hyper(c);
+  a.sc = c->sc;
+  for (int b = 0; b < 2; ++b) {
+    a.hd_idx[b] = c->hd_idx[b];
+    a.hd_d2[b] = c->hd_d2[b];
+    a.ld_idx[b] = c->ld_idx[b];
+  }
+  a.rec = c->rec;
+  a.P = c->P;
+  a.flags = c->flags;
+  a.Y = c->Y;
+  a.V = c->V;
+  a.A = c->A;
+  a.R = c->R;
+  a.Zh = c->Zh;
+  a.zpart = c->zpart;
+  a.fpart = c->fpart;
+  a.neg_scale = c->hp.n_neg > 0 ? (float)(c->N - 1) / (float)c->hp.n_neg : 0.0f;
+  return a;
+}
+
+fsne_status check_hparams(fsne_ctx* c, const fsne_hparams* hp, int32_t Kh, int32_t xdtype) {
+  if (!hp) return fail(c, FSNE_EINVAL, "hparams is NULL");
+  if (!(hp->alpha > 0.0f) || !std::isfinite(hp->alpha))
+    return fail(c, FSNE_EINVAL, "alpha must be > 0");
+  if (!(hp->perplexity > 1.0f) || !(hp->perplexity < (float)Kh))
+    return fail(c, FSNE_EINVAL, "perplexity must satisfy 1 < perplexity < K_hd");
+  if (!(hp->lr >= 0.0f) || !std::isfinite(hp->lr)) return fail(c, FSNE_EINVAL, "lr must be >= 0");
+  if (!(hp->momentum >= 0.0f && hp->momentum < 1.0f))
+    return fail(c, FSNE_EINVAL, "momentum must be in [0, 1)");
+  if (!(hp->attr >= 0.0f) || !(hp->rep >= 0.0f) || !std::isfinite(hp->attr) ||
+      !std::isfinite(hp->rep))
+    return fail(c, FSNE_EINVAL, "attr and rep must be >= 0");
+  if (hp->n_neg < 0 || hp->n_neg > 64) return fail(c, FSNE_EINVAL, "n_neg must be in 0..64");
+  if (hp->hd_mode < 0 || hp->hd_mode > 2) return fail(c, FSNE_EINVAL, "hd_mode must be 0, 1, 2");
+  if (hp->dist_mode < 0 || hp->dist_mode > 1)
+    return fail(c, FSNE_EINVAL, "dist_mode must be 0 or 1");
+  if (hp->dist_mode == 1 && xdtype != FSNE_BF16)
+    return fail(c, FSNE_EINVAL, "dist_mode 1 needs BF16 X");
+  if (!(hp->e_smooth > 0.0f && hp->e_smooth <= 1.0f))
+    return fail(c, FSNE_EINVAL, "e_smooth must be in (0, 1]");
+  if (!(hp->p_min >= 0.0f && hp->p_min <= 1.0f))
+    return fail(c, FSNE_EINVAL, "p_min must be in [0, 1]");
+  if (!(hp->rerank_margin >= 0.0f) || !std::isfinite(hp->rerank_margin))
+    return fail(c, FSNE_EINVAL, "rerank_margin must be >= 0");
+  return FSNE_OK;
+}
+
+template <typename T>
+fsne_status dalloc(fsne_ctx* c, T** p, size_t n) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, n * sizeof(T) > 0 ? n * sizeof(T) : 1);
+  if (e != hipSuccess) return fail(c, FSNE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->owned.push_back(q);
+  *p = static_cast<T*>(q);
+  return FSNE_OK;
+}
+
+#define TRY(expr)                    \
+  do {                               \
+    fsne_status s_ = (expr);         \
+    if (s_ != FSNE_OK) return s_;    \
+  } while (0)
+
+size_t xbytes(const fsne_ctx* c) { return c->xdtype == FSNE_F32 ? 4 : 2; }
+
+// Host Y rows (n x d) -> device rows (n x DP, padding zero) at row offset r0.
+fsne_status put_Y(fsne_ctx* c, float* dst, const float* src, int64_t r0, int64_t n) {
+  HIPCHK(c, hipMemsetAsync(dst + r0 * c->DP, 0, sizeof(float) * n * c->DP, c->stream));
+  if (src && n > 0)
+    HIPCHK(c, hipMemcpy2DAsync(dst + r0 * c->DP, sizeof(float) * c->DP, src, sizeof(float) * c->d,
+                               sizeof(float) * c->d, n, hipMemcpyHostToDevice, c->stream));
+  return FSNE_OK;
+}
+
+fsne_status get_rows(fsne_ctx* c, float* dst, const float* src, bool dst_dev) {
+  HIPCHK(c, hipMemcpy2DAsync(dst, sizeof(float) * c->d, src, sizeof(float) * c->DP,
+                             sizeof(float) * c->d, c->N,
+                             dst_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+  return FSNE_OK;
+}
+
+fsne_status read_scalars(fsne_ctx* c, Scalars* s) {
+  HIPCHK(c, hipMemcpyAsync(s, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FSNE_OK;
+}
+
+fsne_status write_scalars(fsne_ctx* c, const Scalars& s) {
+  HIPCHK(c, hipMemcpyAsync(c->sc, &s, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FSNE_OK;
+}
+
+fsne_status refresh_affinities(fsne_ctx* c, bool recalibrate) {
+  StepArgs a = make_args(c);
+  if (recalibrate) HIPCHK(c, fsne::launch_calibrate_all(a, c->stream));
+  HIPCHK(c, fsne::launch_psym(a, 1, c->stream));
+  HIPCHK(c, fsne::launch_set_fire(c->sc, a.h, c->stream));
+  return FSNE_OK;
+}
+
+fsne_status alloc_state(fsne_ctx* c) {
+  const size_t cap = (size_t)c->cap;
+  TRY(dalloc(c, &c->Y, cap * c->DP));
+  TRY(dalloc(c, &c->V, cap * c->DP));
+  TRY(dalloc(c, &c->A, cap * c->DP));
+  TRY(dalloc(c, &c->R, cap * c->DP));
+  TRY(dalloc(c, &c->Zh, cap));
+  TRY(dalloc(c, &c->P, cap * c->Kh));
+  TRY(dalloc(c, &c->zpart, (size_t)fsne::kReduceBlocks));
+  TRY(dalloc(c, &c->fpart, (size_t)fsne::kReduceBlocks));
+  for (int b = 0; b < 2; ++b) {
+    TRY(dalloc(c, &c->hd_idx[b], cap * c->Kh));
+    TRY(dalloc(c, &c->hd_d2[b], cap * c->Kh));
+    TRY(dalloc(c, &c->ld_idx[b], cap * c->Kl));
+  }
+  TRY(dalloc(c, &c->rec, cap));
+  TRY(dalloc(c, &c->flags, cap));
+  TRY(dalloc(c, &c->moved, cap));
+  TRY(dalloc(c, &c->sc, 1));
+  HIPCHK(c, hipMemsetAsync(c->A, 0, sizeof(float) * cap * c->DP, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->R, 0, sizeof(float) * cap * c->DP, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->Zh, 0, sizeof(float) * cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->flags, 0, cap, c->stream));
+  return FSNE_OK;
+}
+
+fsne_status do_init(fsne_ctx* c, const void* X, int32_t x_on_device, const float* Y0) {
+  TRY(alloc_state(c));
+  const size_t xb = xbytes(c);
+  if (x_on_device && c->cap == c->N) {
+    c->X = const_cast<void*>(X);
+  } else {
+    void* q = nullptr;
+    TRY(dalloc(c, reinterpret_cast<uint8_t**>(&q), (size_t)c->cap * c->D * xb));
+    c->X = q;
+    c->own_X = true;
+    HIPCHK(c, hipMemcpyAsync(c->X, X, (size_t)c->N * c->D * xb,
+                             x_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             c->stream));
+  }
+  if (c->xdtype == FSNE_BF16) {
+    TRY(dalloc(c, &c->xnorm, (size_t)c->cap));
+  }
+  TRY(put_Y(c, c->Y, Y0, 0, c->N));
+  HIPCHK(c, hipMemsetAsync(c->V, 0, sizeof(float) * c->cap * c->DP, c->stream));
+  Scalars s{};
+  s.t = 0;
+  s.E = 1.0f;
+  s.hd_cur = 0;
+  TRY(write_scalars(c, s));
+  StepArgs a = make_args(c);
+  a.hd_buf_host = 0;
+  a.ld_buf_host = 0;
+  if (c->xdtype == FSNE_BF16) HIPCHK(c, fsne::launch_xnorm(a, c->xnorm, 0, (int32_t)c->N, c->stream));
+  HIPCHK(c, fsne::launch_init_lists(a, 0, (int32_t)c->N, c->stream));
+  TRY(refresh_affinities(c, false));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FSNE_OK;
+}
+
+void release(fsne_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->owned) (void)hipFree(p);
+  c->owned.clear();
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  c->stream = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+fsne_status fsne_default_hparams(fsne_hparams* hp) {
+  if (!hp) return FSNE_EINVAL;
+  hp->alpha = 1.0f;
+  hp->perplexity = 10.0f;
+  hp->lr = 100.0f;
+  hp->momentum = 0.5f;
+  hp->attr = 1.0f;
+  hp->rep = 1.0f;
+  hp->n_neg = 16;
+  hp->hd_mode = 0;
+  hp->dist_mode = 0;
+  hp->e_smooth = 0.1f;
+  hp->p_min = 0.05f;
+  hp->rerank_margin = 1.0f / 64.0f;
+  return FSNE_OK;
+}
+
+fsne_status fsne_init(fsne_ctx** out, const void* X, int64_t N, int32_t D, int32_t xdtype,
+                      const float* Y0, int32_t d, int32_t K_hd, int32_t K_ld, uint64_t seed,
+                      const fsne_hparams* hp, int32_t x_on_device, void* stream,
+                      int64_t capacity) {
+  if (!out) return FSNE_EINVAL;
+  *out = nullptr;
+  if (!X || N < 3 || N > 2147483647LL || D < 1 || d < 1 || d > 64 || K_hd < 2 || K_hd > 64 ||
+      K_ld < 1 || K_ld > 64 || K_hd >= N || K_ld >= N || (xdtype != FSNE_F32 && xdtype != FSNE_BF16))
+    return FSNE_EINVAL;
+  if (capacity < N || capacity > 2147483647LL) return FSNE_EINVAL;
+  fsne_ctx* c = new (std::nothrow) fsne_ctx();
+  if (!c) return FSNE_ENOMEM;
+  fsne_hparams h;
+  if (hp)
+    h = *hp;
+  else
+    fsne_default_hparams(&h);
+  fsne_status st = check_hparams(c, &h, K_hd, xdtype);
+  if (st != FSNE_OK) {
+    delete c;
+    return st;
+  }
+  c->N = N;
+  c->cap = capacity;
+  c->D = D;
+  c->d = d;
+  c->DP = pad_dim(d);
+  c->Kh = K_hd;
+  c->Kl = K_ld;
+  c->xdtype = xdtype;
+  c->seed = seed;
+  c->hp = h;
+  if (stream) {
+    c->stream = static_cast<hipStream_t>(stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return FSNE_EHIP;
+    }
+    c->own_stream = true;
+  }
+  st = do_init(c, X, x_on_device, Y0);
+  if (st != FSNE_OK) {
+    release(c);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return FSNE_OK;
+}
+
+fsne_status fsne_step(fsne_ctx* c, int32_t n_iters) {
+  if (!c) return FSNE_EINVAL;
+  if (n_iters < 0) return fail(c, FSNE_EINVAL, "n_iters < 0");
+  const StepArgs a = make_args(c);
+  for (int32_t it = 0; it < n_iters; ++it) {
+    HIPCHK(c, fsne::launch_hd_refine(a, c->stream));
+    HIPCHK(c, fsne::launch_psym(a, 0, c->stream));
+    HIPCHK(c, fsne::launch_ld_grad(a, c->stream));
+    HIPCHK(c, fsne::launch_reduce_update(a, c->stream));
+  }
+  return FSNE_OK;
+}
+
+fsne_status fsne_set_hyperparams(fsne_ctx* c, const fsne_hparams* hp) {
+  if (!c) return FSNE_EINVAL;
+  TRY(check_hparams(c, hp, c->Kh, c->xdtype));
+  const bool perp_changed = hp->perplexity != c->hp.perplexity;
+  c->hp = *hp;
+  if (perp_changed) {
+    TRY(refresh_affinities(c, true));
+  } else {
+    HIPCHK(c, fsne::launch_set_fire(c->sc, make_hyper(c), c->stream));
+  }
+  return FSNE_OK;
+}
+
+fsne_status fsne_get_hyperparams(const fsne_ctx* c, fsne_hparams* hp) {
+  if (!c || !hp) return FSNE_EINVAL;
+  *hp = c->hp;
+  return FSNE_OK;
+}
+
+fsne_status fsne_sync(fsne_ctx* c) {
+  if (!c) return FSNE_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FSNE_OK;
+}
+
+fsne_status fsne_get_Y(fsne_ctx* c, float* out, int32_t out_on_device) {
+  if (!c || !out) return c ? fail(c, FSNE_EINVAL, "out is NULL") : FSNE_EINVAL;
+  TRY(get_rows(c, out, c->Y, out_on_device != 0));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FSNE_OK;
+}
+
+fsne_status fsne_get_knn(fsne_ctx* c, int32_t which, int32_t* idx, float* dist2) {
+  if (!c) return FSNE_EINVAL;
+  if (!idx || (which != 0 && which != 1) || (which == 1 && dist2))
+    return fail(c, FSNE_EINVAL, "bad arguments to fsne_get_knn");
+  Scalars s;
+  TRY(read_scalars(c, &s));
+  if (which == 0) {
+    HIPCHK(c, hipMemcpyAsync(idx, c->hd_idx[s.hd_cur], sizeof(int32_t) * c->N * c->Kh,
+                             hipMemcpyDeviceToHost, c->stream));
+    if (dist2)
+      HIPCHK(c, hipMemcpyAsync(dist2, c->hd_d2[s.hd_cur], sizeof(float) * c->N * c->Kh,
+                               hipMemcpyDeviceToHost, c->stream));
+  } else {
+    HIPCHK(c, hipMemcpyAsync(idx, c->ld_idx[s.t & 1], sizeof(int32_t) * c->N * c->Kl,
+                             hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FSNE_OK;
+}
+
+fsne_status fsne_get_state(fsne_ctx* c, const fsne_state_view* v) {
+  if (!c || !v) return c ? fail(c, FSNE_EINVAL, "view is NULL") : FSNE_EINVAL;
+  Scalars s;
+  TRY(read_scalars(c, &s));
+  const int64_t N = c->N;
+  const hipMemcpyKind k = hipMemcpyDeviceToHost;
+  if (v->Y) TRY(get_rows(c, v->Y, c->Y, false));
+  if (v->V) TRY(get_rows(c, v->V, c->V, false));
+  if (v->A) TRY(get_rows(c, v->A, c->A, false));
+  if (v->R) TRY(get_rows(c, v->R, c->R, false));
+  if (v->Zh) HIPCHK(c, hipMemcpyAsync(v->Zh, c->Zh, sizeof(float) * N, k, c->stream));
+  if (v->hd_idx)
+    HIPCHK(c, hipMemcpyAsync(v->hd_idx, c->hd_idx[s.hd_cur], sizeof(int32_t) * N * c->Kh, k,
+                             c->stream));
+  if (v->hd_d2)
+    HIPCHK(c, hipMemcpyAsync(v->hd_d2, c->hd_d2[s.hd_cur], sizeof(float) * N * c->Kh, k,
+                             c->stream));
+  if (v->ld_idx)
+    HIPCHK(c, hipMemcpyAsync(v->ld_idx, c->ld_idx[s.t & 1], sizeof(int32_t) * N * c->Kl, k,
+                             c->stream));
+  if (v->rec) HIPCHK(c, hipMemcpyAsync(v->rec, c->rec, sizeof(float4) * N, k, c->stream));
+  if (v->P) HIPCHK(c, hipMemcpyAsync(v->P, c->P, sizeof(float) * N * c->Kh, k, c->stream));
+  if (v->flags) HIPCHK(c, hipMemcpyAsync(v->flags, c->flags, (size_t)N, k, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (v->E) *v->E = s.E;
+  if (v->t) *v->t = s.t;
+  return FSNE_OK;
+}
+
+fsne_status fsne_set_state(fsne_ctx* c, const fsne_state_view* v) {
+  if (!c || !v) return c ? fail(c, FSNE_EINVAL, "view is NULL") : FSNE_EINVAL;
+  Scalars s;
+  TRY(read_scalars(c, &s));
+  const int64_t N = c->N;
+  const hipMemcpyKind k = hipMemcpyHostToDevice;
+  const uint32_t t_new = v->t ? *v->t : s.t;
+  if (((t_new ^ s.t) & 1u) && !v->ld_idx)
+    HIPCHK(c, hipMemcpyAsync(c->ld_idx[t_new & 1], c->ld_idx[s.t & 1],
+                             sizeof(int32_t) * N * c->Kl, hipMemcpyDeviceToDevice, c->stream));
+  if (v->Y) TRY(put_Y(c, c->Y, v->Y, 0, N));
+  if (v->V) TRY(put_Y(c, c->V, v->V, 0, N));
+  if (v->hd_idx)
+    HIPCHK(c, hipMemcpyAsync(c->hd_idx[s.hd_cur], v->hd_idx, sizeof(int32_t) * N * c->Kh, k,
+                             c->stream));
+  if (v->hd_d2)
+    HIPCHK(c, hipMemcpyAsync(c->hd_d2[s.hd_cur], v->hd_d2, sizeof(float) * N * c->Kh, k,
+                             c->stream));
+  if (v->ld_idx)
+    HIPCHK(c, hipMemcpyAsync(c->ld_idx[t_new & 1], v->ld_idx, sizeof(int32_t) * N * c->Kl, k,
+                             c->stream));
+  if (v->rec) HIPCHK(c, hipMemcpyAsync(c->rec, v->rec, sizeof(float4) * N, k, c->stream));
+  if (v->P) HIPCHK(c, hipMemcpyAsync(c->P, v->P, sizeof(float) * N * c->Kh, k, c->stream));
+  if (v->flags) HIPCHK(c, hipMemcpyAsync(c->flags, v->flags, (size_t)N, k, c->stream));
+  if (v->E) s.E = *v->E;
+  s.t = t_new;
+  s.nonfinite = 0;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  TRY(write_scalars(c, s));
+  HIPCHK(c, fsne::launch_set_fire(c->sc, make_hyper(c), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FSNE_OK;
+}
+
+fsne_status fsne_get_stats(fsne_ctx* c, fsne_stats* st) {
+  if (!c || !st) return c ? fail(c, FSNE_EINVAL, "stats is NULL") : FSNE_EINVAL;
+  Scalars s;
+  TRY(read_scalars(c, &s));
+  st->N = c->N;
+  st->t = s.t;
+  st->E = s.E;
+  st->next_fire = s.fire;
+  st->last_fired = s.last_fired;
+  st->n_new = s.n_new;
+  st->Z = s.Z;
+  st->nonfinite = s.nonfinite;
+  if (s.nonfinite) return fail(c, FSNE_ENONFINITE, "embedding holds a NaN or infinity");
+  return FSNE_OK;
+}
+
+fsne_status fsne_insert_points(fsne_ctx* c, const void* Xnew, int64_t n, const float* Yinit) {
+  if (!c) return FSNE_EINVAL;
+  if (!Xnew || n < 0) return fail(c, FSNE_EINVAL, "bad arguments to fsne_insert_points");
+  if (n == 0) return FSNE_OK;
+  if (c->N + n > c->cap) return fail(c, FSNE_ENOMEM, "insert beyond capacity");
+  if (!c->own_X) return fail(c, FSNE_ESTATE, "X is borrowed; create the context with capacity");
+  Scalars s;
+  TRY(read_scalars(c, &s));
+  const int64_t N0 = c->N;
+  const size_t xb = xbytes(c);
+  HIPCHK(c, hipMemcpyAsync(static_cast<uint8_t*>(c->X) + (size_t)N0 * c->D * xb, Xnew,
+                           (size_t)n * c->D * xb, hipMemcpyHostToDevice, c->stream));
+  TRY(put_Y(c, c->Y, Yinit, N0, n));
+  HIPCHK(c, hipMemsetAsync(c->V + N0 * c->DP, 0, sizeof(float) * n * c->DP, c->stream));
+  c->N = N0 + n;
+  StepArgs a = make_args(c);
+  a.hd_buf_host = s.hd_cur;
+  a.ld_buf_host = (int32_t)(s.t & 1u);
+  if (c->xdtype == FSNE_BF16)
+    HIPCHK(c, fsne::launch_xnorm(a, c->xnorm, (int32_t)N0, (int32_t)n, c->stream));
+  HIPCHK(c, fsne::launch_init_lists(a, (int32_t)N0, (int32_t)n, c->stream));
+  TRY(refresh_affinities(c, false));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FSNE_OK;
+}
+
+fsne_status fsne_drift_points(fsne_ctx* c, const int64_t* ids, const void* Xnew, int64_t n,
+                              const float* Yinit) {
+  if (!c) return FSNE_EINVAL;
+  if (!ids || !Xnew || n < 0) return fail(c, FSNE_EINVAL, "bad arguments to fsne_drift_points");
+  if (n == 0) return FSNE_OK;
+  if (!c->own_X) return fail(c, FSNE_ESTATE, "X is borrowed; create the context with capacity");
+  std::vector<uint8_t> seen((size_t)c->N, 0);
+  std::vector<int32_t> ids32((size_t)n);
+  for (int64_t k = 0; k < n; ++k) {
+    if (ids[k] < 0 || ids[k] >= c->N) return fail(c, FSNE_EINVAL, "drift id out of range");
+    if (seen[(size_t)ids[k]]) return fail(c, FSNE_EINVAL, "duplicate drift id");
+    seen[(size_t)ids[k]] = 1;
+    ids32[(size_t)k] = (int32_t)ids[k];
+  }
+  const size_t xrow = (size_t)c->D * xbytes(c);
+  int32_t* dids = nullptr;
+  uint8_t* dx = nullptr;
+  float* dy = nullptr;
+  fsne_status st = FSNE_OK;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(c->stream);
+    if (dids) (void)hipFree(dids);
+    if (dx) (void)hipFree(dx);
+    if (dy) (void)hipFree(dy);
+  };
+  if (hipMalloc(&dids, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc(&dx, xrow * n) != hipSuccess ||
+      (Yinit && hipMalloc(&dy, sizeof(float) * n * c->DP) != hipSuccess)) {
+    cleanup();
+    return fail(c, FSNE_ENOMEM, "drift staging allocation failed");
+  }
+  do {
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dids, ids32.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
+                            c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(dx, Xnew, xrow * n, hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+        (e = fsne::launch_scatter_rows(c->X, dx, dids, (int32_t)n, (int32_t)xrow, c->stream)) !=
+            hipSuccess) {
+      st = hip_fail(c, e, "drift upload");
+      break;
+    }
+    if (Yinit) {
+      if ((st = put_Y(c, dy, Yinit, 0, n)) != FSNE_OK) break;
+      if ((e = fsne::launch_scatter_rows(c->Y, dy, dids, (int32_t)n,
+                                         (int32_t)(sizeof(float) * c->DP), c->stream)) !=
+          hipSuccess) {
+        st = hip_fail(c, e, "drift Y");
+        break;
+      }
+    }
+    if ((e = hipMemsetAsync(c->moved, 0, (size_t)c->N, c->stream)) != hipSuccess ||
+        (e = fsne::launch_mark_moved(c->moved, c->V, c->DP, dids, (int32_t)n, c->stream)) !=
+            hipSuccess) {
+      st = hip_fail(c, e, "drift marks");
+      break;
+    }
+    StepArgs a = make_args(c);
+    if (c->xdtype == FSNE_BF16 &&
+        (e = fsne::launch_xnorm(a, c->xnorm, 0, (int32_t)c->N, c->stream)) != hipSuccess) {
+      st = hip_fail(c, e, "drift norms");
+      break;
+    }
+    if ((e = fsne::launch_drift_rows(a, c->moved, c->stream)) != hipSuccess) {
+      st = hip_fail(c, e, "drift rows");
+      break;
+    }
+    st = refresh_affinities(c, false);
+  } while (false);
+  cleanup();
+  return st;
+}
+
+fsne_status fsne_implode(fsne_ctx* c, float factor) {
+  if (!c) return FSNE_EINVAL;
+  if (!(factor > 0.0f) || !std::isfinite(factor)) return fail(c, FSNE_EINVAL, "factor must be > 0");
+  HIPCHK(c, fsne::launch_scale(c->Y, c->V, c->N * c->DP, 1.0f / factor, c->stream));
+  return FSNE_OK;
+}
+
+void fsne_destroy(fsne_ctx* c) {
+  if (!c) return;
+  release(c);
+  delete c;
+}
+
+const char* fsne_last_error(const fsne_ctx* c) {
+  if (!c) return kNoCtx;
+  return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Internal interface between the C-ABI host code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fsne_device.h"
+
+namespace fsne {
+
+// Everything a step kernel needs, passed by value as the kernel argument.
+struct StepArgs {
+  const void* X;            // N x D, float or bfloat16 bits (xdtype 0 / 1)
+  const float* xnorm;       // N squared norms of the BF16 rows (BF16 screen only)
+  int32_t xdtype, xvec_ok;  // xvec_ok: X base is 16-byte aligned
+  int32_t N, D, d, DP, Kh, Kl;
+  Hyper h;
+  Scalars* sc;
+  int32_t* hd_idx[2];
+  float* hd_d2[2];
+  int32_t* ld_idx[2];
+  float4* rec;              // per point {beta, m, r, invS}
+  float* P;                 // N x Kh
+  uint8_t* flags;           // N
+  float* Y;                 // N x DP
+  float* V;                 // N x DP
+  float* A;                 // N x DP
+  float* R;                 // N x DP
+  float* Zh;                // N
+  float* zpart;             // kReduceBlocks
+  int32_t* fpart;           // kReduceBlocks
+  float neg_scale;          // (N - 1) / n_neg
+  int32_t hd_buf_host;      // HD buffer written by init / insert
+  int32_t ld_buf_host;      // LD buffer written by init / insert
+};
+
+hipError_t launch_init_lists(const StepArgs& a, int32_t i0, int32_t n, hipStream_t s);
+hipError_t launch_hd_refine(const StepArgs& a, hipStream_t s);
+hipError_t launch_hd_refine_bf16(const StepArgs& a, hipStream_t s);
+hipError_t launch_psym(const StepArgs& a, int standalone, hipStream_t s);
+hipError_t launch_ld_grad(const StepArgs& a, hipStream_t s);
+hipError_t launch_reduce_update(const StepArgs& a, hipStream_t s);
+hipError_t launch_set_fire(Scalars* sc, const Hyper& h, hipStream_t s);
+hipError_t launch_scale(float* Y, float* V, int64_t n, float inv, hipStream_t s);
+hipError_t launch_calibrate_all(const StepArgs& a, hipStream_t s);
+hipError_t launch_drift_rows(const StepArgs& a, const uint8_t* moved, hipStream_t s);
+hipError_t launch_xnorm(const StepArgs& a, float* xnorm, int32_t i0, int32_t n, hipStream_t s);
+hipError_t launch_scatter_rows(void* dst, const void* src, const int32_t* ids, int32_t n,
+                               int32_t row_bytes, hipStream_t s);
+hipError_t launch_mark_moved(uint8_t* moved, float* V, int32_t DP, const int32_t* ids, int32_t n,
+                             hipStream_t s);
+
+}  // namespace fsne

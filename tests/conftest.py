@@ -19,3 +19,16 @@ def oracle_lib():
 
     O.lib()
     return O
+
+
+@pytest.fixture(scope="session")
+def fsne_lib():
+    """The HIP library's binding (built in-tree first if it is missing)."""
+    from paper_2509_07681_amd import fsne as F
+
+    if not os.path.exists(F.LIB_PATH):
+        from paper_2509_07681_amd.build import build
+
+        build()
+    F.load_library()
+    return F

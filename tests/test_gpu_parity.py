@@ -1,0 +1,281 @@
+"""GPU (HIP) vs FP64 oracle, element by element, with the oracle's state
+injected before every compared iteration.
+
+Sizes: a few thousand points (hundreds of 4-wave blocks) with ragged tails;
+the full-size workloads are covered by test_gpu_fullsize.py.
+"""
+import numpy as np
+import pytest
+
+from inputs.generators import (blobs, f32_to_bf16_bits, image_like, manifolds, y_init,
+                               zipf_mixture)
+from tests.parity import compare_hd_rows, hd_tie_tol, rel_l2
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+
+def _f32(v):
+    return float(np.float32(v))
+
+
+def make_hp(O, F, N, **kw):
+    """The same hyperparameters for both sides (the oracle gets the FP32 values)."""
+    base = dict(alpha=1.0, perplexity=10.0, lr=N / 12.0, momentum=0.5, attr=12.0, rep=1.0,
+                n_neg=8, hd_mode=0, e_smooth=0.1, p_min=0.05)
+    base.update(kw)
+    hp_o = O.Hyper(**{k: (_f32(v) if isinstance(v, float) else v) for k, v in base.items()})
+    hp_g = F.fsne_default_hparams(**base)
+    return hp_o, hp_g
+
+
+WORKLOADS = {
+    "blobs_2000": lambda: (blobs(seed=1001)[0], dict(d=2, K_hd=32, K_ld=16, n_neg=8, alpha=1.0,
+                                                      perplexity=10.0)),
+    "blobs_1237": lambda: (blobs(seed=1001)[0][:1237],
+                           dict(d=2, K_hd=32, K_ld=16, n_neg=8, alpha=1.0, perplexity=10.0)),
+    "image_3001_a05": lambda: (image_like(n_per_class=301, seed=1002)[0][:3001],
+                               dict(d=2, K_hd=32, K_ld=32, n_neg=16, alpha=0.5, perplexity=10.0)),
+    "image_2003_a4": lambda: (image_like(n_per_class=201, seed=1002)[0][:2003],
+                              dict(d=2, K_hd=32, K_ld=32, n_neg=16, alpha=4.0, perplexity=10.0)),
+    "manifold_4003_f32": lambda: (manifolds(per_manifold=81, seed=1003)[0][:4003],
+                                  dict(d=16, K_hd=32, K_ld=32, n_neg=16, alpha=1.0,
+                                       perplexity=10.0)),
+    "manifold_4003_bf16": lambda: (f32_to_bf16_bits(manifolds(per_manifold=81, seed=1003)[0][:4003]),
+                                   dict(d=16, K_hd=32, K_ld=32, n_neg=16, alpha=1.0,
+                                        perplexity=10.0)),
+    "zipf_3000_bf16": lambda: (f32_to_bf16_bits(zipf_mixture(N=3000, n_clusters=30, seed=1005)[0]),
+                               dict(d=32, K_hd=64, K_ld=32, n_neg=32, alpha=0.5, perplexity=20.0)),
+    "odd_dims_777": lambda: (np.random.default_rng(3).normal(size=(777, 13)).astype(np.float32),
+                             dict(d=5, K_hd=10, K_ld=7, n_neg=3, alpha=1.7, perplexity=4.0)),
+}
+
+
+def _setup(O, F, name, seed=42, **hpkw):
+    X, c = WORKLOADS[name]()
+    N = X.shape[0]
+    hp_o, hp_g = make_hp(O, F, N, alpha=c["alpha"], perplexity=c["perplexity"],
+                         n_neg=c["n_neg"], **hpkw)
+    Y0 = y_init(N, c["d"])
+    S = O.OracleState(X, c["d"], c["K_hd"], c["K_ld"], seed, Y0).init(hp_o)
+    emb = F.Embedding(X, Y0, c["d"], c["K_hd"], c["K_ld"], seed=seed, hp=hp_g)
+    return X, c, S, emb, hp_o, hp_g
+
+
+def _check_hd(X, c, g, S, bf16):
+    tol = hd_tie_tol(X.shape[1], bf16)
+    N = S.N
+    differ, nbad, bad = compare_hd_rows(X, g["hd_idx"], S.live("hd_idx"), S.live("hd_d2"), tol)
+    assert nbad == 0, f"HD rows beyond the tie rule: {bad[:10]}"
+    assert differ <= max(3, N // 500), f"{differ} HD rows differ at ties"
+    same = np.all(g["hd_idx"] == S.live("hd_idx"), axis=1)
+    d_o = S.live("hd_d2")[same]
+    assert np.all(np.abs(g["hd_d2"][same] - d_o) <= 0.5 * tol * d_o + 1e-30)
+    return same
+
+
+def _clean_points(S, same_hd):
+    """Points whose HD row and whose HD neighbours' rows match the oracle exactly.
+
+    A tie-swapped row j changes the neighbour-of-neighbour candidates of every
+    point listing j, so those points are compared through properties only.
+    """
+    hd = S.live("hd_idx")
+    return same_hd & np.all(same_hd[hd], axis=1)
+
+
+def _clean_affinity(S, g_hd, same_hd):
+    """Points whose HD row matches and whose neighbours' rows hold the same sets
+    (the symmetrised affinity only asks whether i is listed by j)."""
+    o_hd = S.live("hd_idx")
+    same_set = np.array([set(a.tolist()) == set(b.tolist()) for a, b in zip(g_hd, o_hd)])
+    return same_hd & np.all(same_set[o_hd], axis=1)
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_init_matches_oracle(oracle_lib, fsne_lib, name):
+    O, F = oracle_lib, fsne_lib
+    X, c, S, emb, hp_o, hp_g = _setup(O, F, name)
+    g = emb.state()
+    np.testing.assert_array_equal(g["ld_idx"], S.live("ld_idx"))        # integer draws
+    same = _check_hd(X, c, g, S, X.dtype == np.uint16)
+    rec_o = np.stack([S.live("beta"), S.live("m"), S.live("r"), S.live("invS")], 1)
+    assert rel_l2(g["rec"][same, 0], rec_o[same, 0]) < 1e-4          # beta
+    assert rel_l2(g["rec"][same, 3], rec_o[same, 3]) < 1e-4          # invS
+    cleanP = _clean_affinity(S, g["hd_idx"], same)
+    assert cleanP.mean() > 0.97
+    assert rel_l2(g["P"][cleanP], S.live("P")[cleanP]) < 1e-4
+    assert g["E"] == 1.0 and g["t"] == 0
+    emb.close()
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+@pytest.mark.parametrize("hd_mode", [1, 0])
+def test_step_matches_oracle_with_injection(oracle_lib, fsne_lib, name, hd_mode):
+    O, F = oracle_lib, fsne_lib
+    X, c, S, emb, hp_o, hp_g = _setup(O, F, name, hd_mode=hd_mode)
+    bf16 = X.dtype == np.uint16
+    d = c["d"]
+    fired_seen = set()
+    for it in range(6):
+        emb.set_state(S.as_gpu_state())
+        Y0 = S.live("Y").copy()
+        Y0f = Y0.astype(np.float32).astype(np.float64)
+        out = S.step(hp_o, want_partials=True)
+        emb.step(1)
+        st = emb.stats()
+        assert st["last_fired"] == out["fired"]
+        fired_seen.add(out["fired"])
+        g = emb.state()
+        assert g["t"] == out["t"] and g["E"] == np.float32(out["E"])
+        same = _check_hd(X, c, g, S, bf16)
+        if out["fired"]:
+            assert np.array_equal(g["flags"][same], S.live("flags")[same])
+            assert abs(st["n_new"] - out["n_new"]) <= (~same).sum()
+        cleanP = _clean_affinity(S, g["hd_idx"], same)
+        assert cleanP.mean() > 0.97
+        assert rel_l2(g["P"][cleanP], S.live("P")[cleanP]) < 1e-4
+        clean = _clean_points(S, same)
+        assert clean.mean() > 0.8
+        ld_same = np.all(g["ld_idx"] == S.live("ld_idx"), axis=1)
+        assert np.all(ld_same[clean]), np.where(clean & ~ld_same)[0][:10]
+        ok = clean & ld_same
+        assert rel_l2(g["A"][ok], out["A"][ok]) < 1e-4
+        assert rel_l2(g["R"][ok], out["R"][ok]) < 1e-4
+        assert np.all(np.abs(g["Zh"][ok] - out["Zh"][ok]) <= 1e-5 * out["Zh"][ok])
+        assert abs(st["Z"] - out["Z"]) <= 1e-4 * out["Z"]
+        dY_g = g["Y"].astype(np.float64) - Y0f
+        dY_o = S.live("Y") - Y0
+        assert rel_l2(dY_g[ok], dY_o[ok]) < 1e-4
+        assert g["Y"].shape == (S.N, d)
+    if hd_mode == 1:
+        assert fired_seen == {1}
+    emb.close()
+
+
+def test_complete_lists_give_the_exact_gradient(oracle_lib, fsne_lib):
+    """K_hd = N - 1: the GPU step equals plain gradient descent on eq. (5)."""
+    O, F = oracle_lib, fsne_lib
+    rng = np.random.default_rng(9)
+    N, D, d = 48, 6, 3
+    X = rng.normal(size=(N, D)).astype(np.float32)
+    Y0 = rng.normal(scale=1.5, size=(N, d)).astype(np.float32)
+    for alpha in (0.5, 1.0, 2.5):
+        hp_o, hp_g = make_hp(O, F, N, alpha=alpha, perplexity=8.0, lr=2.0, momentum=0.0,
+                             attr=1.0, n_neg=4, hd_mode=1)
+        emb = F.Embedding(X, Y0, d, N - 1, N - 1, seed=5, hp=hp_g)
+        emb.step(1)
+        Y1 = emb.Y().astype(np.float64)
+        Pex, _ = O.exact_P(X, 8.0)
+        G = O.exact_grad(Pex, Y0.astype(np.float64), alpha)
+        assert rel_l2(Y1 - Y0, -hp_o.lr * G) < 1e-4
+        emb.close()
+
+
+def test_free_run_recall_and_validity(oracle_lib, fsne_lib):
+    """500 GPU iterations on the 2000-point blobs: lists valid, HD recall near 1."""
+    O, F = oracle_lib, fsne_lib
+    X, lab = blobs(seed=1001)
+    N = X.shape[0]
+    hp_o, hp_g = make_hp(O, F, N)
+    emb = F.Embedding(X, y_init(N, 2), 2, 32, 16, seed=42, hp=hp_g)
+    prev_kth = emb.knn(0)[1][:, -1].copy()
+    for it in range(25):
+        emb.step(20)
+        idx, d2 = emb.knn(0)
+        assert np.all(np.diff(d2, axis=1) >= 0)
+        assert np.all(d2[:, -1] <= prev_kth)
+        prev_kth = d2[:, -1].copy()
+        if it == 12:
+            emb.set_hyperparams(F.fsne_default_hparams(**{**hp_g.as_dict(), "attr": 1.0,
+                                                           "momentum": 0.8}))
+    idx, d2 = emb.knn(0)
+    ld, _ = emb.knn(1)
+    for i in range(0, N, 37):
+        assert len(set(idx[i])) == 32 and i not in set(idx[i])
+        assert len(set(ld[i])) == 16 and i not in set(ld[i])
+    ex, _ = O.knn_exact(X, np.arange(N), 32)
+    recall = np.mean([len(set(idx[i]) & set(ex[i])) for i in range(N)]) / 32
+    assert recall > 0.99, recall
+    agree = (lab[ld] == lab[:, None]).mean()
+    assert agree > 0.97, agree
+    st = emb.stats()
+    assert st["status"] == 0 and st["t"] == 500
+    emb.close()
+
+
+def test_determinism_and_resume(fsne_lib, oracle_lib):
+    O, F = oracle_lib, fsne_lib
+    X, _ = blobs(seed=1001)
+    N = X.shape[0]
+    _, hp_g = make_hp(O, F, N)
+    Y0 = y_init(N, 2)
+    a = F.Embedding(X, Y0, 2, 32, 16, seed=7, hp=hp_g)
+    b = F.Embedding(X, Y0, 2, 32, 16, seed=7, hp=hp_g)
+    a.step(60)
+    b.step(60)
+    assert np.array_equal(a.Y(), b.Y())
+    snap = a.state()
+    a.step(40)
+    c = F.Embedding(X, Y0, 2, 32, 16, seed=7, hp=hp_g)
+    c.set_state({k: v for k, v in snap.items() if k not in ("A", "R", "Zh")})
+    c.step(40)
+    assert np.array_equal(a.Y(), c.Y())
+    assert np.array_equal(a.knn(0)[0], c.knn(0)[0])
+    for e in (a, b, c):
+        e.close()
+
+
+def test_perplexity_change_and_implode(oracle_lib, fsne_lib):
+    O, F = oracle_lib, fsne_lib
+    X, c, S, emb, hp_o, hp_g = _setup(O, F, "blobs_1237")
+    emb.step(5)
+    st = emb.state()
+    hp2 = F.fsne_default_hparams(**{**hp_g.as_dict(), "perplexity": 5.0})
+    emb.set_hyperparams(hp2)
+    g = emb.state()
+    for i in range(0, st["hd_d2"].shape[0], 97):
+        (beta, m, r, invS), _ = O.calibrate(g["hd_d2"][i].astype(np.float64), 5.0)
+        assert abs(g["rec"][i, 0] - beta) <= 1e-4 * beta
+    Y = emb.Y()
+    emb.implode(10.0)
+    assert np.allclose(emb.Y(), Y / 10.0, rtol=1e-6)
+    emb.close()
+
+
+def test_insert_and_drift_match_oracle(oracle_lib, fsne_lib):
+    O, F = oracle_lib, fsne_lib
+    X, _ = blobs(seed=1001)
+    N0, n_ins = 1500, 300
+    hp_o, hp_g = make_hp(O, F, N0, hd_mode=1)
+    Y0 = y_init(N0, 2)
+    S = O.OracleState(X[:N0], 2, 32, 16, 42, Y0, capacity=N0 + n_ins).init(hp_o)
+    emb = F.Embedding(X[:N0], Y0, 2, 32, 16, seed=42, hp=hp_g, capacity=N0 + n_ins)
+    for _ in range(3):
+        S.step(hp_o)
+    emb.set_state(S.as_gpu_state())
+    Yn = np.random.default_rng(1).normal(size=(n_ins, 2)).astype(np.float32)
+    S.insert(hp_o, X[N0:N0 + n_ins], Yn)
+    emb.insert(X[N0:N0 + n_ins], Yn)
+    g = emb.state()
+    Xall = X[:N0 + n_ins]
+    np.testing.assert_array_equal(g["ld_idx"][N0:], S.live("ld_idx")[N0:])
+    same = _check_hd(Xall, None, g, S, False)
+    clean = _clean_affinity(S, g["hd_idx"], same)
+    assert rel_l2(g["P"][clean], S.live("P")[clean]) < 1e-4
+    # drift 40 points to new coordinates
+    rng = np.random.default_rng(2)
+    ids = rng.choice(N0 + n_ins, 40, replace=False)
+    Xn = (X[ids] + rng.normal(scale=0.5, size=X[ids].shape)).astype(np.float32)
+    Yd = rng.normal(size=(40, 2)).astype(np.float32)
+    emb.set_state(S.as_gpu_state())
+    S.drift(hp_o, ids, Xn, Yd)
+    emb.drift(ids, Xn, Yd)
+    g = emb.state()
+    Xall = S.X[:S.N]
+    same = _check_hd(Xall, None, g, S, False)
+    np.testing.assert_array_equal(g["flags"][same], S.live("flags")[same])
+    np.testing.assert_allclose(g["Y"][ids], Yd)
+    assert np.all(g["V"][ids] == 0)
+    clean = _clean_affinity(S, g["hd_idx"], same)
+    assert rel_l2(g["P"][clean], S.live("P")[clean]) < 1e-4
+    emb.close()
