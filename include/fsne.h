@@ -177,6 +177,27 @@ fsne_status fsne_drift_points(fsne_ctx *ctx, const int64_t *ids, const void *Xne
  * (Sec. 3, the "implosion" control).  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_implode(fsne_ctx *ctx, float factor);
 
+/* Kernels of one iteration, in launch order (indices of fsne_get_kernel_times). */
+enum {
+    FSNE_K_HD_REFINE = 0, /* HD candidates, distances, merge, recalibration     */
+    FSNE_K_AFFINITY = 1,  /* symmetrised affinities of eq. (1)                   */
+    FSNE_K_LD_GRAD = 2,   /* LD refinement and gradient partials (eqs. (4)-(6))  */
+    FSNE_K_REDUCE = 3,    /* fixed-order partial sums of Z and N_new             */
+    FSNE_K_UPDATE = 4,    /* momentum update and next-iteration scalars          */
+    FSNE_NKERNELS = 5
+};
+
+/* Measurement: with enable = 1, fsne_step records a HIP event pair on the
+ * context stream around every kernel it launches; enabling or disabling
+ * clears the totals.  Errors: FSNE_EHIP. */
+fsne_status fsne_profile(fsne_ctx *ctx, int32_t enable);
+
+/* Totals since fsne_profile(ctx, 1): ms[k] summed kernel time and
+ * launches[k] launch count, k < FSNE_NKERNELS (host arrays).  A kernel that
+ * exits early because the coin did not fire still counts as a launch.
+ * Synchronises.  Errors: FSNE_EINVAL, FSNE_EHIP. */
+fsne_status fsne_get_kernel_times(fsne_ctx *ctx, double *ms, int64_t *launches);
+
 /* Destroy the context and free its device memory (NULL is accepted). */
 void fsne_destroy(fsne_ctx *ctx);
 

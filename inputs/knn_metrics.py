@@ -1,0 +1,55 @@
+"""Neighbour-list quality metrics for evaluation (not part of the method).
+
+Exact K-NN ground truth by brute force on the CPU: candidates from the
+expanded form in float32 (torch matmul), then their distances recomputed
+directly in float64 so the order is exact.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _as_f32(X):
+    from inputs.generators import bf16_bits_to_f32
+
+    return bf16_bits_to_f32(X) if X.dtype == np.uint16 else np.asarray(X, dtype=np.float32)
+
+
+def exact_knn(X, queries, K, batch=256):
+    """Exact K nearest neighbours (self excluded) of the query rows: (idx, d2 float64)."""
+    import torch
+
+    Xf = _as_f32(X)
+    Xt = torch.from_numpy(Xf)
+    nrm = (Xt * Xt).sum(1)
+    q = np.asarray(queries, dtype=np.int64)
+    out_i = np.empty((q.size, K), dtype=np.int64)
+    out_d = np.empty((q.size, K), dtype=np.float64)
+    extra = min(Xf.shape[0] - 1, 2 * K + 8)
+    for s in range(0, q.size, batch):
+        qq = q[s:s + batch]
+        Q = Xt[qq]
+        approx = nrm[qq][:, None] + nrm[None, :] - 2.0 * (Q @ Xt.T)
+        approx[torch.arange(qq.size), torch.from_numpy(qq)] = float("inf")
+        cand = torch.topk(approx, extra + 1, dim=1, largest=False).indices.numpy()
+        for r, i in enumerate(qq):
+            c = cand[r][cand[r] != i][:extra]
+            d = ((Xf[c].astype(np.float64) - Xf[i].astype(np.float64)) ** 2).sum(1)
+            order = np.lexsort((c, d))[:K]
+            out_i[s + r] = c[order]
+            out_d[s + r] = d[order]
+    return out_i, out_d
+
+
+def recall_at_k(lists, X, queries, exact_d2, rel_tie=1e-6):
+    """Fraction of list entries whose exact distance is within the exact K-th
+    distance (times 1 + rel_tie): a hit at a tie counts."""
+    Xf = _as_f32(X)
+    q = np.asarray(queries, dtype=np.int64)
+    K = exact_d2.shape[1]
+    hits = 0
+    for r, i in enumerate(q):
+        lst = np.asarray(lists[i][:K], dtype=np.int64)
+        d = ((Xf[lst].astype(np.float64) - Xf[i].astype(np.float64)) ** 2).sum(1)
+        hits += int(np.sum(d <= exact_d2[r, K - 1] * (1.0 + rel_tie)))
+    return hits / (q.size * K)

@@ -37,6 +37,16 @@ struct fsne_ctx {
   Scalars* sc = nullptr;
   std::string err;
   std::vector<void*> owned;
+  // per-kernel timing (fsne_profile)
+  bool prof = false;
+  struct Timed {
+    int kernel;
+    hipEvent_t start, stop;
+  };
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> spare;
+  double ms[FSNE_NKERNELS] = {0};
+  int64_t launches[FSNE_NKERNELS] = {0};
 };
 
 namespace {
@@ -164,20 +174,45 @@ fsne_status dalloc(fsne_ctx* c, T** p, size_t n) {
 
 size_t xbytes(const fsne_ctx* c) { return c->xdtype == FSNE_F32 ? 4 : 2; }
 
-// Host Y rows (n x d) -> device rows (n x DP, padding zero) at row offset r0.
+// Host rows (n x d) -> device rows (n x DP, padding zero) at row offset r0.
+// The host block goes over in one contiguous copy; a kernel re-strides it.
 fsne_status put_Y(fsne_ctx* c, float* dst, const float* src, int64_t r0, int64_t n) {
-  HIPCHK(c, hipMemsetAsync(dst + r0 * c->DP, 0, sizeof(float) * n * c->DP, c->stream));
-  if (src && n > 0)
-    HIPCHK(c, hipMemcpy2DAsync(dst + r0 * c->DP, sizeof(float) * c->DP, src, sizeof(float) * c->d,
-                               sizeof(float) * c->d, n, hipMemcpyHostToDevice, c->stream));
+  if (n <= 0) return FSNE_OK;
+  if (!src) {
+    HIPCHK(c, hipMemsetAsync(dst + r0 * c->DP, 0, sizeof(float) * n * c->DP, c->stream));
+    return FSNE_OK;
+  }
+  if (c->d == c->DP) {
+    HIPCHK(c, hipMemcpyAsync(dst + r0 * c->DP, src, sizeof(float) * n * c->d,
+                             hipMemcpyHostToDevice, c->stream));
+    return FSNE_OK;
+  }
+  float* tmp = nullptr;
+  HIPCHK(c, hipMallocAsync(reinterpret_cast<void**>(&tmp), sizeof(float) * n * c->d, c->stream));
+  HIPCHK(c, hipMemcpyAsync(tmp, src, sizeof(float) * n * c->d, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, fsne::launch_restride(dst + r0 * c->DP, c->DP, tmp, c->d, n, c->d, c->DP, c->stream));
+  HIPCHK(c, hipFreeAsync(tmp, c->stream));
   return FSNE_OK;
 }
 
+// Device rows (N x DP) -> caller rows (N x d), host or device.
 fsne_status get_rows(fsne_ctx* c, float* dst, const float* src, bool dst_dev) {
-  HIPCHK(c, hipMemcpy2DAsync(dst, sizeof(float) * c->d, src, sizeof(float) * c->DP,
-                             sizeof(float) * c->d, c->N,
+  const int64_t n = c->N;
+  if (c->d == c->DP) {
+    HIPCHK(c, hipMemcpyAsync(dst, src, sizeof(float) * n * c->d,
                              dst_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                              c->stream));
+    return FSNE_OK;
+  }
+  if (dst_dev) {
+    HIPCHK(c, fsne::launch_restride(dst, c->d, src, c->DP, n, c->d, c->d, c->stream));
+    return FSNE_OK;
+  }
+  float* tmp = nullptr;
+  HIPCHK(c, hipMallocAsync(reinterpret_cast<void**>(&tmp), sizeof(float) * n * c->d, c->stream));
+  HIPCHK(c, fsne::launch_restride(tmp, c->d, src, c->DP, n, c->d, c->d, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dst, tmp, sizeof(float) * n * c->d, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipFreeAsync(tmp, c->stream));
   return FSNE_OK;
 }
 
@@ -261,9 +296,58 @@ fsne_status do_init(fsne_ctx* c, const void* X, int32_t x_on_device, const float
   return FSNE_OK;
 }
 
+hipError_t take_event(fsne_ctx* c, hipEvent_t* e) {
+  if (!c->spare.empty()) {
+    *e = c->spare.back();
+    c->spare.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Sum the elapsed times of the recorded kernel launches (synchronises).
+fsne_status drain_timings(fsne_ctx* c) {
+  if (c->pending.empty()) return FSNE_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (const auto& t : c->pending) {
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, t.start, t.stop));
+    c->ms[t.kernel] += ms;
+    c->launches[t.kernel] += 1;
+    c->spare.push_back(t.start);
+    c->spare.push_back(t.stop);
+  }
+  c->pending.clear();
+  return FSNE_OK;
+}
+
+template <typename Launch>
+fsne_status timed_launch(fsne_ctx* c, int kernel, Launch&& launch) {
+  if (!c->prof) {
+    HIPCHK(c, launch());
+    return FSNE_OK;
+  }
+  fsne_ctx::Timed t{kernel, nullptr, nullptr};
+  HIPCHK(c, take_event(c, &t.start));
+  HIPCHK(c, take_event(c, &t.stop));
+  HIPCHK(c, hipEventRecord(t.start, c->stream));
+  HIPCHK(c, launch());
+  HIPCHK(c, hipEventRecord(t.stop, c->stream));
+  c->pending.push_back(t);
+  if (c->pending.size() >= 4096) TRY(drain_timings(c));
+  return FSNE_OK;
+}
+
 void release(fsne_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (const auto& t : c->pending) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
+  c->pending.clear();
+  c->spare.clear();
   for (void* p : c->owned) (void)hipFree(p);
   c->owned.clear();
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -347,11 +431,13 @@ fsne_status fsne_step(fsne_ctx* c, int32_t n_iters) {
   if (!c) return FSNE_EINVAL;
   if (n_iters < 0) return fail(c, FSNE_EINVAL, "n_iters < 0");
   const StepArgs a = make_args(c);
+  hipStream_t s = c->stream;
   for (int32_t it = 0; it < n_iters; ++it) {
-    HIPCHK(c, fsne::launch_hd_refine(a, c->stream));
-    HIPCHK(c, fsne::launch_psym(a, 0, c->stream));
-    HIPCHK(c, fsne::launch_ld_grad(a, c->stream));
-    HIPCHK(c, fsne::launch_reduce_update(a, c->stream));
+    TRY(timed_launch(c, FSNE_K_HD_REFINE, [&] { return fsne::launch_hd_refine(a, s); }));
+    TRY(timed_launch(c, FSNE_K_AFFINITY, [&] { return fsne::launch_psym(a, 0, s); }));
+    TRY(timed_launch(c, FSNE_K_LD_GRAD, [&] { return fsne::launch_ld_grad(a, s); }));
+    TRY(timed_launch(c, FSNE_K_REDUCE, [&] { return fsne::launch_reduce(a, s); }));
+    TRY(timed_launch(c, FSNE_K_UPDATE, [&] { return fsne::launch_update(a, s); }));
   }
   return FSNE_OK;
 }
@@ -583,6 +669,28 @@ fsne_status fsne_drift_points(fsne_ctx* c, const int64_t* ids, const void* Xnew,
   } while (false);
   cleanup();
   return st;
+}
+
+fsne_status fsne_profile(fsne_ctx* c, int32_t enable) {
+  if (!c) return FSNE_EINVAL;
+  TRY(drain_timings(c));
+  c->prof = enable != 0;
+  for (int k = 0; k < FSNE_NKERNELS; ++k) {
+    c->ms[k] = 0.0;
+    c->launches[k] = 0;
+  }
+  return FSNE_OK;
+}
+
+fsne_status fsne_get_kernel_times(fsne_ctx* c, double* ms, int64_t* launches) {
+  if (!c) return FSNE_EINVAL;
+  if (!ms || !launches) return fail(c, FSNE_EINVAL, "ms and launches must not be NULL");
+  TRY(drain_timings(c));
+  for (int k = 0; k < FSNE_NKERNELS; ++k) {
+    ms[k] = c->ms[k];
+    launches[k] = c->launches[k];
+  }
+  return FSNE_OK;
 }
 
 fsne_status fsne_implode(fsne_ctx* c, float factor) {

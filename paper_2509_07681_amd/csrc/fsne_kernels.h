@@ -38,7 +38,8 @@ hipError_t launch_hd_refine(const StepArgs& a, hipStream_t s);
 hipError_t launch_hd_refine_bf16(const StepArgs& a, hipStream_t s);
 hipError_t launch_psym(const StepArgs& a, int standalone, hipStream_t s);
 hipError_t launch_ld_grad(const StepArgs& a, hipStream_t s);
-hipError_t launch_reduce_update(const StepArgs& a, hipStream_t s);
+hipError_t launch_reduce(const StepArgs& a, hipStream_t s);
+hipError_t launch_update(const StepArgs& a, hipStream_t s);
 hipError_t launch_set_fire(Scalars* sc, const Hyper& h, hipStream_t s);
 hipError_t launch_scale(float* Y, float* V, int64_t n, float inv, hipStream_t s);
 hipError_t launch_calibrate_all(const StepArgs& a, hipStream_t s);
@@ -48,5 +49,7 @@ hipError_t launch_scatter_rows(void* dst, const void* src, const int32_t* ids, i
                                int32_t row_bytes, hipStream_t s);
 hipError_t launch_mark_moved(uint8_t* moved, float* V, int32_t DP, const int32_t* ids, int32_t n,
                              hipStream_t s);
+hipError_t launch_restride(float* dst, int dst_stride, const float* src, int src_stride,
+                           int64_t n, int width, int zero_to, hipStream_t s);
 
 }  // namespace fsne

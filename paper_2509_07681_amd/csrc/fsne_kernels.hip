@@ -310,9 +310,22 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
   const float4 ri = a.rec[i];
   const float4 rj = a.rec[j];
   const float pji = expf(-ri.x * (d2 - ri.y)) * ri.w;
-  const int32_t* row = hl + (int64_t)j * Kh;
+  // Every stored HD distance comes from the same symmetric FP32 computation,
+  // so i can only be in j's sorted list if d2 <= r_j (j's largest distance);
+  // the list itself is scanned only then, 16 bytes per load.
   bool member = false;
-  for (int k = 0; k < Kh; ++k) member |= (row[k] == i);
+  if (d2 <= rj.z * (1.0f + 1e-6f)) {
+    const int32_t* row = hl + (int64_t)j * Kh;
+    if ((Kh & 3) == 0) {
+      const int4* r4 = reinterpret_cast<const int4*>(row);
+      for (int k = 0; k < (Kh >> 2); ++k) {
+        const int4 v = r4[k];
+        member |= (v.x == i) | (v.y == i) | (v.z == i) | (v.w == i);
+      }
+    } else {
+      for (int k = 0; k < Kh; ++k) member |= (row[k] == i);
+    }
+  }
   const float pij = member ? expf(-rj.x * (d2 - rj.y)) * rj.w : 0.0f;
   a.P[(int64_t)i * Kh + lane] = (pji + pij) / (2.0f * (float)a.N);
 }
@@ -326,15 +339,24 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
 // with w = (1 + d^2/alpha)^(-alpha), U = HD list union new LD list.  Rows
 // of Y are stored with a padded stride DP (zeros beyond d).
 // ---------------------------------------------------------------------------
+// Row-group layout: a row of DP floats is spread over G lanes, VEC floats
+// each, so one load instruction fetches RPI whole rows (coalesced per row).
 template <int DP>
-__device__ __forceinline__ void load_row(const float* __restrict__ Y, int32_t j, float* r) {
-  const float* p = Y + (int64_t)j * DP;
-  if constexpr (DP % 4 == 0) {
-#pragma unroll
-    for (int c = 0; c < DP; c += 4) {
-      const float4 v = *reinterpret_cast<const float4*>(p + c);
-      r[c] = v.x; r[c + 1] = v.y; r[c + 2] = v.z; r[c + 3] = v.w;
-    }
+struct LdGeom {
+  static constexpr int VEC = DP >= 4 ? 4 : DP;
+  static constexpr int G = DP / VEC;
+  static constexpr int LG = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : 4;
+  static constexpr int RPI = kWave / G;
+  static constexpr int MAXE = kWave + kCand;                 // LD entries: old list + slots
+  static constexpr int MAXP = (MAXE + RPI - 1) / RPI;         // passes over the entries
+  static constexpr bool CACHE = MAXP * VEC <= 48;             // keep entry rows in registers
+};
+
+template <int VEC>
+__device__ __forceinline__ void load_chunk(const float* __restrict__ p, float* r) {
+  if constexpr (VEC == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
   } else {
     const float2 v = *reinterpret_cast<const float2*>(p);
     r[0] = v.x; r[1] = v.y;
@@ -342,31 +364,58 @@ __device__ __forceinline__ void load_row(const float* __restrict__ Y, int32_t j,
 }
 
 // The LD distance that decides list membership: components summed in index
-// order, each product and sum rounded separately.
+// order, each square and each sum rounded separately.  The row is split over
+// G lanes, so the running sum is handed from lane to lane in component order;
+// the last lane of the group ends with the total.
 template <int DP>
-__device__ __forceinline__ float ld_decision_d2(const float* yi, const float* yj) {
+__device__ __forceinline__ float ld_decision_d2(const float* yi, const float* yj, int q) {
 #pragma clang fp contract(off)
+  using Geo = LdGeom<DP>;
+  float sq[Geo::VEC];
+#pragma unroll
+  for (int v = 0; v < Geo::VEC; ++v) {
+    const float df = yj[v] - yi[v];
+    sq[v] = df * df;
+  }
   float acc = 0.0f;
 #pragma unroll
-  for (int c = 0; c < DP; ++c) {
-    const float df = yj[c] - yi[c];
-    const float sq = df * df;
-    acc = acc + sq;
+  for (int k = 0; k < Geo::G; ++k) {
+    const float prev = Geo::G > 1 ? __shfl_up(acc, 1) : 0.0f;
+    if (q == k) {
+      float s = k == 0 ? 0.0f : prev;
+#pragma unroll
+      for (int v = 0; v < Geo::VEC; ++v) s = s + sq[v];
+      acc = s;
+    }
   }
   return acc;
 }
 
-template <int DP>
-__device__ __forceinline__ void add_pair(const float* yi, const float* yj, const Hyper& h,
-                                         float patt, float scale, float* A, float* R,
-                                         float& Zh) {
-  float dy[DP];
-  float q2 = 0.0f;
+// Sum over the G lanes of a row group (every lane of the group gets it).
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
 #pragma unroll
-  for (int c = 0; c < DP; ++c) {
-    dy[c] = yi[c] - yj[c];
-    q2 = fmaf(dy[c], dy[c], q2);
-  }
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+struct LdLds {
+  int ent[2 * kWave];     // LD entries: old list, then candidate slots (-1: none)
+  float dd[2 * kWave];    // their decision distances
+  float key[2 * kWave];   // rank scratch
+  int id[2 * kWave];
+  int newl[kWave];        // new LD list
+  int kind[2 * kWave];    // 1: entry kept and not an HD neighbour
+  int neg[kWave];         // negative samples outside U (-1: none)
+};
+
+// Adds one neighbour's contribution to this lane's components:
+//   A += patt w^(1/a) (y_i - y_j),  R += scale w^(1+1/a) (y_i - y_j);
+// returns scale * w (the Zh term), with w = (1 + q2/alpha)^(-alpha).
+template <int VEC>
+__device__ __forceinline__ float pair_terms(const float* yi, const float* yj, float q2,
+                                            const Hyper& h, float patt, float scale, float* A,
+                                            float* R) {
   const float wa = 1.0f / fmaf(q2, h.inv_alpha, 1.0f);
   float w;
   if (h.alpha == 1.0f)
@@ -377,21 +426,26 @@ __device__ __forceinline__ void add_pair(const float* yi, const float* yj, const
     w = exp2f(h.alpha * log2f(wa));
   const float fa = patt * wa, fr = scale * w * wa;
 #pragma unroll
-  for (int c = 0; c < DP; ++c) {
-    A[c] = fmaf(fa, dy[c], A[c]);
-    R[c] = fmaf(fr, dy[c], R[c]);
+  for (int v = 0; v < VEC; ++v) {
+    const float dy = yi[v] - yj[v];
+    A[v] = fmaf(fa, dy, A[v]);
+    R[v] = fmaf(fr, dy, R[v]);
   }
-  Zh = fmaf(scale, w, Zh);
+  return scale * w;
 }
 
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
-  __shared__ WaveLds lds_all[kWavesPerBlock];
-  WaveLds& S = lds_all[threadIdx.x / kWave];
+  using Geo = LdGeom<DP>;
+  constexpr int VEC = Geo::VEC, G = Geo::G, RPI = Geo::RPI;
+  __shared__ LdLds lds_all[kWavesPerBlock];
+  LdLds& S = lds_all[threadIdx.x / kWave];
   const int32_t i = (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   if (i >= a.N) return;
   const Scalars* sc = a.sc;
   const int lane = lane_id();
+  const int q = lane & (G - 1);          // chunk of the row this lane holds
+  const int rg = lane >> Geo::LG;        // row slot within a pass
   const uint32_t t = sc->t;
   const int hb = sc->hd_cur ^ sc->fire;  // HD lists after this iteration's HD phase
   const int Kh = a.Kh, Kl = a.Kl;
@@ -400,37 +454,58 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   int32_t* lout = a.ld_idx[(t & 1) ^ 1];
   const float* Y = a.Y;
 
-  float yi[DP];
-  load_row<DP>(Y, i, yi);
+  float yi[VEC];
+  load_chunk<VEC>(Y + (int64_t)i * DP + q * VEC, yi);
   const int hid = lane < Kh ? hl[(int64_t)i * Kh + lane] : -1;
   const float pk = lane < Kh ? a.P[(int64_t)i * Kh + lane] : 0.0f;
   const int lid = lane < Kl ? lin[(int64_t)i * Kl + lane] : -1;
   const int c = make_candidate(i, t, kStreamLDC, a.h, lin, Kl, lid, hl, Kh, hid, a.N);
 
-  float yl[DP], yc[DP];
-  float dl = kInf, dc = kInf;
-  if (lane < Kl) {
-    load_row<DP>(Y, lid, yl);
-    dl = ld_decision_d2<DP>(yi, yl);
-  }
-  if (c >= 0) {
-    load_row<DP>(Y, c, yc);
-    dc = ld_decision_d2<DP>(yi, yc);
-  }
-  int rl, rc;
-  rank_two(lane < Kl ? dl : kInf, lane < Kl ? lid : kNoId, dc, c >= 0 ? c : kNoId, Kl, kCand,
-           S.key, S.id, rl, rc);
-  const bool keep_l = lane < Kl && rl < Kl;
-  const bool keep_c = c >= 0 && rc < Kl;
-  if (keep_l) {
-    lout[(int64_t)i * Kl + rl] = lid;
-    S.lst[rl] = lid;
-  }
-  if (keep_c) {
-    lout[(int64_t)i * Kl + rc] = c;
-    S.lst[rc] = c;
+  // entry table: old LD list at [0, Kl), candidate slot s at Kl + s
+  const int ne = Kl + kCand;
+  if (lane < Kl) S.ent[lane] = lid;
+  if (lane < kCand) S.ent[Kl + lane] = c;
+  wave_lds_sync();
+
+  // decision distances of the entries, rows kept in registers when they fit
+  float rows[Geo::CACHE ? Geo::MAXP : 1][VEC];
+#pragma unroll
+  for (int p = 0; p < Geo::MAXP; ++p) {
+    if (p * RPI < ne) {
+      const int e = p * RPI + rg;
+      const int id = e < ne ? S.ent[e] : -1;
+      float yj[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) yj[v] = yi[v];
+      if (id >= 0) load_chunk<VEC>(Y + (int64_t)id * DP + q * VEC, yj);
+      const float dist = ld_decision_d2<DP>(yi, yj, q);
+      if (q == G - 1 && e < ne) S.dd[e] = id >= 0 ? dist : kInf;
+      if constexpr (Geo::CACHE) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) rows[p][v] = yj[v];
+      }
+    }
   }
   wave_lds_sync();
+
+  // merge: rank of every entry by (distance, index); keep the first Kl
+  const int eA = lane, eB = kWave + lane;
+  const int idA = eA < ne ? S.ent[eA] : -1;
+  const int idB = eB < ne ? S.ent[eB] : -1;
+  const float dA = idA >= 0 ? S.dd[eA] : kInf;
+  const float dB = idB >= 0 ? S.dd[eB] : kInf;
+  int rA, rB;
+  rank_two(dA, idA >= 0 ? idA : kNoId, dB, idB >= 0 ? idB : kNoId, min(ne, kWave),
+           max(ne - kWave, 0), S.key, S.id, rA, rB);
+  const bool keepA = idA >= 0 && rA < Kl, keepB = idB >= 0 && rB < Kl;
+  if (keepA) {
+    lout[(int64_t)i * Kl + rA] = idA;
+    S.newl[rA] = idA;
+  }
+  if (keepB) {
+    lout[(int64_t)i * Kl + rB] = idB;
+    S.newl[rB] = idB;
+  }
 
   // negatives: uniform other points, one per lane
   const bool has_neg = lane < a.h.n_neg;
@@ -439,48 +514,105 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
     const uint4 u = philox((uint32_t)i, t, kStreamNeg, (uint32_t)lane, a.h.key0, a.h.key1);
     jn = draw_other(u.x, i, a.N);
   }
-  // membership in the HD list (LD entries and negatives), and in the new LD list (negatives)
-  bool l_in_hd = false, c_in_hd = false, n_in_u = false;
+  bool a_hd = false, b_hd = false, n_in = false;
   for (int k = 0; k < Kh; ++k) {
     const int v = __builtin_amdgcn_readlane(hid, k);
-    l_in_hd |= (lid == v);
-    c_in_hd |= (c == v);
-    n_in_u |= (jn == v);
+    a_hd |= (idA == v);
+    b_hd |= (idB == v);
+    n_in |= (jn == v);
   }
-  for (int k = 0; k < Kl; ++k) n_in_u |= (jn == S.lst[k]);
+  wave_lds_sync();
+  for (int k = 0; k < Kl; ++k) n_in |= (jn == S.newl[k]);
+  if (eA < ne) S.kind[eA] = (keepA && !a_hd) ? 1 : 0;
+  if (eB < ne) S.kind[eB] = (keepB && !b_hd) ? 1 : 0;
+  S.neg[lane] = (has_neg && !n_in) ? jn : -1;
+  wave_lds_sync();
 
-  float A[DP], R[DP], Zh = 0.0f;
+  float A[VEC], R[VEC];
 #pragma unroll
-  for (int q = 0; q < DP; ++q) A[q] = R[q] = 0.0f;
-  if (lane < Kh) {
-    float yh[DP];
-    load_row<DP>(Y, hid, yh);
-    add_pair<DP>(yi, yh, a.h, pk, 1.0f, A, R, Zh);
-  }
-  if (keep_l && !l_in_hd) add_pair<DP>(yi, yl, a.h, 0.0f, 1.0f, A, R, Zh);
-  if (keep_c && !c_in_hd) add_pair<DP>(yi, yc, a.h, 0.0f, 1.0f, A, R, Zh);
-  if (has_neg && !n_in_u) {
-    float yn[DP];
-    load_row<DP>(Y, jn, yn);
-    add_pair<DP>(yi, yn, a.h, 0.0f, a.neg_scale, A, R, Zh);
-  }
+  for (int v = 0; v < VEC; ++v) A[v] = R[v] = 0.0f;
+  float zh = 0.0f;
+  // HD neighbours: attraction and repulsion
+  for (int b = 0; b < Kh; b += RPI) {
+    const int r = b + rg;
+    const int id = __shfl(hid, r & (kWave - 1));
+    const float pr = __shfl(pk, r & (kWave - 1));
+    float yj[VEC];
 #pragma unroll
-  for (int q = 0; q < DP; ++q) {
-    A[q] = wave_sum(A[q]);
-    R[q] = wave_sum(R[q]);
-  }
-  Zh = wave_sum(Zh);
-  if (lane < DP) {
-    float av = 0.0f, rv = 0.0f;
+    for (int v = 0; v < VEC; ++v) yj[v] = yi[v];
+    if (r < Kh) load_chunk<VEC>(Y + (int64_t)id * DP + q * VEC, yj);
+    float part = 0.0f;
 #pragma unroll
-    for (int q = 0; q < DP; ++q) {
-      av = lane == q ? A[q] : av;
-      rv = lane == q ? R[q] : rv;
+    for (int v = 0; v < VEC; ++v) {
+      const float dy = yi[v] - yj[v];
+      part = fmaf(dy, dy, part);
     }
-    a.A[(int64_t)i * DP + lane] = av;
-    a.R[(int64_t)i * DP + lane] = rv;
+    const float q2 = group_sum<G>(part);
+    if (r < Kh) {
+      const float z = pair_terms<VEC>(yi, yj, q2, a.h, pr, 1.0f, A, R);
+      if (q == 0) zh += z;
+    }
   }
-  if (lane == 0) a.Zh[i] = Zh;
+  // LD neighbours that are not HD neighbours: repulsion
+#pragma unroll
+  for (int p = 0; p < Geo::MAXP; ++p) {
+    if (p * RPI < ne) {
+      const int e = p * RPI + rg;
+      if (e < ne && S.kind[e]) {
+        float yj[VEC];
+        if constexpr (Geo::CACHE) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) yj[v] = rows[p][v];
+        } else {
+          load_chunk<VEC>(Y + (int64_t)S.ent[e] * DP + q * VEC, yj);
+        }
+        const float z = pair_terms<VEC>(yi, yj, S.dd[e], a.h, 0.0f, 1.0f, A, R);
+        if (q == 0) zh += z;
+      }
+    }
+  }
+  // negative samples outside U, weighted (N-1)/n_neg
+  for (int b = 0; b < a.h.n_neg; b += RPI) {
+    const int r = b + rg;
+    const int id = r < a.h.n_neg ? S.neg[r] : -1;
+    float yj[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) yj[v] = yi[v];
+    if (id >= 0) load_chunk<VEC>(Y + (int64_t)id * DP + q * VEC, yj);
+    float part = 0.0f;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const float dy = yi[v] - yj[v];
+      part = fmaf(dy, dy, part);
+    }
+    const float q2 = group_sum<G>(part);
+    if (id >= 0) {
+      const float z = pair_terms<VEC>(yi, yj, q2, a.h, 0.0f, a.neg_scale, A, R);
+      if (q == 0) zh += z;
+    }
+  }
+  // sum over the row slots (lanes holding the same chunk), then store
+#pragma unroll
+  for (int o = G; o < kWave; o <<= 1) {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      A[v] += __shfl_xor(A[v], o);
+      R[v] += __shfl_xor(R[v], o);
+    }
+  }
+  zh = wave_sum(zh);
+  if (lane < G) {
+    float* ao = a.A + (int64_t)i * DP + lane * VEC;
+    float* ro = a.R + (int64_t)i * DP + lane * VEC;
+    if constexpr (VEC == 4) {
+      *reinterpret_cast<float4*>(ao) = make_float4(A[0], A[1], A[2], A[3]);
+      *reinterpret_cast<float4*>(ro) = make_float4(R[0], R[1], R[2], R[3]);
+    } else {
+      *reinterpret_cast<float2*>(ao) = make_float2(A[0], A[1]);
+      *reinterpret_cast<float2*>(ro) = make_float2(R[0], R[1]);
+    }
+  }
+  if (lane == 0) a.Zh[i] = zh;
 }
 
 // ---------------------------------------------------------------------------
@@ -735,10 +867,12 @@ hipError_t launch_ld_grad(const StepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_update(const StepArgs& a, hipStream_t s) {
+hipError_t launch_reduce(const StepArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(kReduceBlocks), dim3(256), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const StepArgs& a, hipStream_t s) {
   const int64_t total = (int64_t)a.N * a.DP;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 1024) blocks = 1024;
@@ -791,6 +925,27 @@ hipError_t launch_mark_moved(uint8_t* moved, float* V, int32_t DP, const int32_t
                              hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mark_moved, dim3(256), dim3(256), 0, s, moved, V, DP, ids, n);
+  return hipGetLastError();
+}
+
+// Row re-striding between the caller's n x d layout and the padded n x DP one
+// (padding written as zero).
+__global__ void k_restride(float* dst, int dst_stride, const float* src, int src_stride,
+                           int64_t n, int width, int zero_to) {
+  const int64_t total = n * (int64_t)zero_to;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = q / zero_to;
+    const int c = (int)(q % zero_to);
+    dst[r * dst_stride + c] = c < width ? src[r * src_stride + c] : 0.0f;
+  }
+}
+
+hipError_t launch_restride(float* dst, int dst_stride, const float* src, int src_stride,
+                           int64_t n, int width, int zero_to, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_restride, dim3(2048), dim3(256), 0, s, dst, dst_stride, src, src_stride,
+                     n, width, zero_to);
   return hipGetLastError();
 }
 

@@ -297,6 +297,12 @@ class Embedding:
     def implode(self, factor):
         fsne_implode(self.ctx, factor)
 
+    def profile(self, enable=True):
+        fsne_profile(self.ctx, enable)
+
+    def kernel_times(self):
+        return fsne_get_kernel_times(self.ctx)
+
     def close(self):
         if getattr(self, "ctx", None):
             fsne_destroy(self.ctx)
@@ -307,3 +313,24 @@ class Embedding:
             self.close()
         except Exception:
             pass
+
+
+FSNE_NKERNELS = 5
+KERNEL_NAMES = ("hd_refine", "affinity", "ld_grad", "reduce", "update")
+
+
+def fsne_profile(ctx, enable: bool):
+    L = load_library()
+    L.fsne_profile.argtypes = [C.c_void_p, C.c_int32]
+    L.fsne_profile.restype = C.c_int
+    _check(ctx, L.fsne_profile(ctx, 1 if enable else 0))
+
+
+def fsne_get_kernel_times(ctx):
+    L = load_library()
+    L.fsne_get_kernel_times.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.fsne_get_kernel_times.restype = C.c_int
+    ms = np.zeros(FSNE_NKERNELS, dtype=np.float64)
+    n = np.zeros(FSNE_NKERNELS, dtype=np.int64)
+    _check(ctx, L.fsne_get_kernel_times(ctx, _ptr(ms), _ptr(n)))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_NAMES)}
