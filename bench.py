@@ -39,14 +39,30 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def bytes_per_point(cfg, xbytes):
-    """Algorithmic bytes per point of each kernel (no cache reuse assumed)."""
+def bytes_per_point(cfg, xbytes, hd_cand, ld_cand):
+    """Bytes each kernel must move per point, no cache reuse assumed.
+
+    hd_cand / ld_cand: mean number of distinct candidate rows per point that
+    the kernels loaded (duplicate slots are dropped before any row is read).
+    """
+    D, d, Kh, Kl, nn = cfg["D"], cfg["d"], cfg["K_hd"], cfg["K_ld"], cfg["n_neg"]
+    dp = 2
+    while dp < d:
+        dp *= 2
+    sx, sy = D * xbytes, 4 * dp
+    hd = sx * (1 + hd_cand) + 16 * Kh + 4 * Kl + 96 + 33
+    ld = sy * (1 + Kl + ld_cand + Kh + nn + 2) + 8 * Kh + 8 * Kl + 96 + 5
+    upd = 6 * sy
+    return dict(hd_refine=hd, ld_grad=ld, update=upd)
+
+
+def survey_bytes_per_point(cfg, xbytes):
+    """The same with every one of the 32 candidate slots counted."""
     D, d, Kh, Kl, nn = cfg["D"], cfg["d"], cfg["K_hd"], cfg["K_ld"], cfg["n_neg"]
     sx, sy = D * xbytes, 4 * d
     hd = (C_SLOTS + 1) * sx + 96 + 16 * Kh + 12 + 24 * Kh + 12
     ld = sy + 8 * Kl + 8 * Kh + 96 + (Kl + C_SLOTS + Kh + nn) * sy + 2 * sy
-    upd = 6 * sy
-    return dict(hd_refine=hd, ld_grad=ld, update=upd)
+    return dict(hd_refine=hd, ld_grad=ld, update=6 * sy)
 
 
 def schedule(F, base, t):
@@ -145,22 +161,23 @@ def main():
     st = emb.stats()
     assert st["nonfinite"] == 0, "embedding diverged"
 
-    # per-kernel durations from HIP events recorded on the library's stream
+    # per-kernel durations from HIP events recorded on the library's stream,
+    # and the candidate rows each iteration actually loaded
     n_prof = min(args.steps, 50)
     emb.profile(True)
-    emb.step(n_prof)
+    hd_c, ld_c = [], []
+    for _ in range(n_prof):
+        emb.step(1)
+        s1 = emb.stats()
+        hd_c.append(s1["hd_cand_rows"] / N)
+        ld_c.append(s1["ld_cand_rows"] / N)
     kt = emb.kernel_times()
     emb.profile(False)
-    hp_ld = F.fsne_default_hparams(**{**hp.as_dict(), "hd_mode": 2})
-    emb.set_hyperparams(hp_ld)
-    emb.sync()
-    t1 = time.perf_counter()
-    emb.step(n_prof)
-    emb.sync()
-    ld_only_ms = (time.perf_counter() - t1) * 1e3 / n_prof
     emb.close()
 
-    bpp = bytes_per_point(cfg, 4)
+    hd_cand, ld_cand = float(np.mean(hd_c)), float(np.mean(ld_c))
+    bpp = bytes_per_point(cfg, 4, hd_cand, ld_cand)
+    sbpp = survey_bytes_per_point(cfg, 4)
     kernels = {}
     for k, (ms, n) in kt.items():
         avg = ms / max(n, 1)
@@ -168,8 +185,12 @@ def main():
         if k in bpp:
             gb = bpp[k] * N / 1e9
             e.update(algorithmic_GB=round(gb, 3), GBps=round(gb / (avg * 1e-3), 1),
-                     frac=round(gb / (avg * 1e-3) / PEAK_HBM_GBS, 4))
+                     frac=round(gb / (avg * 1e-3) / PEAK_HBM_GBS, 4),
+                     all_slots_GB=round(sbpp[k] * N / 1e9, 3))
         kernels[k] = e
+    kernels["hd_refine"]["candidate_rows_per_point"] = round(hd_cand, 3)
+    kernels["ld_grad"]["candidate_rows_per_point"] = round(ld_cand, 3)
+    ld_only_ms = sum(kernels[k]["avg_ms"] for k in ("ld_grad", "reduce", "update"))
     dom = kernels["hd_refine"]
     traffic = None
     tf = os.path.join(ROOT, "profiles", "traffic.json")
@@ -200,6 +221,7 @@ def main():
                      "traffic": traffic},
         "kernels": kernels,
         "ld_only_ms_per_step": round(ld_only_ms, 4),
+        "ld_only_iters_per_s": round(1000.0 / ld_only_ms, 2),
     }
 
     if not args.no_quality:

@@ -25,7 +25,7 @@
  *     the get_* calls synchronise the stream before they return.
  *   - A context is not thread-safe: calls on one context must not overlap.
  *   - Layouts are row-major: point i's row of an N x W array starts at i*W.
- *   - N <= 2^31 - 1; K_hd, K_ld <= 64; d <= 64; n_neg <= 64.
+ *   - N <= 2^31 - 1; K_hd, K_ld <= 64; d <= 64; n_neg <= 64; D <= fsne_max_dim().
  */
 #ifndef FSNE_H
 #define FSNE_H
@@ -96,7 +96,14 @@ typedef struct fsne_stats {
     int32_t n_new;      /* points whose HD list changed in the last refinement     */
     float Z;            /* normaliser of the last iteration                        */
     int32_t nonfinite;  /* 1 if a NaN/inf reached the embedding                    */
+    uint32_t hd_cand_rows; /* distinct HD candidate rows loaded by the last HD
+                              refinement (duplicates are never loaded)             */
+    uint32_t ld_cand_rows; /* distinct LD candidate rows of the last iteration     */
 } fsne_stats;
+
+/* Largest HD dimension D the library accepts for rows of xdtype: 4096 for
+ * FP32 with D % 4 == 0, 2048 for BF16 with D % 8 == 0, 1024 otherwise. */
+int32_t fsne_max_dim(int32_t xdtype, int32_t D);
 
 /* Fill *hp with the defaults: alpha 1, perplexity 10, lr 100, momentum 0.5,
  * attr 1, rep 1, n_neg 16, hd_mode 0, dist_mode 0, e_smooth 0.1, p_min 0.05,

@@ -28,6 +28,8 @@ struct fsne_ctx {
   float *Y = nullptr, *V = nullptr, *A = nullptr, *R = nullptr, *Zh = nullptr, *P = nullptr;
   float* zpart = nullptr;
   int32_t* fpart = nullptr;
+  uint32_t* cpart = nullptr;
+  uint8_t* ldc = nullptr;
   int32_t* hd_idx[2] = {nullptr, nullptr};
   float* hd_d2[2] = {nullptr, nullptr};
   int32_t* ld_idx[2] = {nullptr, nullptr};
@@ -125,6 +127,8 @@ StepArgs make_args(const fsne_ctx* c) {
   a.Zh = c->Zh;
   a.zpart = c->zpart;
   a.fpart = c->fpart;
+  a.cpart = c->cpart;
+  a.ldc = c->ldc;
   a.neg_scale = c->hp.n_neg > 0 ? (float)(c->N - 1) / (float)c->hp.n_neg : 0.0f;
   return a;
 }
@@ -246,6 +250,8 @@ fsne_status alloc_state(fsne_ctx* c) {
   TRY(dalloc(c, &c->P, cap * c->Kh));
   TRY(dalloc(c, &c->zpart, (size_t)fsne::kReduceBlocks));
   TRY(dalloc(c, &c->fpart, (size_t)fsne::kReduceBlocks));
+  TRY(dalloc(c, &c->cpart, 2 * (size_t)fsne::kReduceBlocks));
+  TRY(dalloc(c, &c->ldc, cap));
   for (int b = 0; b < 2; ++b) {
     TRY(dalloc(c, &c->hd_idx[b], cap * c->Kh));
     TRY(dalloc(c, &c->hd_d2[b], cap * c->Kh));
@@ -259,6 +265,7 @@ fsne_status alloc_state(fsne_ctx* c) {
   HIPCHK(c, hipMemsetAsync(c->R, 0, sizeof(float) * cap * c->DP, c->stream));
   HIPCHK(c, hipMemsetAsync(c->Zh, 0, sizeof(float) * cap, c->stream));
   HIPCHK(c, hipMemsetAsync(c->flags, 0, cap, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->ldc, 0, cap, c->stream));
   return FSNE_OK;
 }
 
@@ -358,6 +365,13 @@ void release(fsne_ctx* c) {
 
 extern "C" {
 
+int32_t fsne_max_dim(int32_t xdtype, int32_t D) {
+  // rows are spread over a wave in vectors of 16 bytes (when D allows) or
+  // single elements, at most 16 (FP32) / 4 (BF16) vectors per lane
+  if (xdtype == FSNE_F32) return D % 4 == 0 ? 64 * 4 * 16 : 64 * 16;
+  return D % 8 == 0 ? 64 * 8 * 4 : 64 * 16;
+}
+
 fsne_status fsne_default_hparams(fsne_hparams* hp) {
   if (!hp) return FSNE_EINVAL;
   hp->alpha = 1.0f;
@@ -385,6 +399,7 @@ fsne_status fsne_init(fsne_ctx** out, const void* X, int64_t N, int32_t D, int32
       K_ld < 1 || K_ld > 64 || K_hd >= N || K_ld >= N || (xdtype != FSNE_F32 && xdtype != FSNE_BF16))
     return FSNE_EINVAL;
   if (capacity < N || capacity > 2147483647LL) return FSNE_EINVAL;
+  if (D > fsne_max_dim(xdtype, D)) return FSNE_EINVAL;
   fsne_ctx* c = new (std::nothrow) fsne_ctx();
   if (!c) return FSNE_ENOMEM;
   fsne_hparams h;
@@ -518,6 +533,8 @@ fsne_status fsne_get_state(fsne_ctx* c, const fsne_state_view* v) {
   if (v->P) HIPCHK(c, hipMemcpyAsync(v->P, c->P, sizeof(float) * N * c->Kh, k, c->stream));
   if (v->flags) HIPCHK(c, hipMemcpyAsync(v->flags, c->flags, (size_t)N, k, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (v->flags)
+    for (int64_t k = 0; k < N; ++k) v->flags[k] &= 1u;
   if (v->E) *v->E = s.E;
   if (v->t) *v->t = s.t;
   return FSNE_OK;
@@ -569,6 +586,8 @@ fsne_status fsne_get_stats(fsne_ctx* c, fsne_stats* st) {
   st->n_new = s.n_new;
   st->Z = s.Z;
   st->nonfinite = s.nonfinite;
+  st->hd_cand_rows = s.hd_cand;
+  st->ld_cand_rows = s.ld_cand;
   if (s.nonfinite) return fail(c, FSNE_ENONFINITE, "embedding holds a NaN or infinity");
   return FSNE_OK;
 }

@@ -36,6 +36,8 @@ struct Scalars {
   float Z;             // normaliser of the last iteration
   int32_t nonfinite;   // set when a NaN/inf reached the embedding
   int32_t last_fired;  // whether iteration t-1 refined the HD lists
+  uint32_t hd_cand;    // distinct HD candidate rows loaded in the last iteration
+  uint32_t ld_cand;    // distinct LD candidate rows loaded in the last iteration
 };
 
 // Hyperparameters in the form the kernels use.
@@ -121,20 +123,41 @@ __device__ __forceinline__ float readlane_f(float v, int k) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+// DPP moves (row = 16 lanes).  Lanes outside row_mask keep 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+constexpr int kDppSwap1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppSwap2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7-i within 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15-i within a row
+constexpr int kDppBcast15 = 0x142;     // lane 15 of row r -> row r+1
+constexpr int kDppBcast31 = 0x143;     // lane 31 -> rows 2, 3
+
+// Sum over aligned groups of g lanes (g = 1, 2, ..., 64; g wave-uniform).
+// For g <= 16 every lane of the group gets the sum; for g = 32 and 64 the
+// last lane of the group holds it.  The sequence of additions depends only
+// on lane positions.
+__device__ __forceinline__ float group_sum_dpp(float v, int g) {
+  if (g >= 2) v += dpp<kDppSwap1>(v);
+  if (g >= 4) v += dpp<kDppSwap2>(v);
+  if (g >= 8) v += dpp<kDppHalfMirror>(v);
+  if (g >= 16) v += dpp<kDppMirror>(v);
+  if (g >= 32) v += dpp<kDppBcast15, 0xA>(v);
+  if (g >= 64) v += dpp<kDppBcast31, 0xC>(v);
   return v;
 }
 
-// Wave sum broadcast from lane 0.  Partner lanes of the butterfly can round
-// differently once the compiler fuses a product into its first add, so a
-// value that steers control flow is taken from one lane: every lane then
-// branches alike and no lane drops out of a later cross-lane operation.
+// Wave sum, the same value in every lane (taken from lane 63 with readlane,
+// so it is wave-uniform: control flow that depends on it cannot diverge and
+// no lane drops out of a later cross-lane operation).
 __device__ __forceinline__ float wave_sum_uniform(float v) {
-  v = wave_sum(v);
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+  v = group_sum_dpp(v, kWave);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1));
 }
+
+__device__ __forceinline__ float wave_sum(float v) { return wave_sum_uniform(v); }
 
 __device__ __forceinline__ int popc_below(uint64_t mask, int lane) {
   return __popcll(mask & ((1ull << lane) - 1ull));
@@ -148,29 +171,159 @@ __device__ __forceinline__ bool key_less(float da, int ia, float db, int ib) {
 // nA + nB entries of the wave, ordered by (distance, index).  Invalid
 // entries carry (+inf, INT_MAX) and rank after every valid one.
 __device__ __forceinline__ void rank_two(float ka, int ia, float kb, int ib, int nA, int nB,
-                                         float* skey, int* sid, int& ra, int& rb) {
+                                         int2* skey, int& ra, int& rb) {
   const int lane = lane_id();
-  skey[lane] = ka;
-  sid[lane] = ia;
-  skey[kWave + lane] = kb;
-  sid[kWave + lane] = ib;
+  skey[lane] = make_int2(__float_as_int(ka), ia);
+  skey[kWave + lane] = make_int2(__float_as_int(kb), ib);
   wave_lds_sync();
   int a = 0, b = 0;
   for (int k = 0; k < nA; ++k) {
-    const float kk = skey[k];
-    const int ii = sid[k];
-    a += key_less(kk, ii, ka, ia);
-    b += key_less(kk, ii, kb, ib);
+    const int2 e = skey[k];
+    const float kk = __int_as_float(e.x);
+    a += key_less(kk, e.y, ka, ia);
+    b += key_less(kk, e.y, kb, ib);
   }
   for (int k = 0; k < nB; ++k) {
-    const float kk = skey[kWave + k];
-    const int ii = sid[kWave + k];
-    a += key_less(kk, ii, ka, ia);
-    b += key_less(kk, ii, kb, ib);
+    const int2 e = skey[kWave + k];
+    const float kk = __int_as_float(e.x);
+    a += key_less(kk, e.y, ka, ia);
+    b += key_less(kk, e.y, kb, ib);
   }
   ra = a;
   rb = b;
   wave_lds_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Sorting keys: (squared distance bits << 32) | index.  Distances are >= 0,
+// so the unsigned order of the bits is the numeric order and ties between
+// equal distances go to the smaller index; an empty slot is all ones.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kNoKey = ~0ull;
+
+__device__ __forceinline__ uint64_t pack_key(float d2, int id) {
+  return ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)id;
+}
+__device__ __forceinline__ int key_id(uint64_t k) { return (int)(uint32_t)k; }
+__device__ __forceinline__ float key_d2(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppSwap1, 0xF, 0xF, false);
+  else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppSwap2, 0xF, 0xF, false);
+  else if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (J << 10) | 0x1F);
+  else return (uint32_t)__shfl_xor((int)v, J);
+}
+
+// One compare-exchange stage of a bitonic network: block size KB, distance J.
+template <int KB, int J>
+__device__ __forceinline__ void bitonic_stage(uint64_t& key, uint32_t& aux, int lane) {
+  const uint32_t lo = xor_lane<J>((uint32_t)key);
+  const uint32_t hi = xor_lane<J>((uint32_t)(key >> 32));
+  const uint32_t pa = xor_lane<J>(aux);
+  const uint64_t pk = ((uint64_t)hi << 32) | lo;
+  const bool up = (lane & KB) == 0;            // this block sorts ascending
+  const bool low = (lane & J) == 0;            // lower lane of the pair
+  const bool take_min = (low == up);
+  const bool mine = take_min ? (key <= pk) : (key >= pk);
+  key = mine ? key : pk;
+  aux = mine ? aux : pa;
+}
+
+// Ascending bitonic sort of one key (+ an attached word) per lane over
+// aligned groups of NL lanes (NL = 32 or 64).
+template <int NL>
+__device__ __forceinline__ void bitonic_sort(uint64_t& key, uint32_t& aux) {
+  const int lane = lane_id();
+  bitonic_stage<2, 1>(key, aux, lane);
+  bitonic_stage<4, 2>(key, aux, lane);
+  bitonic_stage<4, 1>(key, aux, lane);
+  bitonic_stage<8, 4>(key, aux, lane);
+  bitonic_stage<8, 2>(key, aux, lane);
+  bitonic_stage<8, 1>(key, aux, lane);
+  bitonic_stage<16, 8>(key, aux, lane);
+  bitonic_stage<16, 4>(key, aux, lane);
+  bitonic_stage<16, 2>(key, aux, lane);
+  bitonic_stage<16, 1>(key, aux, lane);
+  bitonic_stage<NL == 32 ? 0 : 32, 16>(key, aux, lane);
+  bitonic_stage<NL == 32 ? 0 : 32, 8>(key, aux, lane);
+  bitonic_stage<NL == 32 ? 0 : 32, 4>(key, aux, lane);
+  bitonic_stage<NL == 32 ? 0 : 32, 2>(key, aux, lane);
+  bitonic_stage<NL == 32 ? 0 : 32, 1>(key, aux, lane);
+  if constexpr (NL == 64) {
+    bitonic_stage<0, 32>(key, aux, lane);
+    bitonic_stage<0, 16>(key, aux, lane);
+    bitonic_stage<0, 8>(key, aux, lane);
+    bitonic_stage<0, 4>(key, aux, lane);
+    bitonic_stage<0, 2>(key, aux, lane);
+    bitonic_stage<0, 1>(key, aux, lane);
+  }
+}
+
+// Number of keys of the ascending array a[0..n) below k (n <= 64; keys past
+// n read as kNoKey).
+__device__ __forceinline__ int count_below(const uint64_t* a, int n, uint64_t k) {
+  int pos = 0;
+#pragma unroll
+  for (int step = 64; step >= 1; step >>= 1) {
+    const int probe = pos + step;
+    if (probe <= n && a[probe - 1] < k) pos = probe;
+  }
+  return pos;
+}
+
+// ---------------------------------------------------------------------------
+// Per-wave open-addressing set of point ids in LDS (kHashSlots entries,
+// -1 = empty), filled with LDS compare-and-swap; tag bits ride along.
+// ---------------------------------------------------------------------------
+constexpr int kHashSlots = 256;
+
+__device__ __forceinline__ int hash_slot(int id) {
+  return (int)(((uint32_t)id * 0x9E3779B1u) >> 24);
+}
+
+__device__ __forceinline__ void hash_clear(int* tab, int* tag) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < kHashSlots / kWave; ++k) {
+    tab[k * kWave + lane] = -1;
+    if (tag) tag[k * kWave + lane] = 0;
+  }
+  wave_lds_sync();
+}
+
+// Insert id (id >= 0); returns true if it was absent.  Lanes with id < 0 do
+// nothing and return false.  tag_bits (if a tag array is given) are OR-ed
+// into the slot's tag whether or not the id was new.
+__device__ __forceinline__ bool hash_insert(int* tab, int* tag, int id, int tag_bits) {
+  bool fresh = false;
+  if (id >= 0) {
+    int slot = hash_slot(id);
+    for (int probe = 0; probe < kHashSlots; ++probe) {
+      const int old = atomicCAS(&tab[slot], -1, id);
+      if (old == -1 || old == id) {
+        fresh = old == -1;
+        if (tag) atomicOr(&tag[slot], tag_bits);
+        break;
+      }
+      slot = (slot + 1) & (kHashSlots - 1);
+    }
+  }
+  wave_lds_sync();
+  return fresh;
+}
+
+// Tag of id in the set (0 if absent or id < 0).
+__device__ __forceinline__ int hash_find(const int* tab, const int* tag, int id) {
+  if (id < 0) return 0;
+  int slot = hash_slot(id);
+  for (int probe = 0; probe < kHashSlots; ++probe) {
+    const int v = tab[slot];
+    if (v == id) return tag ? tag[slot] : 1;
+    if (v == -1) return 0;
+    slot = (slot + 1) & (kHashSlots - 1);
+  }
+  return 0;
 }
 
 // True if v equals the value some lane k < n holds in x (n wave-uniform).
@@ -203,7 +356,8 @@ __device__ inline float4 calibrate_row(float d2, int K, const Hyper& h, float be
   if (!(beta > 0.0f && beta < 1e29f)) beta = (float)K / wave_sum_uniform(D);
   float lo = 0.0f, hi = __int_as_float(0x7f800000);
   for (int it = 0; it < 48; ++it) {
-    const float e = act ? expf(-beta * D) : 0.0f;
+    const float bl = beta * 1.44269504f;   // exp(-beta D) = 2^(-beta log2(e) D)
+    const float e = act ? exp2f(-bl * D) : 0.0f;
     const float S = wave_sum_uniform(e);
     const float T = wave_sum_uniform(e * D);
     const float U = wave_sum_uniform(e * D * D);

@@ -28,6 +28,8 @@ struct StepArgs {
   float* Zh;                // N
   float* zpart;             // kReduceBlocks
   int32_t* fpart;           // kReduceBlocks
+  uint32_t* cpart;          // 2 x kReduceBlocks: candidate-row counts (HD, LD)
+  uint8_t* ldc;             // N: LD candidate rows of each point in the last step
   float neg_scale;          // (N - 1) / n_neg
   int32_t hd_buf_host;      // HD buffer written by init / insert
   int32_t ld_buf_host;      // LD buffer written by init / insert

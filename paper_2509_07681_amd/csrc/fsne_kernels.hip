@@ -83,37 +83,66 @@ __device__ __forceinline__ RowGeom row_geom(int D, int VEC) {
 }
 
 // Squared distances from x_i to the rows whose ids lanes 0..nrows-1 hold in
-// cid (negative: skip).  Results go to sd2[0..nrows).
-template <typename TX, int VEC>
+// cid (negative: skip).  Results go to sd2[0..nrows).  CH bounds the vectors
+// per lane; x_i stays in registers and the loads of U passes are issued
+// before their reductions.
+template <typename TX, int VEC, int CH>
 __device__ void hd_dist_rows(const TX* __restrict__ X, int D, int32_t i, int cid, int nrows,
                              float* sd2) {
+  constexpr int U = CH >= 4 ? 1 : 4;
   const int lane = lane_id();
   const RowGeom geo = row_geom(D, VEC);
   const int g = lane >> geo.lg, sl = lane & (geo.G - 1);
   const int R = kWave >> geo.lg;
-  const TX* xi = X + (int64_t)i * D;
-  for (int p = 0; p < nrows; p += R) {
-    const int slot = p + g;
-    const int c = __shfl(cid, slot & (kWave - 1));
-    float acc = 0.0f;
-    if (slot < nrows && c >= 0) {
-      const TX* xc = X + (int64_t)c * D;
-      for (int k = 0; k < geo.chunks; ++k) {
-        const int e = (sl + k * geo.G) * VEC;
-        if (e < D) {
-          float a[VEC], b[VEC];
-          VecLoad<TX, VEC>::load(xi + e, a);
-          VecLoad<TX, VEC>::load(xc + e, b);
+  float xi[CH][VEC];
+  const TX* xr = X + (int64_t)i * D;
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) {
-            const float df = a[v] - b[v];
-            acc = fmaf(df, df, acc);
-          }
+  for (int k = 0; k < CH; ++k) {
+    const int e = (sl + k * geo.G) * VEC;
+    if (k < geo.chunks && e < D) {
+      VecLoad<TX, VEC>::load(xr + e, xi[k]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) xi[k][v] = 0.0f;
+    }
+  }
+  for (int p = 0; p < nrows; p += R * U) {
+    float acc[U];
+    float xc[U][CH][VEC];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int slot = p + u * R + g;
+      const int c = __shfl(cid, slot & (kWave - 1));
+      const bool ok = slot < nrows && c >= 0;
+      const TX* cr = X + (int64_t)(ok ? c : i) * D;
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int e = (sl + k * geo.G) * VEC;
+        if (k < geo.chunks && e < D) {
+          VecLoad<TX, VEC>::load(cr + e, xc[u][k]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) xc[u][k][v] = xi[k][v];
         }
       }
     }
-    for (int o = geo.G >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-    if (sl == 0 && slot < nrows) sd2[slot] = acc;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float s = 0.0f;
+#pragma unroll
+      for (int k = 0; k < CH; ++k)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const float df = xi[k][v] - xc[u][k][v];
+          s = fmaf(df, df, s);
+        }
+      acc[u] = group_sum_dpp(s, geo.G);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int slot = p + u * R + g;
+      if (sl == geo.G - 1 && slot < nrows) sd2[slot] = acc[u];
+    }
   }
   wave_lds_sync();
 }
@@ -133,7 +162,7 @@ __device__ void hd_dist_rows(const TX* __restrict__ X, int D, int32_t i, int cid
 __device__ __forceinline__ int make_candidate(int32_t i, uint32_t t, uint32_t stream,
                                               const Hyper& h, const int32_t* __restrict__ L,
                                               int K, int own, const int32_t* __restrict__ Lx,
-                                              int Kx, int other, int32_t N) {
+                                              int Kx, int other, int32_t N, int* tab) {
   const int lane = lane_id();
   const int s = lane & (kCand - 1);
   const uint4 u = philox((uint32_t)i, t, stream, (uint32_t)s, h.key0, h.key1);
@@ -152,9 +181,13 @@ __device__ __forceinline__ int make_candidate(int32_t i, uint32_t t, uint32_t st
     else
       c = draw_other(u.x, i, N);
   }
-  bool ok = lane < kCand && c != i && !in_lanes(c, own, K);
-  for (int k = 0; k < kCand; ++k) ok &= !(k < s && c == __builtin_amdgcn_readlane(c, k));
-  return ok ? c : -1;
+  // Duplicates go through a per-wave hash set: i's own list first, then the
+  // candidates; of several equal candidates exactly one is inserted.  The
+  // surviving set of ids is the one the earliest-slot rule keeps.
+  hash_clear(tab, nullptr);
+  hash_insert(tab, nullptr, lane < K ? own : -1, 0);
+  const bool fresh = hash_insert(tab, nullptr, (lane < kCand && c != i) ? c : -1, 0);
+  return fresh ? c : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -191,13 +224,16 @@ __device__ void random_list(int32_t i, int32_t N, int K, uint32_t stream, const 
 }
 
 struct WaveLds {
-  float key[2 * kWave];
-  int id[2 * kWave];
+  int2 key[2 * kWave];
   float d2[kWave];
+  float row[kWave];
   int lst[kWave];
+  int tab[kHashSlots];
+  uint64_t ck[kWave];
+  uint64_t ok[kWave];
 };
 
-template <typename TX, int VEC>
+template <typename TX, int VEC, int CH>
 __global__ __launch_bounds__(kBlock) void k_init_lists(const TX* __restrict__ X, int32_t N,
                                                        int32_t i0, int D, int Kh, int Kl,
                                                        Hyper h, int32_t* __restrict__ hd_idx,
@@ -215,11 +251,11 @@ __global__ __launch_bounds__(kBlock) void k_init_lists(const TX* __restrict__ X,
   wave_lds_sync();
   random_list(i, N, Kh, kStreamInitHD, h, S.lst);
   const int id = lane < Kh ? S.lst[lane] : -1;
-  hd_dist_rows<TX, VEC>(X, D, i, id, Kh, S.d2);
+  hd_dist_rows<TX, VEC, CH>(X, D, i, id, Kh, S.d2);
   const float dd = lane < Kh ? S.d2[lane] : kInf;
   const int ii = lane < Kh ? id : kNoId;
   int ra, rb;
-  rank_two(dd, ii, kInf, kNoId, Kh, 0, S.key, S.id, ra, rb);
+  rank_two(dd, ii, kInf, kNoId, Kh, 0, S.key, ra, rb);
   if (lane < Kh) {
     hd_idx[(int64_t)i * Kh + ra] = ii;
     hd_d2[(int64_t)i * Kh + ra] = dd;
@@ -239,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_init_lists(const TX* __restrict__ X,
 // HD lists and the LD lists of iteration t, their distances, merge into the
 // sorted list, flag, and recalibration of beta_i when the list changed.
 // ---------------------------------------------------------------------------
-template <typename TX, int VEC>
+template <typename TX, int VEC, int CH>
 __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
   const Scalars* sc = a.sc;
   if (!sc->fire) return;
@@ -257,30 +293,63 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
   const int own = lane < Kh ? hin[(int64_t)i * Kh + lane] : -1;
   const float od2 = lane < Kh ? din[(int64_t)i * Kh + lane] : kInf;
   const int oth = lane < Kl ? lin[(int64_t)i * Kl + lane] : -1;
-  const int c = make_candidate(i, t, kStreamHDC, a.h, hin, Kh, own, lin, Kl, oth, a.N);
-  hd_dist_rows<TX, VEC>(static_cast<const TX*>(a.X), a.D, i, c, kCand, S.d2);
-  const float cd2 = c >= 0 ? S.d2[lane & (kCand - 1)] : kInf;
-  int ro, rc;
-  rank_two(lane < Kh ? od2 : kInf, lane < Kh ? own : kNoId, cd2, c >= 0 ? c : kNoId, Kh,
-           kCand, S.key, S.id, ro, rc);
+  const int c = make_candidate(i, t, kStreamHDC, a.h, hin, Kh, own, lin, Kl, oth, a.N, S.tab);
+  hd_dist_rows<TX, VEC, CH>(static_cast<const TX*>(a.X), a.D, i, c, kCand, S.d2);
+  // sort the candidates by (distance, index), then rank old entries and
+  // candidates against each other by binary search
+  uint64_t ck = c >= 0 ? pack_key(S.d2[lane & (kCand - 1)], c) : kNoKey;
+  uint32_t aux = 0;
+  bitonic_sort<32>(ck, aux);
+  const int ncand = __popcll(__ballot(c >= 0));
+  const uint64_t ko = lane < Kh ? pack_key(od2, own) : kNoKey;
+  S.ck[lane] = ck;
+  S.ok[lane] = ko;
+  wave_lds_sync();
   int32_t* hout = a.hd_idx[cur ^ 1];
   float* dout = a.hd_d2[cur ^ 1];
-  if (lane < Kh && ro < Kh) {
-    hout[(int64_t)i * Kh + ro] = own;
-    dout[(int64_t)i * Kh + ro] = od2;
-    S.d2[ro] = od2;
+  // The stored list is ordered by this key, except after a state load whose
+  // order came from other arithmetic (equal FP32 distances); then sort it.
+  uint64_t ks = ko;
+  uint32_t below = (uint32_t)lane;     // old entries before this one
+  {
+    const uint32_t nlo = (uint32_t)__shfl_down((int)(uint32_t)ko, 1);
+    const uint32_t nhi = (uint32_t)__shfl_down((int)(uint32_t)(ko >> 32), 1);
+    const uint64_t next = ((uint64_t)nhi << 32) | nlo;
+    if (__ballot(lane + 1 < Kh && !(ko < next)) != 0ull) {
+      bitonic_sort<kWave>(ks, below);   // below: original lane of the sorted key
+      S.ok[lane] = ks;
+      wave_lds_sync();
+      const uint32_t src = below;
+      below = (uint32_t)lane;
+      // sorted position of this lane's own entry
+      for (int k = 0; k < Kh; ++k)
+        if (__builtin_amdgcn_readlane((int)src, k) == lane) below = (uint32_t)k;
+    }
   }
-  const bool enter = c >= 0 && rc < Kh;
-  if (enter) {
-    hout[(int64_t)i * Kh + rc] = c;
-    dout[(int64_t)i * Kh + rc] = cd2;
-    S.d2[rc] = cd2;
+  if (lane < Kh) {
+    const int ro = (int)below + count_below(S.ck, ncand, ko);
+    if (ro < Kh) {
+      hout[(int64_t)i * Kh + ro] = own;
+      dout[(int64_t)i * Kh + ro] = od2;
+      S.row[ro] = od2;
+    }
+  }
+  bool enter = false;
+  if (lane < ncand) {
+    const int rc = lane + count_below(S.ok, Kh, ck);
+    enter = rc < Kh;
+    if (enter) {
+      hout[(int64_t)i * Kh + rc] = key_id(ck);
+      dout[(int64_t)i * Kh + rc] = key_d2(ck);
+      S.row[rc] = key_d2(ck);
+    }
   }
   wave_lds_sync();
   const bool changed = __ballot(enter) != 0ull;
-  if (lane == 0) a.flags[i] = changed ? 1 : 0;
+  // bit 0: list changed; bits 1..6: candidate rows loaded (for measurement)
+  if (lane == 0) a.flags[i] = (uint8_t)((changed ? 1 : 0) | (ncand << 1));
   if (changed) {
-    const float sorted = lane < Kh ? S.d2[lane] : 0.0f;
+    const float sorted = lane < Kh ? S.row[lane] : 0.0f;
     const float4 r = calibrate_row(sorted, Kh, a.h, a.rec[i].x);
     if (lane == 0) a.rec[i] = r;
   }
@@ -380,7 +449,7 @@ __device__ __forceinline__ float ld_decision_d2(const float* yi, const float* yj
   float acc = 0.0f;
 #pragma unroll
   for (int k = 0; k < Geo::G; ++k) {
-    const float prev = Geo::G > 1 ? __shfl_up(acc, 1) : 0.0f;
+    const float prev = Geo::G > 1 ? dpp<0x111>(acc) : 0.0f;   // row_shr:1
     if (q == k) {
       float s = k == 0 ? 0.0f : prev;
 #pragma unroll
@@ -391,22 +460,34 @@ __device__ __forceinline__ float ld_decision_d2(const float* yi, const float* yj
   return acc;
 }
 
-// Sum over the G lanes of a row group (every lane of the group gets it).
+// Sum over the G lanes of a row group (G <= 16: every lane gets it).
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+  return group_sum_dpp(v, G);
+}
+
+// Sum over the lanes holding the same chunk (lane mod G): row rotations by
+// G, 2G, ... < 16 within each row, then the four rows.
+template <int G>
+__device__ __forceinline__ float strided_sum(float v) {
+  if constexpr (G <= 1) v += dpp<0x121>(v);   // row_ror:1
+  if constexpr (G <= 2) v += dpp<0x122>(v);   // row_ror:2
+  if constexpr (G <= 4) v += dpp<0x124>(v);   // row_ror:4
+  if constexpr (G <= 8) v += dpp<0x128>(v);   // row_ror:8
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
   return v;
 }
 
 struct LdLds {
-  int ent[2 * kWave];     // LD entries: old list, then candidate slots (-1: none)
+  int ent[2 * kWave];     // LD entries: candidate slots, then the old list (-1: none)
   float dd[2 * kWave];    // their decision distances
-  float key[2 * kWave];   // rank scratch
-  int id[2 * kWave];
+  int2 key[2 * kWave];    // rank scratch
   int newl[kWave];        // new LD list
   int kind[2 * kWave];    // 1: entry kept and not an HD neighbour
   int neg[kWave];         // negative samples outside U (-1: none)
+  int tab[kHashSlots];    // hash set of ids (candidate dedupe, then U)
+  int tag[kHashSlots];    // 1: HD neighbour, 2: new LD neighbour
 };
 
 // Adds one neighbour's contribution to this lane's components:
@@ -438,37 +519,82 @@ template <int DP>
 __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   using Geo = LdGeom<DP>;
   constexpr int VEC = Geo::VEC, G = Geo::G, RPI = Geo::RPI;
+  constexpr int LP = (kWave + RPI - 1) / RPI;   // passes over a list of <= 64 rows
+  constexpr bool PRE_H = LP * VEC <= 32;        // HD rows kept in registers
+  constexpr bool PRE_E = Geo::CACHE;            // entry rows kept in registers
   __shared__ LdLds lds_all[kWavesPerBlock];
   LdLds& S = lds_all[threadIdx.x / kWave];
   const int32_t i = (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   if (i >= a.N) return;
   const Scalars* sc = a.sc;
   const int lane = lane_id();
-  const int q = lane & (G - 1);          // chunk of the row this lane holds
+  const int q = lane & (G - 1);          // chunk of a row this lane holds
   const int rg = lane >> Geo::LG;        // row slot within a pass
   const uint32_t t = sc->t;
   const int hb = sc->hd_cur ^ sc->fire;  // HD lists after this iteration's HD phase
-  const int Kh = a.Kh, Kl = a.Kl;
+  const int Kh = a.Kh, Kl = a.Kl, nneg = a.h.n_neg;
+  const int ne = kCand + Kl;             // entries: candidate slots [0,32), old LD list after
   const int32_t* hl = a.hd_idx[hb];
   const int32_t* lin = a.ld_idx[t & 1];
   int32_t* lout = a.ld_idx[(t & 1) ^ 1];
-  const float* Y = a.Y;
+  const float* yrow = a.Y + q * VEC;     // chunk q of row j: yrow + j * DP
 
+  // Loads that do not depend on the candidates go out first: own row, lists,
+  // HD neighbour rows, old LD neighbour rows, negative sample rows.
   float yi[VEC];
-  load_chunk<VEC>(Y + (int64_t)i * DP + q * VEC, yi);
+  load_chunk<VEC>(yrow + (int64_t)i * DP, yi);
   const int hid = lane < Kh ? hl[(int64_t)i * Kh + lane] : -1;
   const float pk = lane < Kh ? a.P[(int64_t)i * Kh + lane] : 0.0f;
   const int lid = lane < Kl ? lin[(int64_t)i * Kl + lane] : -1;
-  const int c = make_candidate(i, t, kStreamLDC, a.h, lin, Kl, lid, hl, Kh, hid, a.N);
+  int jn = -1;
+  if (lane < nneg) {
+    const uint4 u = philox((uint32_t)i, t, kStreamNeg, (uint32_t)lane, a.h.key0, a.h.key1);
+    jn = draw_other(u.x, i, a.N);
+  }
+  float yh[PRE_H ? LP : 1][VEC];
+  float er[PRE_E ? Geo::MAXP : 1][VEC];
+  if constexpr (PRE_H) {
+#pragma unroll
+    for (int p = 0; p < LP; ++p) {
+      const int r = p * RPI + rg;
+      const int id = __shfl(hid, r & (kWave - 1));
+      if (p * RPI < Kh && r < Kh) load_chunk<VEC>(yrow + (int64_t)id * DP, yh[p]);
+    }
+  }
+  if constexpr (PRE_E) {
+#pragma unroll
+    for (int p = 0; p < Geo::MAXP; ++p) {
+      const int e = p * RPI + rg;
+      const int id = __shfl(lid, (e - kCand) & (kWave - 1));
+      if (p * RPI + RPI > kCand && e >= kCand && e < ne)
+        load_chunk<VEC>(yrow + (int64_t)id * DP, er[p]);
+    }
+  }
+  float yn[VEC];
+  {
+    const int id = __shfl(jn, rg & (kWave - 1));
+    if (nneg <= RPI && rg < nneg) load_chunk<VEC>(yrow + (int64_t)id * DP, yn);
+  }
 
-  // entry table: old LD list at [0, Kl), candidate slot s at Kl + s
-  const int ne = Kl + kCand;
-  if (lane < Kl) S.ent[lane] = lid;
-  if (lane < kCand) S.ent[Kl + lane] = c;
+  const int c = make_candidate(i, t, kStreamLDC, a.h, lin, Kl, lid, hl, Kh, hid, a.N, S.tab);
+  if (lane < kCand) S.ent[lane] = c;
+  if (lane < Kl) S.ent[kCand + lane] = lid;
+  {
+    const int nc = __popcll(__ballot(c >= 0));
+    if (lane == 0) a.ldc[i] = (uint8_t)nc;
+  }
+  if constexpr (PRE_E) {
+#pragma unroll
+    for (int p = 0; p < Geo::MAXP; ++p) {
+      const int e = p * RPI + rg;
+      const int id = __shfl(c, e & (kWave - 1));
+      if (p * RPI < kCand && e < kCand && id >= 0)
+        load_chunk<VEC>(yrow + (int64_t)id * DP, er[p]);
+    }
+  }
   wave_lds_sync();
 
-  // decision distances of the entries, rows kept in registers when they fit
-  float rows[Geo::CACHE ? Geo::MAXP : 1][VEC];
+  // decision distances of all entries
 #pragma unroll
   for (int p = 0; p < Geo::MAXP; ++p) {
     if (p * RPI < ne) {
@@ -477,55 +603,74 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
       float yj[VEC];
 #pragma unroll
       for (int v = 0; v < VEC; ++v) yj[v] = yi[v];
-      if (id >= 0) load_chunk<VEC>(Y + (int64_t)id * DP + q * VEC, yj);
+      if (id >= 0) {
+        if constexpr (PRE_E) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) yj[v] = er[p][v];
+        } else {
+          load_chunk<VEC>(yrow + (int64_t)id * DP, yj);
+        }
+      }
       const float dist = ld_decision_d2<DP>(yi, yj, q);
       if (q == G - 1 && e < ne) S.dd[e] = id >= 0 ? dist : kInf;
-      if constexpr (Geo::CACHE) {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) rows[p][v] = yj[v];
-      }
     }
   }
   wave_lds_sync();
 
-  // merge: rank of every entry by (distance, index); keep the first Kl
-  const int eA = lane, eB = kWave + lane;
-  const int idA = eA < ne ? S.ent[eA] : -1;
-  const int idB = eB < ne ? S.ent[eB] : -1;
-  const float dA = idA >= 0 ? S.dd[eA] : kInf;
-  const float dB = idB >= 0 ? S.dd[eB] : kInf;
-  int rA, rB;
-  rank_two(dA, idA >= 0 ? idA : kNoId, dB, idB >= 0 ? idB : kNoId, min(ne, kWave),
-           max(ne - kWave, 0), S.key, S.id, rA, rB);
-  const bool keepA = idA >= 0 && rA < Kl, keepB = idB >= 0 && rB < Kl;
-  if (keepA) {
-    lout[(int64_t)i * Kl + rA] = idA;
-    S.newl[rA] = idA;
-  }
-  if (keepB) {
-    lout[(int64_t)i * Kl + rB] = idB;
-    S.newl[rB] = idB;
-  }
-
-  // negatives: uniform other points, one per lane
-  const bool has_neg = lane < a.h.n_neg;
-  int jn = -1;
-  if (has_neg) {
-    const uint4 u = philox((uint32_t)i, t, kStreamNeg, (uint32_t)lane, a.h.key0, a.h.key1);
-    jn = draw_other(u.x, i, a.N);
-  }
-  bool a_hd = false, b_hd = false, n_in = false;
-  for (int k = 0; k < Kh; ++k) {
-    const int v = __builtin_amdgcn_readlane(hid, k);
-    a_hd |= (idA == v);
-    b_hd |= (idB == v);
-    n_in |= (jn == v);
+  // merge: order the entries by (distance, index) and keep the first Kl
+  bool keep = false;
+  int kid = -1;
+  if (ne <= kWave) {
+    const int e = lane;
+    const int id = e < ne ? S.ent[e] : -1;
+    uint64_t key = id >= 0 ? pack_key(S.dd[e], id) : kNoKey;
+    uint32_t slot = (uint32_t)e;
+    bitonic_sort<kWave>(key, slot);
+    S.kind[lane] = 0;
+    S.kind[kWave + lane] = 0;
+    keep = lane < Kl && key != kNoKey;
+    kid = keep ? key_id(key) : -1;
+    wave_lds_sync();
+    if (keep) {
+      lout[(int64_t)i * Kl + lane] = kid;
+      S.newl[lane] = kid;
+      S.kind[slot] = 2;   // kept; refined below
+    }
+  } else {
+    const int eA = lane, eB = kWave + lane;
+    const int idA = eA < ne ? S.ent[eA] : -1;
+    const int idB = eB < ne ? S.ent[eB] : -1;
+    const float dA = idA >= 0 ? S.dd[eA] : kInf;
+    const float dB = idB >= 0 ? S.dd[eB] : kInf;
+    int rA, rB;
+    rank_two(dA, idA >= 0 ? idA : kNoId, dB, idB >= 0 ? idB : kNoId, min(ne, kWave),
+             max(ne - kWave, 0), S.key, rA, rB);
+    const bool keepA = idA >= 0 && rA < Kl, keepB = idB >= 0 && rB < Kl;
+    S.kind[eA] = keepA ? 2 : 0;
+    S.kind[eB] = keepB ? 2 : 0;
+    if (keepA) {
+      lout[(int64_t)i * Kl + rA] = idA;
+      S.newl[rA] = idA;
+    }
+    if (keepB) {
+      lout[(int64_t)i * Kl + rB] = idB;
+      S.newl[rB] = idB;
+    }
+    wave_lds_sync();
+    keep = lane < Kl;
+    kid = keep ? S.newl[lane] : -1;
   }
   wave_lds_sync();
-  for (int k = 0; k < Kl; ++k) n_in |= (jn == S.newl[k]);
-  if (eA < ne) S.kind[eA] = (keepA && !a_hd) ? 1 : 0;
-  if (eB < ne) S.kind[eB] = (keepB && !b_hd) ? 1 : 0;
-  S.neg[lane] = (has_neg && !n_in) ? jn : -1;
+  // U = HD list + new LD list as a tagged hash set: LD entries that are HD
+  // neighbours too act once, as HD neighbours; negatives in U act not at all
+  hash_clear(S.tab, S.tag);
+  hash_insert(S.tab, S.tag, lane < Kh ? hid : -1, 1);
+  hash_insert(S.tab, S.tag, kid, 2);
+  for (int e = lane; e < ne; e += kWave) {
+    if (S.kind[e] == 2) S.kind[e] = (hash_find(S.tab, S.tag, S.ent[e]) & 1) ? 0 : 1;
+  }
+  const bool n_in = hash_find(S.tab, S.tag, jn) != 0;
+  S.neg[lane] = (lane < nneg && !n_in) ? jn : -1;
   wave_lds_sync();
 
   float A[VEC], R[VEC];
@@ -533,24 +678,34 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   for (int v = 0; v < VEC; ++v) A[v] = R[v] = 0.0f;
   float zh = 0.0f;
   // HD neighbours: attraction and repulsion
-  for (int b = 0; b < Kh; b += RPI) {
-    const int r = b + rg;
-    const int id = __shfl(hid, r & (kWave - 1));
-    const float pr = __shfl(pk, r & (kWave - 1));
-    float yj[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) yj[v] = yi[v];
-    if (r < Kh) load_chunk<VEC>(Y + (int64_t)id * DP + q * VEC, yj);
-    float part = 0.0f;
+  for (int p = 0; p < LP; ++p) {
+    if (p * RPI < Kh) {
+      const int r = p * RPI + rg;
+      const float pr = __shfl(pk, r & (kWave - 1));
+      float yj[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      const float dy = yi[v] - yj[v];
-      part = fmaf(dy, dy, part);
-    }
-    const float q2 = group_sum<G>(part);
-    if (r < Kh) {
-      const float z = pair_terms<VEC>(yi, yj, q2, a.h, pr, 1.0f, A, R);
-      if (q == 0) zh += z;
+      for (int v = 0; v < VEC; ++v) yj[v] = yi[v];
+      if constexpr (PRE_H) {
+        if (r < Kh) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) yj[v] = yh[p][v];
+        }
+      } else {
+        const int id = __shfl(hid, r & (kWave - 1));
+        if (r < Kh) load_chunk<VEC>(yrow + (int64_t)id * DP, yj);
+      }
+      float part = 0.0f;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const float dy = yi[v] - yj[v];
+        part = fmaf(dy, dy, part);
+      }
+      const float q2 = group_sum<G>(part);
+      if (r < Kh) {
+        const float z = pair_terms<VEC>(yi, yj, q2, a.h, pr, 1.0f, A, R);
+        if (q == 0) zh += z;
+      }
     }
   }
   // LD neighbours that are not HD neighbours: repulsion
@@ -560,11 +715,11 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
       const int e = p * RPI + rg;
       if (e < ne && S.kind[e]) {
         float yj[VEC];
-        if constexpr (Geo::CACHE) {
+        if constexpr (PRE_E) {
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) yj[v] = rows[p][v];
+          for (int v = 0; v < VEC; ++v) yj[v] = er[p][v];
         } else {
-          load_chunk<VEC>(Y + (int64_t)S.ent[e] * DP + q * VEC, yj);
+          load_chunk<VEC>(yrow + (int64_t)S.ent[e] * DP, yj);
         }
         const float z = pair_terms<VEC>(yi, yj, S.dd[e], a.h, 0.0f, 1.0f, A, R);
         if (q == 0) zh += z;
@@ -572,13 +727,20 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
     }
   }
   // negative samples outside U, weighted (N-1)/n_neg
-  for (int b = 0; b < a.h.n_neg; b += RPI) {
+  for (int b = 0; b < nneg; b += RPI) {
     const int r = b + rg;
-    const int id = r < a.h.n_neg ? S.neg[r] : -1;
+    const int id = r < nneg ? S.neg[r] : -1;
     float yj[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) yj[v] = yi[v];
-    if (id >= 0) load_chunk<VEC>(Y + (int64_t)id * DP + q * VEC, yj);
+    if (id >= 0) {
+      if (nneg <= RPI) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) yj[v] = yn[v];
+      } else {
+        load_chunk<VEC>(yrow + (int64_t)id * DP, yj);
+      }
+    }
     float part = 0.0f;
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
@@ -593,14 +755,11 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   }
   // sum over the row slots (lanes holding the same chunk), then store
 #pragma unroll
-  for (int o = G; o < kWave; o <<= 1) {
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      A[v] += __shfl_xor(A[v], o);
-      R[v] += __shfl_xor(R[v], o);
-    }
+  for (int v = 0; v < VEC; ++v) {
+    A[v] = strided_sum<G>(A[v]);
+    R[v] = strided_sum<G>(R[v]);
   }
-  zh = wave_sum(zh);
+  zh = wave_sum_uniform(zh);
   if (lane < G) {
     float* ao = a.A + (int64_t)i * DP + lane * VEC;
     float* ro = a.R + (int64_t)i * DP + lane * VEC;
@@ -622,6 +781,7 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
 __global__ __launch_bounds__(256) void k_reduce(StepArgs a) {
   __shared__ float sz[256];
   __shared__ int sf[256];
+  __shared__ uint32_t sh[256], sl[256];
   const int fire = a.sc->fire;
   const int64_t N = a.N;
   const int64_t chunk = (N + kReduceBlocks - 1) / kReduceBlocks;
@@ -629,23 +789,35 @@ __global__ __launch_bounds__(256) void k_reduce(StepArgs a) {
   const int64_t hi = lo + chunk < N ? lo + chunk : N;
   float z = 0.0f;
   int f = 0;
+  uint32_t ch = 0, cl = 0;
   for (int64_t k = lo + threadIdx.x; k < hi; k += 256) {
     z += a.Zh[k];
-    if (fire) f += a.flags[k];
+    if (fire) {
+      const uint32_t fl = a.flags[k];
+      f += (int)(fl & 1u);
+      ch += fl >> 1;
+    }
+    cl += a.ldc[k];
   }
   sz[threadIdx.x] = z;
   sf[threadIdx.x] = f;
+  sh[threadIdx.x] = ch;
+  sl[threadIdx.x] = cl;
   __syncthreads();
   for (int o = 128; o >= 1; o >>= 1) {
     if ((int)threadIdx.x < o) {
       sz[threadIdx.x] += sz[threadIdx.x + o];
       sf[threadIdx.x] += sf[threadIdx.x + o];
+      sh[threadIdx.x] += sh[threadIdx.x + o];
+      sl[threadIdx.x] += sl[threadIdx.x + o];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     a.zpart[blockIdx.x] = sz[0];
     a.fpart[blockIdx.x] = sf[0];
+    a.cpart[blockIdx.x] = sh[0];
+    a.cpart[kReduceBlocks + blockIdx.x] = sl[0];
   }
 }
 
@@ -688,17 +860,32 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a) {
   if (bad) sc->nonfinite = 1;
   if (blockIdx.x == 0) {
     __shared__ int sf[256];
+    __shared__ uint32_t sh[256], sl[256];
     const int fire = sc->fire;
     int f = 0;
-    if (fire)
-      for (int k = threadIdx.x; k < kReduceBlocks; k += 256) f += a.fpart[k];
+    uint32_t ch = 0, cl = 0;
+    for (int k = threadIdx.x; k < kReduceBlocks; k += 256) {
+      if (fire) {
+        f += a.fpart[k];
+        ch += a.cpart[k];
+      }
+      cl += a.cpart[kReduceBlocks + k];
+    }
     sf[threadIdx.x] = f;
+    sh[threadIdx.x] = ch;
+    sl[threadIdx.x] = cl;
     __syncthreads();
     for (int o = 128; o >= 1; o >>= 1) {
-      if ((int)threadIdx.x < o) sf[threadIdx.x] += sf[threadIdx.x + o];
+      if ((int)threadIdx.x < o) {
+        sf[threadIdx.x] += sf[threadIdx.x + o];
+        sh[threadIdx.x] += sh[threadIdx.x + o];
+        sl[threadIdx.x] += sl[threadIdx.x + o];
+      }
       __syncthreads();
     }
     if (threadIdx.x == 0) {
+      sc->hd_cand = sh[0];
+      sc->ld_cand = sl[0];
       const uint32_t t1 = sc->t + 1u;
       float E = sc->E;
       if (fire) {
@@ -746,7 +933,7 @@ __global__ __launch_bounds__(kBlock) void k_calibrate_all(StepArgs a) {
 // Drift: recompute every HD entry that pairs with a moved point (moved[] is
 // a per-point byte map), re-sort those rows, flag and recalibrate them.
 // ---------------------------------------------------------------------------
-template <typename TX, int VEC>
+template <typename TX, int VEC, int CH>
 __global__ __launch_bounds__(kBlock) void k_drift_rows(StepArgs a, const uint8_t* moved) {
   __shared__ WaveLds lds_all[kWavesPerBlock];
   WaveLds& S = lds_all[threadIdx.x / kWave];
@@ -765,10 +952,10 @@ __global__ __launch_bounds__(kBlock) void k_drift_rows(StepArgs a, const uint8_t
     if (lane == 0) a.flags[i] = 0;
     return;
   }
-  hd_dist_rows<TX, VEC>(static_cast<const TX*>(a.X), a.D, i, redo ? id : -1, Kh, S.d2);
+  hd_dist_rows<TX, VEC, CH>(static_cast<const TX*>(a.X), a.D, i, redo ? id : -1, Kh, S.d2);
   const float dd = lane < Kh ? (redo ? S.d2[lane] : old) : kInf;
   int ra, rb;
-  rank_two(dd, lane < Kh ? id : kNoId, kInf, kNoId, Kh, 0, S.key, S.id, ra, rb);
+  rank_two(dd, lane < Kh ? id : kNoId, kInf, kNoId, Kh, 0, S.key, ra, rb);
   if (lane < Kh) {
     hl[(int64_t)i * Kh + ra] = id;
     hd[(int64_t)i * Kh + ra] = dd;
@@ -790,21 +977,35 @@ static inline unsigned wave_blocks(int64_t n) {
   return (unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
-// Vector width: 16-byte loads when every row starts 16-byte aligned.
-template <template <typename, int> class F, typename... Args>
-static hipError_t dispatch_x(const StepArgs& a, Args&&... args) {
-  if (a.xdtype == 0) {
-    if (a.xvec_ok && a.D % 4 == 0) return F<float, 4>::run(a, args...);
-    return F<float, 1>::run(a, args...);
+// Vector width: 16-byte loads when every row starts 16-byte aligned; CH
+// bounds the vectors each lane holds (chunks = ceil(D / VEC / 64) when a row
+// takes the whole wave).
+template <template <typename, int, int> class F, typename TX, int VEC, typename... Args>
+static hipError_t dispatch_ch(int D, Args&&... args) {
+  const int V = (D + VEC - 1) / VEC;
+  const int chunks = V <= 64 ? 1 : (V + 63) / 64;
+  if (chunks <= 1) return F<TX, VEC, 1>::run(args...);
+  if (chunks <= 4) return F<TX, VEC, 4>::run(args...);
+  if constexpr (VEC * sizeof(TX) <= 4) {
+    if (chunks <= 16) return F<TX, VEC, 16>::run(args...);
   }
-  if (a.xvec_ok && a.D % 8 == 0) return F<uint16_t, 8>::run(a, args...);
-  return F<uint16_t, 1>::run(a, args...);
+  return hipErrorInvalidValue;
 }
 
-template <typename TX, int VEC>
+template <template <typename, int, int> class F, typename... Args>
+static hipError_t dispatch_x(const StepArgs& a, Args&&... args) {
+  if (a.xdtype == 0) {
+    if (a.xvec_ok && a.D % 4 == 0) return dispatch_ch<F, float, 4>(a.D, a, args...);
+    return dispatch_ch<F, float, 1>(a.D, a, args...);
+  }
+  if (a.xvec_ok && a.D % 8 == 0) return dispatch_ch<F, uint16_t, 8>(a.D, a, args...);
+  return dispatch_ch<F, uint16_t, 1>(a.D, a, args...);
+}
+
+template <typename TX, int VEC, int CH>
 struct InitLaunch {
   static hipError_t run(const StepArgs& a, int32_t i0, int32_t n, hipStream_t s) {
-    hipLaunchKernelGGL((k_init_lists<TX, VEC>), dim3(wave_blocks(n)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_init_lists<TX, VEC, CH>), dim3(wave_blocks(n)), dim3(kBlock), 0, s,
                        static_cast<const TX*>(a.X), i0 + n, i0, a.D, a.Kh, a.Kl, a.h,
                        a.hd_idx[a.hd_buf_host], a.hd_d2[a.hd_buf_host], a.ld_idx[a.ld_buf_host],
                        a.rec, a.flags);
@@ -812,18 +1013,18 @@ struct InitLaunch {
   }
 };
 
-template <typename TX, int VEC>
+template <typename TX, int VEC, int CH>
 struct RefineLaunch {
   static hipError_t run(const StepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_hd_refine<TX, VEC>), dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_hd_refine<TX, VEC, CH>), dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
   }
 };
 
-template <typename TX, int VEC>
+template <typename TX, int VEC, int CH>
 struct DriftLaunch {
   static hipError_t run(const StepArgs& a, const uint8_t* moved, hipStream_t s) {
-    hipLaunchKernelGGL((k_drift_rows<TX, VEC>), dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a,
+    hipLaunchKernelGGL((k_drift_rows<TX, VEC, CH>), dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a,
                        moved);
     return hipGetLastError();
   }
