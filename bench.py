@@ -125,7 +125,19 @@ def main():
     ap.add_argument("--queries", type=int, default=1000)
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device to device (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the step shards by point range; see the design notes).", file=sys.stderr)
@@ -224,18 +236,40 @@ def main():
         "ld_only_iters_per_s": round(1000.0 / ld_only_ms, 2),
     }
 
+    # the BF16 forms: step time with the HD refinement on
+    Xb = f32_to_bf16_bits(X)
+    forms = {}
+    for name, dm in (("bf16_rows_direct", 0), ("bf16_mfma_screen", 1)):
+        hpf = F.fsne_default_hparams(**{**hp.as_dict(), "dist_mode": dm})
+        e2 = F.Embedding(Xb, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hpf)
+        e2.step(args.warmup)
+        e2.profile(True)
+        nf = min(args.steps, 50)
+        e2.step(nf)
+        kt2 = e2.kernel_times()
+        e2.sync()
+        t2 = time.perf_counter()
+        e2.step(nf)
+        e2.sync()
+        ms2 = (time.perf_counter() - t2) * 1e3 / nf
+        e2.close()
+        forms[name] = {"ms_per_step": round(ms2, 4), "iters_per_s": round(1000.0 / ms2, 2),
+                       "hd_refine_ms": round(kt2["hd_refine"][0] / max(kt2["hd_refine"][1], 1), 4)}
+    out["forms"] = forms
+
     if not args.no_quality:
         from inputs.knn_metrics import exact_knn
 
         rng = np.random.default_rng(7)
         queries = rng.choice(N, args.queries, replace=False)
         _, ex_d2 = exact_knn(X, queries, cfg["K_hd"])
-        forms = {"f32": quality_run(F, X, cfg, Y0, args.quality_iters, RUN_SEED, queries, ex_d2)}
-        Xb = f32_to_bf16_bits(X)
+        runs = {"f32": quality_run(F, X, cfg, Y0, args.quality_iters, RUN_SEED, queries, ex_d2)}
         _, ex_b = exact_knn(Xb, queries, cfg["K_hd"])
-        forms["bf16_rows"] = quality_run(F, Xb, cfg, Y0, args.quality_iters, RUN_SEED, queries,
-                                         ex_b)
-        out["runs"] = forms
+        runs["bf16_rows_direct"] = quality_run(F, Xb, cfg, Y0, args.quality_iters, RUN_SEED,
+                                               queries, ex_b)
+        runs["bf16_mfma_screen"] = quality_run(F, Xb, cfg, Y0, args.quality_iters, RUN_SEED,
+                                               queries, ex_b, dist_mode=1)
+        out["runs"] = runs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, cfg, Y0, RUN_SEED)
     print(json.dumps(out))

@@ -133,7 +133,8 @@ StepArgs make_args(const fsne_ctx* c) {
   return a;
 }
 
-fsne_status check_hparams(fsne_ctx* c, const fsne_hparams* hp, int32_t Kh, int32_t xdtype) {
+fsne_status check_hparams(fsne_ctx* c, const fsne_hparams* hp, int32_t Kh, int32_t xdtype,
+                          int32_t D) {
   if (!hp) return fail(c, FSNE_EINVAL, "hparams is NULL");
   if (!(hp->alpha > 0.0f) || !std::isfinite(hp->alpha))
     return fail(c, FSNE_EINVAL, "alpha must be > 0");
@@ -149,8 +150,8 @@ fsne_status check_hparams(fsne_ctx* c, const fsne_hparams* hp, int32_t Kh, int32
   if (hp->hd_mode < 0 || hp->hd_mode > 2) return fail(c, FSNE_EINVAL, "hd_mode must be 0, 1, 2");
   if (hp->dist_mode < 0 || hp->dist_mode > 1)
     return fail(c, FSNE_EINVAL, "dist_mode must be 0 or 1");
-  if (hp->dist_mode == 1 && xdtype != FSNE_BF16)
-    return fail(c, FSNE_EINVAL, "dist_mode 1 needs BF16 X");
+  if (hp->dist_mode == 1 && (xdtype != FSNE_BF16 || D % 16 != 0))
+    return fail(c, FSNE_EINVAL, "dist_mode 1 needs BF16 X with D % 16 == 0");
   if (!(hp->e_smooth > 0.0f && hp->e_smooth <= 1.0f))
     return fail(c, FSNE_EINVAL, "e_smooth must be in (0, 1]");
   if (!(hp->p_min >= 0.0f && hp->p_min <= 1.0f))
@@ -407,7 +408,7 @@ fsne_status fsne_init(fsne_ctx** out, const void* X, int64_t N, int32_t D, int32
     h = *hp;
   else
     fsne_default_hparams(&h);
-  fsne_status st = check_hparams(c, &h, K_hd, xdtype);
+  fsne_status st = check_hparams(c, &h, K_hd, xdtype, D);
   if (st != FSNE_OK) {
     delete c;
     return st;
@@ -459,7 +460,7 @@ fsne_status fsne_step(fsne_ctx* c, int32_t n_iters) {
 
 fsne_status fsne_set_hyperparams(fsne_ctx* c, const fsne_hparams* hp) {
   if (!c) return FSNE_EINVAL;
-  TRY(check_hparams(c, hp, c->Kh, c->xdtype));
+  TRY(check_hparams(c, hp, c->Kh, c->xdtype, c->D));
   const bool perp_changed = hp->perplexity != c->hp.perplexity;
   c->hp = *hp;
   if (perp_changed) {

@@ -1,4 +1,4 @@
-// BF16 form of the HD candidate distances (MFMA screen + FP32 re-rank).
+// Squared norms of the BF16 rows (for the expanded-form screen of the BF16 form).
 #include "fsne_kernels.h"
 
 namespace fsne {
@@ -23,12 +23,6 @@ hipError_t launch_xnorm(const StepArgs& a, float* xnorm, int32_t i0, int32_t n, 
   hipLaunchKernelGGL(k_xnorm, dim3((unsigned)((n + kWavesPerBlock - 1) / kWavesPerBlock)),
                      dim3(kBlock), 0, s, static_cast<const uint16_t*>(a.X), a.D, i0, n, xnorm);
   return hipGetLastError();
-}
-
-hipError_t launch_hd_refine_bf16(const StepArgs& a, hipStream_t s) {
-  (void)a;
-  (void)s;
-  return hipErrorNotSupported;
 }
 
 }  // namespace fsne

@@ -270,12 +270,61 @@ __global__ __launch_bounds__(kBlock) void k_init_lists(const TX* __restrict__ X,
   }
 }
 
+// Moves the non-negative ids of lanes 0..31 to lanes 0..n-1 (in lane order)
+// and returns n; the other lanes get -1.
+__device__ __forceinline__ int compact_ids(int& c, int* scratch) {
+  const int lane = lane_id();
+  const uint64_t m = __ballot(c >= 0);
+  const int n = __popcll(m);
+  if (c >= 0) scratch[popc_below(m, lane)] = c;
+  wave_lds_sync();
+  c = lane < n ? scratch[lane] : -1;
+  wave_lds_sync();
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// BF16 screen of the candidates: dot products x_i . x_c on the matrix cores.
+// The 32 candidate rows are the A operand (32 x 16 per instruction, lane l
+// supplying row l mod 32, k = 8 (l / 32) .. +8), x_i is broadcast into every
+// column of B, so every column of C = A B holds the 32 dot products; lanes 0
+// and 32 hold column 0 (rows 4 (l/32) + 8 (r/4) + r mod 4 in register r).
+// Accumulation is FP32.  Returns the dot product of this lane's slot.
+// ---------------------------------------------------------------------------
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+__device__ __forceinline__ float screen_dots(const uint16_t* __restrict__ X, int D, int32_t i,
+                                             int c, float* sdot) {
+  const int lane = lane_id(), row = lane & (kCand - 1), half = lane >> 5;
+  const int cr = __shfl(c, row);
+  const uint16_t* ar = X + (int64_t)(cr >= 0 ? cr : i) * D + half * 8;
+  const uint16_t* br = X + (int64_t)i * D + half * 8;
+  f32x16_t acc = {};
+#pragma unroll 4
+  for (int k = 0; k < D; k += 16) {
+    uint4 av = make_uint4(0, 0, 0, 0);
+    if (cr >= 0) av = *reinterpret_cast<const uint4*>(ar + k);
+    const uint4 bv = *reinterpret_cast<const uint4*>(br + k);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av),
+                                                  __builtin_bit_cast(bf16x8_t, bv), acc, 0, 0, 0);
+  }
+  if (row == 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sdot[(r & 3) + 8 * (r >> 2) + 4 * half] = acc[r];
+  }
+  wave_lds_sync();
+  const float v = sdot[row];
+  wave_lds_sync();
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // HD refinement of point i (runs when the coin fired): candidates from the
 // HD lists and the LD lists of iteration t, their distances, merge into the
 // sorted list, flag, and recalibration of beta_i when the list changed.
 // ---------------------------------------------------------------------------
-template <typename TX, int VEC, int CH>
+template <typename TX, int VEC, int CH, bool SCREEN>
 __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
   const Scalars* sc = a.sc;
   if (!sc->fire) return;
@@ -293,14 +342,26 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
   const int own = lane < Kh ? hin[(int64_t)i * Kh + lane] : -1;
   const float od2 = lane < Kh ? din[(int64_t)i * Kh + lane] : kInf;
   const int oth = lane < Kl ? lin[(int64_t)i * Kl + lane] : -1;
-  const int c = make_candidate(i, t, kStreamHDC, a.h, hin, Kh, own, lin, Kl, oth, a.N, S.tab);
-  hd_dist_rows<TX, VEC, CH>(static_cast<const TX*>(a.X), a.D, i, c, kCand, S.d2);
+  // candidates, compacted into lanes 0 .. n-1 so that only n rows are visited
+  int c = make_candidate(i, t, kStreamHDC, a.h, hin, Kh, own, lin, Kl, oth, a.N, S.tab);
+  int n = compact_ids(c, S.lst);
+  const int nload = n;   // candidate rows read from X
+  if constexpr (SCREEN) {
+    // keep the candidates whose expanded-form distance
+    // |x_i|^2 + |x_c|^2 - 2 x_i.x_c is within the current K-th distance (1 + margin)
+    const float dot = screen_dots(static_cast<const uint16_t*>(a.X), a.D, i, c, S.d2);
+    const float r_i = readlane_f(od2, Kh - 1);
+    const float approx = a.xnorm[i] + (c >= 0 ? a.xnorm[c] : 0.0f) - 2.0f * dot;
+    c = (c >= 0 && approx <= r_i * (1.0f + a.h.margin)) ? c : -1;
+    n = compact_ids(c, S.lst);
+  }
+  hd_dist_rows<TX, VEC, CH>(static_cast<const TX*>(a.X), a.D, i, c, n, S.d2);
   // sort the candidates by (distance, index), then rank old entries and
   // candidates against each other by binary search
   uint64_t ck = c >= 0 ? pack_key(S.d2[lane & (kCand - 1)], c) : kNoKey;
   uint32_t aux = 0;
   bitonic_sort<32>(ck, aux);
-  const int ncand = __popcll(__ballot(c >= 0));
+  const int ncand = n;
   const uint64_t ko = lane < Kh ? pack_key(od2, own) : kNoKey;
   S.ck[lane] = ck;
   S.ok[lane] = ko;
@@ -347,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
   wave_lds_sync();
   const bool changed = __ballot(enter) != 0ull;
   // bit 0: list changed; bits 1..6: candidate rows loaded (for measurement)
-  if (lane == 0) a.flags[i] = (uint8_t)((changed ? 1 : 0) | (ncand << 1));
+  if (lane == 0) a.flags[i] = (uint8_t)((changed ? 1 : 0) | (nload << 1));
   if (changed) {
     const float sorted = lane < Kh ? S.row[lane] : 0.0f;
     const float4 r = calibrate_row(sorted, Kh, a.h, a.rec[i].x);
@@ -1016,10 +1077,26 @@ struct InitLaunch {
 template <typename TX, int VEC, int CH>
 struct RefineLaunch {
   static hipError_t run(const StepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_hd_refine<TX, VEC, CH>), dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_hd_refine<TX, VEC, CH, false>), dim3(wave_blocks(a.N)), dim3(kBlock),
+                       0, s, a);
     return hipGetLastError();
   }
 };
+
+// BF16 rows, D % 16 == 0 (checked by the host), 16-byte aligned.
+hipError_t launch_hd_refine_bf16(const StepArgs& a, hipStream_t s) {
+  if (a.xdtype != 1 || a.D % 16 != 0 || !a.xvec_ok) return hipErrorInvalidValue;
+  const int chunks = (a.D / 8 + 63) / 64;
+  if (chunks <= 1)
+    hipLaunchKernelGGL((k_hd_refine<uint16_t, 8, 1, true>), dim3(wave_blocks(a.N)), dim3(kBlock),
+                       0, s, a);
+  else if (chunks <= 4)
+    hipLaunchKernelGGL((k_hd_refine<uint16_t, 8, 4, true>), dim3(wave_blocks(a.N)), dim3(kBlock),
+                       0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 template <typename TX, int VEC, int CH>
 struct DriftLaunch {

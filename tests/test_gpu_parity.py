@@ -279,3 +279,43 @@ def test_insert_and_drift_match_oracle(oracle_lib, fsne_lib):
     clean = _clean_affinity(S, g["hd_idx"], same)
     assert rel_l2(g["P"][clean], S.live("P")[clean]) < 1e-4
     emb.close()
+
+
+@pytest.mark.parametrize("name", ["manifold_4003_bf16", "zipf_3000_bf16"])
+def test_bf16_screen_against_direct_and_oracle(oracle_lib, fsne_lib, name):
+    """BF16 form: MFMA expanded-form screen, FP32 direct re-rank of survivors.
+
+    From the same injected state the screened step equals the direct FP32
+    step on the same BF16 rows, except in rows where the screen dropped a
+    candidate that would have entered the list; those rows are counted and
+    must stay rare.  Stored distances are the direct FP32 ones, so they meet
+    the oracle's tie rule."""
+    O, F = oracle_lib, fsne_lib
+    X, c, S, direct, hp_o, hp_g = _setup(O, F, name, hd_mode=1)
+    hp_s = F.fsne_default_hparams(**{**hp_g.as_dict(), "dist_mode": 1})
+    screened = F.Embedding(X, y_init(X.shape[0], c["d"]), c["d"], c["K_hd"], c["K_ld"], seed=42,
+                           hp=hp_s)
+    lost_rows = 0
+    for it in range(4):
+        st0 = S.as_gpu_state()
+        direct.set_state(st0)
+        screened.set_state(st0)
+        S.step(hp_o)
+        direct.step(1)
+        screened.step(1)
+        gd, gs = direct.state(), screened.state()
+        differ = ~np.all(gd["hd_idx"] == gs["hd_idx"], axis=1)
+        for i in np.where(differ)[0]:
+            # the screened row is a valid list that misses candidates the direct row took
+            assert len(set(gs["hd_idx"][i].tolist())) == c["K_hd"]
+            assert np.all(gs["hd_d2"][i][-1] >= gd["hd_d2"][i][-1])
+        lost_rows += int(differ.sum())
+        same = ~differ
+        np.testing.assert_array_equal(gs["hd_d2"][same], gd["hd_d2"][same])  # same FP32 sums
+        tol = hd_tie_tol(X.shape[1], True)
+        _, nbad, bad = compare_hd_rows(X, gs["hd_idx"], S.live("hd_idx"), S.live("hd_d2"), tol,
+                                       rows=np.where(same)[0])
+        assert nbad == 0, bad[:5]
+    assert lost_rows <= 0.005 * 4 * X.shape[0], lost_rows
+    direct.close()
+    screened.close()
