@@ -205,6 +205,60 @@ fsne_status fsne_profile(fsne_ctx *ctx, int32_t enable);
  * Synchronises.  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_get_kernel_times(fsne_ctx *ctx, double *ms, int64_t *launches);
 
+/* ------------------------------------------------------------------------
+ * Placement network for dynamic data (Sec. 3 on online use, Sec. 5): a
+ * multilayer perceptron D -> hidden1 -> hidden2 -> d with ReLU hidden layers,
+ * fitted by mean squared error to the standardised embedding of a context
+ * (y - mean) / std per component, with Adam (Kingma and Ba 2015).  Its
+ * predictions initialise the y of inserted or drifted points (fsne_insert_points
+ * / fsne_drift_points take them as Yinit).  The three large products run on
+ * BF16 matrix cores with FP32 accumulation; weights are FP32.
+ * Parameters (fsne_mlp_get_params) are one flat FP32 array:
+ *   W1 (hidden1 x D), b1 (hidden1), W2 (hidden2 x hidden1), b2 (hidden2),
+ *   W3 (d x hidden2), b3 (d).
+ * ------------------------------------------------------------------------ */
+typedef struct fsne_mlp_opts {
+    int32_t hidden1, hidden2;  /* hidden widths (default 512, 512)               */
+    int32_t epochs;            /* passes over the context's points (default 5)   */
+    int32_t batch;             /* rows per Adam step (default 4096)              */
+    float lr, beta1, beta2, eps; /* Adam (default 1e-3, 0.9, 0.999, 1e-8)        */
+    uint64_t seed;             /* He-uniform initialisation draws (Philox)       */
+} fsne_mlp_opts;
+
+fsne_status fsne_mlp_default_opts(fsne_mlp_opts *opts);
+
+/* Create a network for ctx's D, d and input dtype, initialised He-uniform:
+ * w = (2u - 1) sqrt(6 / fan_in), u from Philox block (index, layer, 8, 0);
+ * biases 0; standardisation mean 0, std 1.  Errors: FSNE_EINVAL, FSNE_ENOMEM. */
+fsne_status fsne_mlp_create(const fsne_ctx *ctx, const fsne_mlp_opts *opts, fsne_mlp **out);
+
+/* Fit the network to ctx's current points (x_i, y_i), i < N: the
+ * standardisation is taken from ctx's Y, then opts.epochs passes of Adam
+ * steps over batches of opts.batch consecutive rows (epoch e starts at row
+ * 104729 e mod N).  *final_loss (may be NULL) gets the mean loss of the last
+ * epoch.  Synchronises ctx's stream first.  Errors: FSNE_EINVAL, FSNE_EHIP. */
+fsne_status fsne_mlp_train(fsne_mlp *m, fsne_ctx *ctx, float *final_loss);
+
+/* Predict y for n host rows X (the context's dtype) into host Y (n x d). */
+fsne_status fsne_mlp_predict(fsne_mlp *m, const void *X, int64_t n, float *Y);
+
+/* Copy parameters / standardisation out of or into host arrays (NULL skips). */
+fsne_status fsne_mlp_get_params(fsne_mlp *m, float *params, float *ymean, float *ystd);
+fsne_status fsne_mlp_set_params(fsne_mlp *m, const float *params, const float *ymean,
+                                const float *ystd);
+
+/* Loss 1/(n d) sum (out - T)^2 and its gradient (flat, host, num_params
+ * floats) for n <= batch host rows X with standardised targets T (n x d). */
+fsne_status fsne_mlp_loss_grad(fsne_mlp *m, const void *X, const float *T, int64_t n,
+                               float *grad, float *loss);
+
+/* One Adam step on n <= batch host rows X with standardised targets T. */
+fsne_status fsne_mlp_train_batch(fsne_mlp *m, const void *X, const float *T, int64_t n);
+
+int64_t fsne_mlp_num_params(const fsne_mlp *m);
+void fsne_mlp_destroy(fsne_mlp *m);
+const char *fsne_mlp_last_error(const fsne_mlp *m);
+
 /* Destroy the context and free its device memory (NULL is accepted). */
 void fsne_destroy(fsne_ctx *ctx);
 

@@ -24,10 +24,10 @@ def build_oracle(force: bool = True) -> str:
     """Compile the C oracle with gcc into oracle/liboracle_fsne.so."""
     if not force and os.path.exists(_LIB_PATH):
         return _LIB_PATH
-    src = os.path.join(_HERE, "fsne_oracle.c")
+    srcs = [os.path.join(_HERE, f) for f in ("fsne_oracle.c", "fsne_mlp_oracle.c")]
     tmp = _LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-Wall", "-shared",
-           "-fPIC", "-o", tmp, src, "-lm"]
+           "-fPIC", "-o", tmp, *srcs, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -48,6 +48,10 @@ class _Hp(C.Structure):
                 ("momentum", C.c_double), ("attr", C.c_double), ("rep", C.c_double),
                 ("n_neg", C.c_int32), ("hd_mode", C.c_int32), ("e_smooth", C.c_float),
                 ("p_min", C.c_float)]
+
+
+class _MlpDims(C.Structure):
+    _fields_ = [("D", C.c_int32), ("H1", C.c_int32), ("H2", C.c_int32), ("d", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -96,6 +100,16 @@ def lib():
         L.fsneo_drift.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P, C.c_int64, P]
         L.fsneo_drift.restype = C.c_int
         L.fsneo_num_threads.restype = C.c_int
+        L.fsneo_mlp_nparams.argtypes = [C.POINTER(_MlpDims)]
+        L.fsneo_mlp_nparams.restype = C.c_int64
+        L.fsneo_mlp_init.argtypes = [C.POINTER(_MlpDims), C.c_uint64, P]
+        L.fsneo_mlp_forward.argtypes = [C.POINTER(_MlpDims), P, P, C.c_int32, C.c_int64,
+                                        C.c_int32, P]
+        L.fsneo_mlp_loss_grad.argtypes = [C.POINTER(_MlpDims), P, P, C.c_int32, P, C.c_int64,
+                                          C.c_int32, P]
+        L.fsneo_mlp_loss_grad.restype = C.c_double
+        L.fsneo_mlp_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int64, C.c_double, C.c_double,
+                                     C.c_double, C.c_double]
         _lib = L
     return _lib
 
@@ -353,3 +367,50 @@ def knn_exact(X, queries, K):
     lib().fsneo_knn_exact(_p(X), xdt, X.shape[0], X.shape[1], _p(q), q.size, int(K), _p(idx),
                           _p(d2))
     return idx, d2
+
+
+# -- placement MLP ------------------------------------------------------------
+class Mlp:
+    """Oracle of the placement network D -> H1 -> H2 -> d (flat float32 params)."""
+
+    def __init__(self, D, H1, H2, d, seed=0):
+        self.dims = _MlpDims(D, H1, H2, d)
+        self.np = lib().fsneo_mlp_nparams(C.byref(self.dims))
+        self.params = np.zeros(self.np, dtype=np.float32)
+        lib().fsneo_mlp_init(C.byref(self.dims), int(seed), _p(self.params))
+        self.m = np.zeros(self.np)
+        self.v = np.zeros(self.np)
+        self.t = 0
+
+    def forward(self, X, bf16_ops=True):
+        X, xdt = _xprep(X)
+        out = np.zeros((X.shape[0], self.dims.d))
+        lib().fsneo_mlp_forward(C.byref(self.dims), _p(self.params), _p(X), xdt, X.shape[0],
+                                int(bf16_ops), _p(out))
+        return out
+
+    def loss_grad(self, X, T, bf16_ops=True):
+        X, xdt = _xprep(X)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        g = np.zeros(self.np)
+        loss = lib().fsneo_mlp_loss_grad(C.byref(self.dims), _p(self.params), _p(X), xdt, _p(T),
+                                         X.shape[0], int(bf16_ops), _p(g))
+        return loss, g
+
+    def adam(self, g, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.t += 1
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        lib().fsneo_mlp_adam(self.np, _p(self.params), _p(self.m), _p(self.v), _p(g), self.t,
+                             lr, b1, b2, eps)
+
+    def split(self, flat=None):
+        """Views W1, b1, W2, b2, W3, b3 of a flat parameter (or gradient) array."""
+        f = self.params if flat is None else flat
+        D, H1, H2, d = self.dims.D, self.dims.H1, self.dims.H2, self.dims.d
+        sizes = [(H1, D), (H1,), (H2, H1), (H2,), (d, H2), (d,)]
+        out, o = [], 0
+        for s in sizes:
+            n = int(np.prod(s))
+            out.append(f[o:o + n].reshape(s))
+            o += n
+        return out

@@ -15,41 +15,7 @@ using fsne::Hyper;
 using fsne::Scalars;
 using fsne::StepArgs;
 
-struct fsne_ctx {
-  int64_t N = 0, cap = 0;
-  int32_t D = 0, d = 0, DP = 0, Kh = 0, Kl = 0, xdtype = 0;
-  uint64_t seed = 0;
-  fsne_hparams hp{};
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  void* X = nullptr;
-  bool own_X = false;
-  float* xnorm = nullptr;
-  float *Y = nullptr, *V = nullptr, *A = nullptr, *R = nullptr, *Zh = nullptr, *P = nullptr;
-  float* zpart = nullptr;
-  int32_t* fpart = nullptr;
-  uint32_t* cpart = nullptr;
-  uint8_t* ldc = nullptr;
-  int32_t* hd_idx[2] = {nullptr, nullptr};
-  float* hd_d2[2] = {nullptr, nullptr};
-  int32_t* ld_idx[2] = {nullptr, nullptr};
-  float4* rec = nullptr;
-  uint8_t* flags = nullptr;
-  uint8_t* moved = nullptr;
-  Scalars* sc = nullptr;
-  std::string err;
-  std::vector<void*> owned;
-  // per-kernel timing (fsne_profile)
-  bool prof = false;
-  struct Timed {
-    int kernel;
-    hipEvent_t start, stop;
-  };
-  std::vector<Timed> pending;
-  std::vector<hipEvent_t> spare;
-  double ms[FSNE_NKERNELS] = {0};
-  int64_t launches[FSNE_NKERNELS] = {0};
-};
+#include "fsne_context.h"
 
 namespace {
 

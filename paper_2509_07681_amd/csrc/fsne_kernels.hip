@@ -301,7 +301,6 @@ __device__ __forceinline__ float screen_dots(const uint16_t* __restrict__ X, int
   const uint16_t* ar = X + (int64_t)(cr >= 0 ? cr : i) * D + half * 8;
   const uint16_t* br = X + (int64_t)i * D + half * 8;
   f32x16_t acc = {};
-#pragma unroll 4
   for (int k = 0; k < D; k += 16) {
     uint4 av = make_uint4(0, 0, 0, 0);
     if (cr >= 0) av = *reinterpret_cast<const uint4*>(ar + k);

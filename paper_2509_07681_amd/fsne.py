@@ -335,3 +335,113 @@ def fsne_get_kernel_times(ctx):
     n = np.zeros(FSNE_NKERNELS, dtype=np.int64)
     _check(ctx, L.fsne_get_kernel_times(ctx, _ptr(ms), _ptr(n)))
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+
+# -- placement network -----------------------------------------------------------
+class fsne_mlp_opts(C.Structure):
+    _fields_ = [("hidden1", C.c_int32), ("hidden2", C.c_int32), ("epochs", C.c_int32),
+                ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64)]
+
+
+def _mlp_lib():
+    L = load_library()
+    if not getattr(L, "_mlp_ready", False):
+        P, I64 = C.c_void_p, C.c_int64
+        L.fsne_mlp_default_opts.argtypes = [C.POINTER(fsne_mlp_opts)]
+        L.fsne_mlp_create.argtypes = [P, C.POINTER(fsne_mlp_opts), C.POINTER(P)]
+        L.fsne_mlp_train.argtypes = [P, P, P]
+        L.fsne_mlp_predict.argtypes = [P, P, I64, P]
+        L.fsne_mlp_get_params.argtypes = [P, P, P, P]
+        L.fsne_mlp_set_params.argtypes = [P, P, P, P]
+        L.fsne_mlp_loss_grad.argtypes = [P, P, P, I64, P, P]
+        L.fsne_mlp_train_batch.argtypes = [P, P, P, I64]
+        L.fsne_mlp_num_params.argtypes = [P]
+        L.fsne_mlp_num_params.restype = I64
+        L.fsne_mlp_destroy.argtypes = [P]
+        L.fsne_mlp_destroy.restype = None
+        L.fsne_mlp_last_error.argtypes = [P]
+        L.fsne_mlp_last_error.restype = C.c_char_p
+        for n in ("fsne_mlp_default_opts", "fsne_mlp_create", "fsne_mlp_train",
+                  "fsne_mlp_predict", "fsne_mlp_get_params", "fsne_mlp_set_params",
+                  "fsne_mlp_loss_grad", "fsne_mlp_train_batch"):
+            getattr(L, n).restype = C.c_int
+        L._mlp_ready = True
+    return L
+
+
+def _mcheck(m, st):
+    if st != FSNE_OK:
+        msg = _mlp_lib().fsne_mlp_last_error(m).decode() if m else "invalid argument"
+        raise FsneError(st, msg)
+
+
+def fsne_mlp_default_opts(**overrides) -> fsne_mlp_opts:
+    o = fsne_mlp_opts()
+    _mcheck(None, _mlp_lib().fsne_mlp_default_opts(C.byref(o)))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Mlp:
+    """Owner of one placement network (fsne_mlp_* entry points)."""
+
+    def __init__(self, emb, opts=None):
+        L = _mlp_lib()
+        self.m = C.c_void_p()
+        opts = opts or fsne_mlp_default_opts()
+        st = L.fsne_mlp_create(emb.ctx, C.byref(opts), C.byref(self.m))
+        if st != FSNE_OK:
+            raise FsneError(st, "fsne_mlp_create failed")
+        self.d = emb.d
+        self.np = L.fsne_mlp_num_params(self.m)
+
+    def train(self, emb):
+        loss = np.zeros(1, np.float32)
+        _mcheck(self.m, _mlp_lib().fsne_mlp_train(self.m, emb.ctx, _ptr(loss)))
+        return float(loss[0])
+
+    def predict(self, X):
+        X = np.ascontiguousarray(X)
+        Y = np.empty((X.shape[0], self.d), np.float32)
+        _mcheck(self.m, _mlp_lib().fsne_mlp_predict(self.m, _ptr(X), X.shape[0], _ptr(Y)))
+        return Y
+
+    def params(self):
+        p = np.empty(self.np, np.float32)
+        mu = np.empty(self.d, np.float32)
+        sd = np.empty(self.d, np.float32)
+        _mcheck(self.m, _mlp_lib().fsne_mlp_get_params(self.m, _ptr(p), _ptr(mu), _ptr(sd)))
+        return p, mu, sd
+
+    def set_params(self, p=None, mean=None, std=None):
+        a = [None if v is None else np.ascontiguousarray(v, np.float32) for v in (p, mean, std)]
+        _mcheck(self.m, _mlp_lib().fsne_mlp_set_params(self.m, *[_ptr(v) for v in a]))
+
+    def loss_grad(self, X, T):
+        X = np.ascontiguousarray(X)
+        T = np.ascontiguousarray(T, np.float32)
+        g = np.empty(self.np, np.float32)
+        loss = np.zeros(1, np.float32)
+        _mcheck(self.m, _mlp_lib().fsne_mlp_loss_grad(self.m, _ptr(X), _ptr(T), X.shape[0],
+                                                     _ptr(g), _ptr(loss)))
+        return float(loss[0]), g
+
+    def train_batch(self, X, T):
+        X = np.ascontiguousarray(X)
+        T = np.ascontiguousarray(T, np.float32)
+        _mcheck(self.m, _mlp_lib().fsne_mlp_train_batch(self.m, _ptr(X), _ptr(T), X.shape[0]))
+
+    def close(self):
+        if getattr(self, "m", None):
+            _mlp_lib().fsne_mlp_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
