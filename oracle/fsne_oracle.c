@@ -195,9 +195,10 @@ static int contains64(const int64_t *list, int n, int64_t v)
 /* set so that the entropy of p_{.|i}, restricted to the row's HD            */
 /* neighbours, equals ln(perplexity).  With e_k = exp(-beta (d2_k - m)):     */
 /*   H(beta) = ln S + beta sum_k p_k (d2_k - m),  p_k = e_k / S.             */
-/* H decreases strictly from ln K (beta = 0) to ln(#ties at the minimum), so */
-/* the root is unique; it is found by bracketing and bisection in double.    */
-/* When no root exists (too many ties at the minimum), beta = 1e30.          */
+/* H decreases strictly from ln K (beta = 0) towards ln(#ties at the        */
+/* minimum), so the root is unique; it is found by bracketing and bisection */
+/* in double.  With #ties >= perplexity H never reaches the target at a     */
+/* finite beta: then beta = 1e30 (the row is uniform over the ties).         */
 /* out = {beta, m, r, invS}.  Returns 1 when the row has no root.            */
 /* ------------------------------------------------------------------------ */
 static double row_entropy(const double *d2, int32_t K, double m, double beta, double *S_out)
@@ -210,6 +211,13 @@ static double row_entropy(const double *d2, int32_t K, double m, double beta, do
     }
     if (S_out) *S_out = S;
     return log(S) + beta * T / S;
+}
+
+static int32_t count_ties(const double *d2, int32_t K, double m)
+{
+    int32_t n = 0;
+    for (int32_t k = 0; k < K; ++k) n += d2[k] == m;
+    return n;
 }
 
 int fsneo_calibrate(const double *d2, int32_t K, double perplexity, double out[4])
@@ -226,7 +234,7 @@ int fsneo_calibrate(const double *d2, int32_t K, double perplexity, double out[4
     if (!(r > m)) {
         beta = 0.0; /* all distances equal: the row is uniform for every beta */
         noroot = !(log((double)K) <= target);
-    } else if (row_entropy(d2, K, m, beta_max, NULL) > target) {
+    } else if (count_ties(d2, K, m) >= perplexity) {
         beta = beta_max;
         noroot = 1;
     } else {

@@ -112,6 +112,16 @@ def test_calibration_degenerate_rows(oracle_lib):
     d2 = np.concatenate([np.zeros(8), np.linspace(1, 2, 8)])
     (beta, m, r, invS), noroot = O.calibrate(d2, 5.0)
     assert noroot and beta == 1e30 and abs(invS - 1 / 8) < 1e-15
+    # exactly perplexity-many ties: the entropy only reaches ln perp in the limit
+    d2 = np.concatenate([np.zeros(5), np.linspace(1, 2, 11)])
+    (beta, m, r, invS), noroot = O.calibrate(d2, 5.0)
+    assert noroot and beta == 1e30 and abs(invS - 1 / 5) < 1e-15
+    # one tie fewer: a finite root exists and hits the target entropy
+    d2 = np.concatenate([np.zeros(4), np.linspace(1e-3, 2, 12)])
+    (beta, m, r, invS), noroot = O.calibrate(d2, 5.0)
+    p = invS * np.exp(-beta * (d2 - m))
+    assert not noroot and beta < 1e30
+    assert abs(-(p[p > 0] * np.log(p[p > 0])).sum() - np.log(5.0)) < 1e-9
 
 
 # --- the method step with complete lists equals the exact gradient ----------
