@@ -230,7 +230,8 @@ def main():
                    "K_ld": cfg["K_ld"], "n_neg": cfg["n_neg"], "hd_mode": "always"},
         "roofline": {"bound": "hbm", "kernel": "hd_refine", "achieved": dom["GBps"],
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": dom["frac"],
-                     "traffic": traffic},
+                     "traffic": traffic, "traffic_unit": "GB per launch (FETCH_SIZE x2.0 "
+                     "+ WRITE_SIZE x1.0, copy-calibrated)"},
         "kernels": kernels,
         "ld_only_ms_per_step": round(ld_only_ms, 4),
         "ld_only_iters_per_s": round(1000.0 / ld_only_ms, 2),
