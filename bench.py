@@ -72,7 +72,10 @@ def schedule(F, base, t):
                                      "momentum": 0.5 if early else 0.8})
 
 
-def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0):
+def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=100):
+    """n_iter iterations under the coin with the standard schedule; HD recall@K
+    on the query sample every ``every`` iterations (the clock is stopped while
+    the recall is measured)."""
     from inputs.knn_metrics import recall_at_k
 
     N = X.shape[0]
@@ -81,22 +84,33 @@ def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0):
     emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=seed,
                       hp=schedule(F, base, 0))
     emb.sync()
-    t0 = time.perf_counter()
-    done, fires = 0, 0
+    done, secs, curve = 0, 0.0, []
     while done < n_iter:
-        n = min(250 - done, n_iter - done) if done < 250 else n_iter - done
+        stop = min(n_iter, (done // every + 1) * every)
+        if done < 250 < stop:
+            stop = 250
         emb.set_hyperparams(schedule(F, base, done))
-        emb.step(n)
-        done += n
-    emb.sync()
-    secs = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        emb.step(stop - done)
+        emb.sync()
+        secs += time.perf_counter() - t0
+        done = stop
+        if done % every == 0 or done == n_iter:
+            idx, _ = emb.knn(0)
+            curve.append([done, round(secs, 4), round(recall_at_k(idx, X, queries, ex_d2), 4)])
     st = emb.stats()
-    idx, _ = emb.knn(0)
-    rec = recall_at_k(idx, X, queries, ex_d2)
     emb.close()
     return dict(iters=n_iter, seconds=round(secs, 3), iters_per_s=round(n_iter / secs, 2),
-                recall_at_32=round(rec, 4), final_E=round(float(st["E"]), 4),
-                nonfinite=int(st["nonfinite"]))
+                recall_at_32=curve[-1][2], final_E=round(float(st["E"]), 4),
+                nonfinite=int(st["nonfinite"]), curve=curve)
+
+
+def seconds_to(curve, target):
+    """Step seconds at the first checkpoint whose recall reaches target (None if never)."""
+    for it, secs, rec in curve:
+        if rec >= target:
+            return secs
+    return None
 
 
 def cpu_baseline(X, cfg, Y0, seed):
@@ -116,6 +130,185 @@ def cpu_baseline(X, cfg, Y0, seed):
                       f"oracle init; {dt:.2f} s"}
 
 
+def mlp_flops(D, H1, H2, d, n):
+    """Multiply-add flops of one training pass over n rows: the forward pass,
+    the weight gradients of all three layers and the input gradients of the
+    two upper layers."""
+    fwd = 2 * n * (D * H1 + H1 * H2 + H2 * d)
+    bwd = 2 * n * (D * H1 + 2 * H1 * H2 + 2 * H2 * d)
+    return fwd + bwd
+
+
+def dynamic_run(F, args):
+    """Online use with learned placement.
+
+    A 500,000-point image-like set is embedded in 2-D (250 iterations with
+    attraction 12 and momentum 0.5, then attraction 1 and momentum 0.8), the
+    placement network 784-512-512-2 is trained on its (x, y) pairs, and then
+    batches of 50,000 new points arrive while 1 % of the live points drift
+    (their x is redrawn from a uniformly chosen class).  Two tracks start from
+    the same base state: in one the network places the new and drifted points,
+    in the other new points start at N(0, 1e-4) and drifted points keep their
+    y.  After each batch the step runs in chunks of 10 iterations until the LD
+    neighbour recall of a sample of the batch's new points (the fraction of
+    their exact 32 HD neighbours among their exact 32 LD neighbours) reaches
+    0.9 times the base points' value, or a cap.  Reported per batch and in
+    total: iterations and step seconds (evaluation excluded)."""
+    import numpy as np
+    import torch
+
+    from inputs.generators import CONFIGS, RUN_SEED, image_like, image_styles, y_init
+    from inputs.knn_metrics import knn_on_device, set_recall
+
+    cfg = CONFIGS["dynamic_500k"]
+    proto = CONFIGS["image_70k"]["data_seed"]
+
+    def rows(classes, seed):
+        if args.dyn_data == "styles":
+            return image_styles(classes, seed=seed, proto_seed=proto)
+        return image_like(classes=classes, seed=seed, proto_seed=proto)
+
+    N0 = args.dyn_base if args.dyn_base else cfg["N"]
+    nb, bs, dfrac = args.dyn_batches, cfg["batch_size"], cfg["drift_frac"]
+    if args.dyn_base:
+        bs = max(1000, N0 // 10)
+    K, d = cfg["K_ld"], cfg["d"]
+    cap = N0 + nb * bs
+    rng = np.random.default_rng(cfg["data_seed"] + 11)
+    t_gen = time.perf_counter()
+    Xb, lab0 = rows(rng.permutation(np.arange(N0) % 10), cfg["data_seed"])
+    labels = np.zeros(cap, np.int32)
+    labels[:N0] = lab0
+    batches, n_live = [], N0
+    for b in range(nb):
+        Xn, ln = rows(rng.integers(0, 10, bs), cfg["data_seed"] + 100 + b)
+        nd = int(round(dfrac * n_live))
+        ids = np.sort(rng.choice(n_live, nd, replace=False)).astype(np.int64)
+        Xd, ld = rows(rng.integers(0, 10, nd), cfg["data_seed"] + 200 + b)
+        sample = n_live + np.sort(rng.choice(bs, min(1000, bs), replace=False))
+        labels[n_live:n_live + bs] = ln
+        labels[ids] = ld
+        batches.append((Xn, ids, Xd, sample, labels[:n_live + bs].copy()))
+        n_live += bs
+    t_gen = time.perf_counter() - t_gen
+
+    dev = torch.device("cuda")
+    # lr = N/48: in 2-D without per-parameter gains, N/12 lets the sampled
+    # far-field repulsion diffuse points out of their classes at this size
+    hp = F.fsne_default_hparams(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=N0 / 48.0,
+                                momentum=0.5, attr=12.0, n_neg=cfg["n_neg"], hd_mode=0)
+    hp2 = F.fsne_default_hparams(**{**hp.as_dict(), "attr": 1.0, "momentum": 0.8})
+    base = F.Embedding(Xb, y_init(N0, d), d, cfg["K_hd"], K, seed=RUN_SEED, hp=hp,
+                       capacity=cap)
+    base.sync()
+    t0 = time.perf_counter()
+    base.step(250)
+    base.set_hyperparams(hp2)
+    base.step(args.dyn_base_iters - 250)
+    base.sync()
+    t_base = time.perf_counter() - t0
+    snap = {k: v for k, v in base.state().items() if k not in ("A", "R", "Zh")}
+    Ybase = base.Y()
+
+    net = F.Mlp(base, F.fsne_mlp_default_opts())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = net.train(base)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    o = F.fsne_mlp_default_opts()
+    flops = o.epochs * mlp_flops(Xb.shape[1], o.hidden1, o.hidden2, d, N0)
+
+    Xlive = torch.zeros((cap, Xb.shape[1]), dtype=torch.float32, device=dev)
+    Xlive[:N0] = torch.from_numpy(Xb).to(dev)
+    rows_b = np.sort(rng.choice(N0, 1000, replace=False))
+    hd_b = knn_on_device(Xlive[:N0], rows_b, K)
+    ld_b = knn_on_device(torch.from_numpy(Ybase).to(dev), rows_b, K, direct=True)
+    base_recall = set_recall(hd_b, ld_b)
+    base_class = float((lab0[ld_b] == lab0[rows_b][:, None]).mean())
+    target = 0.9 * base_recall
+    truth, n_live = [], N0
+    for Xn, ids, Xd, sample, _ in batches:
+        Xlive[n_live:n_live + bs] = torch.from_numpy(Xn).to(dev)
+        Xlive[torch.from_numpy(ids).to(dev)] = torch.from_numpy(Xd).to(dev)
+        n_live += bs
+        truth.append(knn_on_device(Xlive[:n_live], sample, K))
+    del Xlive
+    torch.cuda.empty_cache()
+
+    tracks = {}
+    for mode in ("mlp", "random"):
+        emb = F.Embedding(Xb, Ybase, d, cfg["K_hd"], K, seed=RUN_SEED, hp=hp2, capacity=cap)
+        emb.set_state(snap)
+        res = []
+        if mode == "mlp":
+            # one more epoch on the live points before each batch keeps the
+            # network in step with the embedding as it moves
+            ft = F.Mlp(emb, F.fsne_mlp_default_opts(epochs=1))
+            ft.set_params(*net.params())
+        for b, (Xn, ids, Xd, sample, lab) in enumerate(batches):
+            place = 0.0
+            if mode == "mlp":
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if b > 0:
+                    ft.train(emb)
+                Yn, Ydr = ft.predict(Xn), ft.predict(Xd)
+                torch.cuda.synchronize()
+                place = time.perf_counter() - t0
+                emb.insert(Xn, Yn)
+                emb.drift(ids, Xd, Ydr)
+            else:
+                emb.insert(Xn, y_init(bs, d, seed=RUN_SEED + 1000 + b))
+                emb.drift(ids, Xd, None)
+            it, secs, r0, r, c0 = 0, 0.0, None, 0.0, None
+            while True:
+                Yd = torch.from_numpy(emb.Y()).to(dev)
+                ld_nn = knn_on_device(Yd, sample, K, direct=True)
+                r = set_recall(truth[b], ld_nn)
+                cls = float((lab[ld_nn] == lab[sample][:, None]).mean())
+                if r0 is None:
+                    r0, c0 = r, cls
+                if r >= target or it >= args.dyn_cap:
+                    break
+                emb.sync()
+                t0 = time.perf_counter()
+                emb.step(10)
+                emb.sync()
+                secs += time.perf_counter() - t0
+                it += 10
+            res.append({"batch": b, "reached": bool(r >= target), "iters": it,
+                        "seconds": round(secs, 4), "placement_seconds": round(place, 4),
+                        "recall_at_placement": round(r0, 4),
+                        "recall_final": round(r, 4), "same_class_at_placement": round(c0, 4),
+                        "same_class_final": round(cls, 4)})
+        st = emb.stats()
+        if mode == "mlp":
+            ft.close()
+        tracks[mode] = {"batches": res, "total_iters": sum(x["iters"] for x in res),
+                        "total_seconds": round(sum(x["seconds"] for x in res), 3),
+                        "total_placement_seconds": round(sum(x["placement_seconds"] for x in res), 3),
+                        "all_reached": all(x["reached"] for x in res),
+                        "nonfinite": int(st["nonfinite"])}
+        emb.close()
+    net.close()
+    base.close()
+    out = {"metric": "dynamic placement: iterations and seconds to LD recall target, "
+                     "network vs random placement",
+           "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"{args.dyn_data} image-like 784-dim rows, base N={N0}, {nb} "
+                                  f"batches of {bs} new points + {dfrac:.0%} drift, d={d}, K={K}",
+                      "base_iters": args.dyn_base_iters, "cap_iters": args.dyn_cap},
+           "data_gen_seconds": round(t_gen, 1), "base_seconds": round(t_base, 3),
+           "mlp_train": {"seconds": round(t_train, 3), "final_loss": round(loss, 5),
+                         "flops": flops, "TFLOPps": round(flops / t_train / 1e12, 2),
+                         "peak_bf16_TFLOPps": 2500.0},
+           "base_ld_recall": round(base_recall, 4), "base_same_class": round(base_class, 4),
+           "target": round(target, 4),
+           "tracks": tracks}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +320,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device to device (counter calibration)")
+    ap.add_argument("--no-dynamic", action="store_true", help="skip the online-use experiment")
+    ap.add_argument("--dynamic", action="store_true",
+                    help="run the online-use experiment (learned vs random placement) instead")
+    ap.add_argument("--dyn-base", type=int, default=0, help="base points (0: 500,000)")
+    ap.add_argument("--dyn-batches", type=int, default=10)
+    ap.add_argument("--dyn-base-iters", type=int, default=2000)
+    ap.add_argument("--dyn-cap", type=int, default=1000)
+    ap.add_argument("--dyn-data", choices=("styles", "image"), default="styles",
+                    help="styles: classes with a 3-dim style manifold; image: independent "
+                         "pixel drops and jitter within a class")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -154,6 +357,9 @@ def main():
 
         __graft_entry__.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.dynamic:
+        print(json.dumps(dynamic_run(F, args)))
+        return
 
     X, _, cfg = make_workload("manifold_1m")
     N = X.shape[0]
@@ -270,7 +476,14 @@ def main():
                                                queries, ex_b)
         runs["bf16_mfma_screen"] = quality_run(F, Xb, cfg, Y0, args.quality_iters, RUN_SEED,
                                                queries, ex_b, dist_mode=1)
+        # seconds for each form to reach 0.95 of the FP32 form's final recall
+        target = round(0.95 * runs["f32"]["recall_at_32"], 4)
+        for r in runs.values():
+            r["seconds_to_target"] = seconds_to(r["curve"], target)
         out["runs"] = runs
+        out["runs_recall_target"] = target
+    if not args.no_dynamic:
+        out["dynamic"] = dynamic_run(F, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, cfg, Y0, RUN_SEED)
     print(json.dumps(out))

@@ -23,6 +23,7 @@ __all__ = [
     "blobs",
     "image_like",
     "image_like_prototypes",
+    "image_styles",
     "manifolds",
     "zipf_mixture",
     "y_init",
@@ -104,6 +105,34 @@ def image_like(n_per_class: int = 7000, n_classes: int = 10, D: int = 784,
     if classes is None:
         X, lab = _shuffle(rng, X, lab.astype(np.int32))
     return np.ascontiguousarray(X), lab.astype(np.int32)
+
+
+def image_styles(classes: np.ndarray, seed: int, proto_seed: int = 1002, D: int = 784,
+                 k: int = 3, amp: float = 0.15, jitter: float = 0.03):
+    """Image-like rows with smooth within-class variation (a "style" manifold).
+
+    Class c has the prototype of ``image_like_prototypes`` and a style basis
+    S_c (D x k, N(0, amp^2) entries on the prototype's on-pixels, 0 elsewhere);
+    a row of class c is x = clip(pi_c + S_c z + N(0, jitter^2), 0, 1) on the
+    on-pixels, exactly 0 off them (about 80% zeros), with z ~ N(0, I_k).
+    Unlike ``image_like``, whose within-class differences are independent
+    pixel drops and jitter, neighbours here follow a k-dimensional structure.
+    """
+    proto = image_like_prototypes(10, D, seed=proto_seed)
+    on = proto > 0
+    brng = np.random.Generator(np.random.PCG64(proto_seed + 31))
+    S = brng.normal(0.0, amp, size=(10, D, k)) * on[:, :, None]
+    lab = np.asarray(classes, dtype=np.int64)
+    rng = np.random.Generator(np.random.PCG64(seed + 4973))
+    z = rng.normal(size=(lab.size, k))
+    X = np.empty((lab.size, D), dtype=np.float32)
+    for c in range(10):
+        rows = np.nonzero(lab == c)[0]
+        for s0 in range(0, rows.size, 65536):
+            r = rows[s0:s0 + 65536]
+            x = proto[c] + z[r] @ S[c].T + rng.normal(0.0, jitter, size=(r.size, D))
+            X[r] = np.where(on[c], np.clip(x, 0.0, 1.0), 0.0)
+    return X, lab.astype(np.int32)
 
 
 def manifolds(n_manifolds: int = 50, per_manifold: int = 20000, D: int = 128,

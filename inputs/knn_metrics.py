@@ -53,3 +53,37 @@ def recall_at_k(lists, X, queries, exact_d2, rel_tie=1e-6):
         d = ((Xf[lst].astype(np.float64) - Xf[i].astype(np.float64)) ** 2).sum(1)
         hits += int(np.sum(d <= exact_d2[r, K - 1] * (1.0 + rel_tie)))
     return hits / (q.size * K)
+
+
+def knn_on_device(Xd, queries, K, chunk=256, direct=False):
+    """K nearest neighbours (self excluded) of rows ``queries`` among all rows
+    of the float32 device tensor ``Xd``, by brute force on the device; for
+    recall measurements at sizes where the CPU brute force is too slow.
+
+    ``direct`` sums squared coordinate differences (use for low-dimensional
+    embeddings far from the origin); otherwise the expanded form
+    |q|^2 + |x|^2 - 2 q.x is used.  Returns an int64 numpy array (nq, K).
+    """
+    import torch
+
+    q = torch.as_tensor(np.asarray(queries, dtype=np.int64), device=Xd.device)
+    nrm = None if direct else (Xd * Xd).sum(1)
+    out = []
+    for s in range(0, q.numel(), chunk):
+        qq = q[s:s + chunk]
+        if direct:
+            Q = Xd[qq]
+            d = torch.zeros((qq.numel(), Xd.shape[0]), dtype=torch.float32, device=Xd.device)
+            for c in range(Xd.shape[1]):
+                d += (Xd[None, :, c] - Q[:, c, None]) ** 2
+        else:
+            d = nrm[qq][:, None] + nrm[None, :] - 2.0 * (Xd[qq] @ Xd.T)
+        d[torch.arange(qq.numel(), device=Xd.device), qq] = float("inf")
+        out.append(torch.topk(d, K, dim=1, largest=False).indices.cpu())
+    return torch.cat(out).numpy()
+
+
+def set_recall(a, b):
+    """Mean over rows of |a_r ∩ b_r| / K for two (n, K) index arrays."""
+    K = a.shape[1]
+    return float(np.mean([len(set(x.tolist()) & set(y.tolist())) / K for x, y in zip(a, b)]))

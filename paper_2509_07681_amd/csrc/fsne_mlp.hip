@@ -26,6 +26,8 @@ struct fsne_mlp {
   float *Xb = nullptr, *Tb = nullptr, *H1b = nullptr, *H2b = nullptr; // batch buffers
   float *Ob = nullptr, *dOb = nullptr, *dH1 = nullptr, *dH2 = nullptr;
   float* lpart = nullptr;      // loss partial sums
+  float* ws = nullptr;         // split-K partial products
+  float* part = nullptr;       // row-chunk partial sums (bias and output-layer gradients)
   void* xstage = nullptr;      // host-batch staging (input dtype)
   std::string err;
 };
@@ -35,6 +37,9 @@ namespace {
 using namespace fsne;
 
 constexpr int kBM = 64, kBN = 64, kBK = 32, kLDP = kBK + 8;
+constexpr int kTM = 64, kTN = 64, kTK = 64, kTP = kTK + 8;   // vector-staged tiles
+constexpr int kMaxSplit = 8;      // split-K factor limit of the weight-gradient products
+constexpr int kRowChunk = 64;     // rows per partial sum of the column reductions
 constexpr int kLossBlocks = 256;
 enum { kEpiBias = 1, kEpiRelu = 2, kEpiMask = 4 };
 
@@ -53,6 +58,8 @@ struct GemmArgs {
   const float* mask;       // C(m, n) = 0 where mask[m ldm + n] <= 0
   int64_t ldm;
   int epi;
+  float* ws;               // split-K: partial C of split z at ws + z M N (row stride N)
+  int kchunk;              // split-K: K range of one split (a multiple of kTK)
 };
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -107,12 +114,172 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   }
 }
 
+// Four consecutive elements p[0..3] of an operand along its contiguous index,
+// which starts at c; elements at or beyond lim read as 0.
+__device__ __forceinline__ float4 load4(const float* p, int c, int lim) {
+  if (c + 3 < lim) return *reinterpret_cast<const float4*>(p);
+  float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (c < lim) v.x = p[0];
+  if (c + 1 < lim) v.y = p[1];
+  if (c + 2 < lim) v.z = p[2];
+  return v;
+}
+
+__device__ __forceinline__ uint2 pack4_bf16(float4 v) {
+  return make_uint2((uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16),
+                    (uint32_t)to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16));
+}
+
+// One 64 x 64 FP32 tile of an operand as 4 float4 per thread.  KC: the
+// operand is contiguous along k (rows r of the tile are its m or n index);
+// otherwise it is contiguous along m / n.
+template <bool KC>
+__device__ __forceinline__ void tile_load(const float* __restrict__ P, int64_t s_r, int64_t s_k,
+                                          int r0, int rlim, int k0, int klim, float4* v) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int idx = tid + 256 * j;
+    if constexpr (KC) {
+      const int r = idx >> 4, k = (idx & 15) << 2;
+      const int gr = r0 + r, gk = k0 + k;
+      v[j] = gr < rlim ? load4(P + (int64_t)gr * s_r + gk, gk, klim)
+                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    } else {
+      const int k = idx >> 4, r = (idx & 15) << 2;
+      const int gr = r0 + r, gk = k0 + k;
+      v[j] = gk < klim ? load4(P + (int64_t)gk * s_k + gr, gr, rlim)
+                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  }
+}
+
+// Rounds the tile to bfloat16 into LDS, laid out [row][k].
+template <bool KC>
+__device__ __forceinline__ void tile_store(uint16_t (*L)[kTP], const float4* v) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int idx = tid + 256 * j;
+    if constexpr (KC) {
+      const int r = idx >> 4, k = (idx & 15) << 2;
+      *reinterpret_cast<uint2*>(&L[r][k]) = pack4_bf16(v[j]);
+    } else {
+      const int k = idx >> 4, r = (idx & 15) << 2;
+      L[r][k] = to_bf16(v[j].x);
+      L[r + 1][k] = to_bf16(v[j].y);
+      L[r + 2][k] = to_bf16(v[j].z);
+      L[r + 3][k] = to_bf16(v[j].w);
+    }
+  }
+}
+
+// C = A B (+ bias, ReLU, mask) with 16-byte operand loads and the next K tile
+// loaded into registers while the current one is multiplied.  AK / BK: A / B
+// contiguous along k (else along m / n).  With gridDim.z > 1 each z-slice
+// multiplies one K range and writes its partial product to ws (no epilogue).
+template <bool AK, bool BK>
+__global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[kTM][kTP];
+  __shared__ __align__(16) uint16_t Bs[kTN][kTP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int bm = blockIdx.y * kTM, bn = blockIdx.x * kTN;
+  const int kbeg = blockIdx.z * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+  const int64_t a_r = AK ? g.sam : 0, a_k = AK ? 0 : g.sak;
+  const int64_t b_r = BK ? g.sbn : 0, b_k = BK ? 0 : g.sbk;
+  float4 ra[4], rb[4];
+  tile_load<AK>(g.A, a_r, a_k, bm, g.M, kbeg, kend, ra);
+  tile_load<BK>(g.B, b_r, b_k, bn, g.N, kbeg, kend, rb);
+  f32x16 acc = {};
+  for (int k0 = kbeg; k0 < kend; k0 += kTK) {
+    tile_store<AK>(As, ra);
+    tile_store<BK>(Bs, rb);
+    __syncthreads();
+    if (k0 + kTK < kend) {
+      tile_load<AK>(g.A, a_r, a_k, bm, g.M, k0 + kTK, kend, ra);
+      tile_load<BK>(g.B, b_r, b_k, bn, g.N, k0 + kTK, kend, rb);
+    }
+#pragma unroll
+    for (int s = 0; s < kTK; s += 16) {
+      const int kk = s + (lane >> 5) * 8;
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][kk]);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + (lane & 31)][kk]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int n = bn + wn * 32 + (lane & 31);
+  if (gridDim.z > 1) {
+    float* w = g.ws + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = bm + wm * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+      if (m < g.M && n < g.N) w[(int64_t)m * g.N + n] = acc[r];
+    }
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = bm + wm * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+    if (m < g.M && n < g.N) {
+      float v = acc[r];
+      if (g.epi & kEpiBias) v += g.bias[n];
+      if (g.epi & kEpiRelu) v = v > 0.0f ? v : 0.0f;
+      if (g.epi & kEpiMask) v = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? v : 0.0f;
+      g.C[(int64_t)m * g.ldc + n] = v;
+    }
+  }
+}
+
+// C(m, n) = sum over z of the split-K partials, in split order.
+__global__ void k_splitk_sum(const float* ws, int S, int M, int N, float* C, int64_t ldc) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    float v = 0.0f;
+    for (int z = 0; z < S; ++z) v += ws[(int64_t)z * total + q];
+    C[(q / N) * ldc + q % N] = v;
+  }
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 hipError_t gemm(hipStream_t s, const float* A, int64_t sam, int64_t sak, const float* B,
                 int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M, int N, int K, int epi,
-                const float* bias = nullptr, const float* mask = nullptr, int64_t ldm = 0) {
-  GemmArgs g{A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, mask, ldm, epi};
-  const dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM));
-  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+                const float* bias = nullptr, const float* mask = nullptr, int64_t ldm = 0,
+                float* ws = nullptr) {
+  GemmArgs g{A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, mask, ldm, epi, ws, K};
+  const bool ak = sak == 1, bk = sbk == 1;
+  const bool a_ok = ak ? (sam % 4 == 0) : (sam == 1 && sak % 4 == 0);
+  const bool b_ok = bk ? (sbn % 4 == 0) : (sbn == 1 && sbk % 4 == 0);
+  if (!(a_ok && b_ok && aligned16(A) && aligned16(B))) {
+    const dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM));
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
+  const int tiles = ((N + kTN - 1) / kTN) * ((M + kTM - 1) / kTM);
+  int S = 1;
+  if (epi == 0 && ws && tiles < 256) {
+    // enough slices to fill the chip, each still at least 256 deep in K
+    S = std::min(kMaxSplit, std::max(1, 512 / tiles));
+    while (S > 1 && K / S < 256) --S;
+  }
+  g.kchunk = S > 1 ? ((K + S - 1) / S + kTK - 1) / kTK * kTK : K;
+  S = (K + g.kchunk - 1) / g.kchunk;
+  const dim3 grid((unsigned)((N + kTN - 1) / kTN), (unsigned)((M + kTM - 1) / kTM), (unsigned)S);
+  if (ak && bk)
+    hipLaunchKernelGGL((k_gemm_v<true, true>), grid, dim3(256), 0, s, g);
+  else if (ak && !bk)
+    hipLaunchKernelGGL((k_gemm_v<true, false>), grid, dim3(256), 0, s, g);
+  else if (!ak && bk)
+    hipLaunchKernelGGL((k_gemm_v<false, true>), grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((k_gemm_v<false, false>), grid, dim3(256), 0, s, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || S == 1) return e;
+  hipLaunchKernelGGL(k_splitk_sum, dim3(1024), dim3(256), 0, s, ws, S, M, N, C, ldc);
   return hipGetLastError();
 }
 
@@ -146,9 +313,10 @@ __global__ void k_out_layer(const float* H2, const float* W3, const float* b3, i
   }
 }
 
-// dO = 2 (O - T) / (n d); per-block partial sums of (O - T)^2.
+// dO = 2 (O - T) / (n d); per-block partial sums of (O - T)^2, added to the
+// block's running sum when accumulate is set.
 __global__ void k_dout(const float* O, const float* T, int64_t cnt, float scale, float* dO,
-                       float* lpart) {
+                       float* lpart, int accumulate) {
   __shared__ float sl[256];
   float l = 0.0f;
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < cnt; q += (int64_t)gridDim.x * 256) {
@@ -162,23 +330,41 @@ __global__ void k_dout(const float* O, const float* T, int64_t cnt, float scale,
     if ((int)threadIdx.x < o) sl[threadIdx.x] += sl[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) lpart[blockIdx.x] = sl[0];
+  if (threadIdx.x == 0) lpart[blockIdx.x] = (accumulate ? lpart[blockIdx.x] : 0.0f) + sl[0];
 }
 
-// gW3[j][k] = sum_r dO[r][j] H2[r][k]; gb3[j] = sum_r dO[r][j] (rows in order).
-__global__ void k_grad_out(const float* dO, const float* H2, int n, int H, int d, float* gW3,
-                           float* gb3) {
+// Output-layer gradient over one chunk of rows (blockIdx.y), in row order:
+//   part[c][j (H+1) + k] = sum_r dO[r][j] H2[r][k]   (k < H)
+//   part[c][j (H+1) + H] = sum_r dO[r][j]
+__global__ void k_grad_out_part(const float* dO, const float* H2, int n, int H, int d,
+                                float* part) {
+  const int Q = d * (H + 1);
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= d * (H + 1)) return;
+  if (q >= Q) return;
   const int j = q / (H + 1), k = q % (H + 1);
+  const int r0 = blockIdx.y * kRowChunk, r1 = min(n, r0 + kRowChunk);
   float s = 0.0f;
   if (k < H) {
-    for (int r = 0; r < n; ++r) s = fmaf(dO[(int64_t)r * d + j], H2[(int64_t)r * H + k], s);
-    gW3[(int64_t)j * H + k] = s;
+    for (int r = r0; r < r1; ++r) s = fmaf(dO[(int64_t)r * d + j], H2[(int64_t)r * H + k], s);
   } else {
-    for (int r = 0; r < n; ++r) s += dO[(int64_t)r * d + j];
-    gb3[j] = s;
+    for (int r = r0; r < r1; ++r) s += dO[(int64_t)r * d + j];
   }
+  part[(int64_t)blockIdx.y * Q + q] = s;
+}
+
+// gW3 / gb3 from the chunk partials, summed in chunk order.
+__global__ void k_grad_out_sum(const float* part, int nchunk, int H, int d, float* gW3,
+                               float* gb3) {
+  const int Q = d * (H + 1);
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q) return;
+  float s = 0.0f;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * Q + q];
+  const int j = q / (H + 1), k = q % (H + 1);
+  if (k < H)
+    gW3[(int64_t)j * H + k] = s;
+  else
+    gb3[j] = s;
 }
 
 // dH2[r][k] = (sum_j dO[r][j] W3[j][k]) where H2[r][k] > 0, else 0.
@@ -194,12 +380,22 @@ __global__ void k_back_out(const float* dO, const float* W3, const float* H2, in
   }
 }
 
-// out[c] = sum_r M[r][c] (rows in order).
-__global__ void k_colsum(const float* M, int n, int cols, float* out) {
+// Column sums of M (n x cols) over one chunk of rows (blockIdx.y), in row order.
+__global__ void k_colsum_part(const float* M, int n, int cols, float* part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  const int r0 = blockIdx.y * kRowChunk, r1 = min(n, r0 + kRowChunk);
+  float s = 0.0f;
+  for (int r = r0; r < r1; ++r) s += M[(int64_t)r * cols + c];
+  part[(int64_t)blockIdx.y * cols + c] = s;
+}
+
+// out[c] = sum of the chunk partials, in chunk order.
+__global__ void k_sum_parts(const float* part, int nchunk, int cols, float* out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   float s = 0.0f;
-  for (int r = 0; r < n; ++r) s += M[(int64_t)r * cols + c];
+  for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * cols + c];
   out[c] = s;
 }
 
@@ -289,6 +485,12 @@ fsne_status mfail(fsne_mlp* m, fsne_status st, const std::string& msg) {
     if (e_ != hipSuccess) return mfail(m, FSNE_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+#define MTRY(expr)                 \
+  do {                             \
+    fsne_status s_ = (expr);       \
+    if (s_ != FSNE_OK) return s_;  \
+  } while (0)
+
 struct Views {
   float *W1, *b1, *W2, *b2, *W3, *b3;
 };
@@ -318,35 +520,50 @@ fsne_status forward(fsne_mlp* m, int n) {
   return FSNE_OK;
 }
 
-// Loss and gradient (into G) of n batch rows with targets in Tb.
-fsne_status backward(fsne_mlp* m, int n) {
+// Column sums of an n x cols batch matrix into out, via row-chunk partials.
+fsne_status colsum(fsne_mlp* m, const float* M, int n, int cols, float* out) {
+  const int nchunk = (n + kRowChunk - 1) / kRowChunk;
+  const unsigned gx = (unsigned)((cols + 255) / 256);
+  hipLaunchKernelGGL(k_colsum_part, dim3(gx, (unsigned)nchunk), dim3(256), 0, m->stream, M, n,
+                     cols, m->part);
+  MCHK(m, hipGetLastError());
+  hipLaunchKernelGGL(k_sum_parts, dim3(gx), dim3(256), 0, m->stream, m->part, nchunk, cols, out);
+  MCHK(m, hipGetLastError());
+  return FSNE_OK;
+}
+
+// Loss and gradient (into G) of n batch rows with targets in Tb; the loss
+// partials are added to the running sums when accumulate is set.
+fsne_status backward(fsne_mlp* m, int n, int accumulate = 0) {
   hipStream_t s = m->stream;
   const Views P = views(m, m->P);
   const Views Gv = views(m, m->G);
   const int64_t cnt = (int64_t)n * m->d;
   hipLaunchKernelGGL(k_dout, dim3(kLossBlocks), dim3(256), 0, s, m->Ob, m->Tb, cnt,
-                     1.0f / (float)cnt, m->dOb, m->lpart);
+                     1.0f / (float)cnt, m->dOb, m->lpart, accumulate);
   MCHK(m, hipGetLastError());
   const int q = m->d * (m->H2 + 1);
-  hipLaunchKernelGGL(k_grad_out, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, m->dOb,
-                     m->H2b, n, m->H2, m->d, Gv.W3, Gv.b3);
+  const int nchunk = (n + kRowChunk - 1) / kRowChunk;
+  hipLaunchKernelGGL(k_grad_out_part, dim3((unsigned)((q + 255) / 256), (unsigned)nchunk),
+                     dim3(256), 0, s, m->dOb, m->H2b, n, m->H2, m->d, m->part);
+  MCHK(m, hipGetLastError());
+  hipLaunchKernelGGL(k_grad_out_sum, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, m->part,
+                     nchunk, m->H2, m->d, Gv.W3, Gv.b3);
   MCHK(m, hipGetLastError());
   hipLaunchKernelGGL(k_back_out, dim3(1024), dim3(256), 0, s, m->dOb, P.W3, m->H2b, n, m->H2,
                      m->d, m->dH2);
   MCHK(m, hipGetLastError());
   // gW2 = dH2^T H1, gb2 = column sums of dH2
-  MCHK(m, gemm(s, m->dH2, 1, m->H2, m->H1b, m->H1, 1, Gv.W2, m->H1, m->H2, m->H1, n, 0));
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->H2 + 255) / 256)), dim3(256), 0, s, m->dH2, n,
-                     m->H2, Gv.b2);
-  MCHK(m, hipGetLastError());
+  MCHK(m, gemm(s, m->dH2, 1, m->H2, m->H1b, m->H1, 1, Gv.W2, m->H1, m->H2, m->H1, n, 0,
+               nullptr, nullptr, 0, m->ws));
+  MTRY(colsum(m, m->dH2, n, m->H2, Gv.b2));
   // dH1 = (dH2 W2) where H1 > 0
   MCHK(m, gemm(s, m->dH2, m->H2, 1, P.W2, m->H1, 1, m->dH1, m->H1, n, m->H1, m->H2, kEpiMask,
                nullptr, m->H1b, m->H1));
   // gW1 = dH1^T X, gb1 = column sums of dH1
-  MCHK(m, gemm(s, m->dH1, 1, m->H1, m->Xb, m->D, 1, Gv.W1, m->D, m->H1, m->D, n, 0));
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((m->H1 + 255) / 256)), dim3(256), 0, s, m->dH1, n,
-                     m->H1, Gv.b1);
-  MCHK(m, hipGetLastError());
+  MCHK(m, gemm(s, m->dH1, 1, m->H1, m->Xb, m->D, 1, Gv.W1, m->D, m->H1, m->D, n, 0,
+               nullptr, nullptr, 0, m->ws));
+  MTRY(colsum(m, m->dH1, n, m->H1, Gv.b1));
   return FSNE_OK;
 }
 
@@ -369,11 +586,6 @@ fsne_status malloc_dev(fsne_mlp* m, T** p, size_t n) {
   return FSNE_OK;
 }
 
-#define MTRY(expr)                 \
-  do {                             \
-    fsne_status s_ = (expr);       \
-    if (s_ != FSNE_OK) return s_;  \
-  } while (0)
 
 // Host batch (n rows of the input dtype, targets T n x d or NULL) to Xb / Tb.
 fsne_status upload_batch(fsne_mlp* m, const void* X, const float* T, int64_t n) {
@@ -449,6 +661,11 @@ fsne_status fsne_mlp_create(const fsne_ctx* ctx, const fsne_mlp_opts* opts, fsne
       (st = malloc_dev(m, &m->Ob, B * m->d)) || (st = malloc_dev(m, &m->dOb, B * m->d)) ||
       (st = malloc_dev(m, &m->dH1, B * m->H1)) || (st = malloc_dev(m, &m->dH2, B * m->H2)) ||
       (st = malloc_dev(m, &m->lpart, kLossBlocks)) ||
+      (st = malloc_dev(m, &m->ws, (size_t)kMaxSplit *
+                                      std::max<size_t>((size_t)m->H1 * m->D, (size_t)m->H2 * m->H1))) ||
+      (st = malloc_dev(m, &m->part, ((B + kRowChunk - 1) / kRowChunk) *
+                                        std::max<size_t>(std::max(m->H1, m->H2),
+                                                         (size_t)m->d * (m->H2 + 1)))) ||
       (st = malloc_dev(m, reinterpret_cast<uint8_t**>(&m->xstage), B * m->D * 4)))
     return bad(st);
   if (hipMemsetAsync(m->Mo, 0, sizeof(float) * m->np, m->stream) != hipSuccess ||
@@ -489,27 +706,23 @@ fsne_status fsne_mlp_train(fsne_mlp* m, fsne_ctx* ctx, float* final_loss) {
   MCHK(m, hipGetLastError());
   const int64_t B = m->opts.batch;
   const int64_t nb = (N + B - 1) / B;
-  double lsum = 0.0;
-  int64_t lcnt = 0;
+  MCHK(m, hipMemsetAsync(m->lpart, 0, sizeof(float) * kLossBlocks, m->stream));
   for (int e = 0; e < m->opts.epochs; ++e) {
     const int64_t off = ((int64_t)e * 104729) % N;
+    const int last = e == m->opts.epochs - 1;
     for (int64_t b = 0; b < nb; ++b) {
       const int n = (int)std::min<int64_t>(B, N - b * B);
       hipLaunchKernelGGL(k_gather, dim3(1024), dim3(256), 0, m->stream, ctx->X, ctx->xdtype, m->D,
                          N, off + b * B, n, ctx->Y, ctx->DP, m->d, m->ymean, m->ystd, m->Xb, m->Tb);
       MCHK(m, hipGetLastError());
       MTRY(forward(m, n));
-      MTRY(backward(m, n));
+      MTRY(backward(m, n, last));
       MTRY(adam(m));
-      if (e == m->opts.epochs - 1 && final_loss) {
-        const float l = loss_of(m, (int64_t)n * m->d);
-        lsum += (double)l * n;
-        lcnt += n;
-      }
     }
   }
+  // mean squared error over the last epoch (each of the N rows once)
+  if (final_loss) *final_loss = m->opts.epochs > 0 ? loss_of(m, N * m->d) : NAN;
   MCHK(m, hipStreamSynchronize(m->stream));
-  if (final_loss) *final_loss = lcnt ? (float)(lsum / (double)lcnt) : NAN;
   return FSNE_OK;
 }
 
@@ -582,7 +795,7 @@ void fsne_mlp_destroy(fsne_mlp* m) {
   if (!m) return;
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   void* bufs[] = {m->P, m->G, m->Mo, m->Vo, m->ymean, m->ystd, m->Xb, m->Tb, m->H1b, m->H2b,
-                  m->Ob, m->dOb, m->dH1, m->dH2, m->lpart, m->xstage};
+                  m->Ob, m->dOb, m->dH1, m->dH2, m->lpart, m->ws, m->part, m->xstage};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (m->stream) (void)hipStreamDestroy(m->stream);
