@@ -130,6 +130,71 @@ def cpu_baseline(X, cfg, Y0, seed):
                       f"oracle init; {dt:.2f} s"}
 
 
+def feedback_run(F, args):
+    """Quality of the HD lists over the iterations with the embedding held
+    fixed (learning rate 0: the LD side gives no feedback) and optimised, at
+    d = 2 and d = 8 (the feedback-loop experiment of Sec. 3): AUC of
+    R_NX(K), K = 1 .. K_hd, of the HD lists against the exact neighbours of a
+    query sample, every ``fb_every`` iterations."""
+    import numpy as np
+
+    from inputs.generators import RUN_SEED, make_workload, y_init
+    from inputs.knn_metrics import exact_knn, rnx_auc, rnx_curve
+
+    X, _, cfg = make_workload("manifold_1m", N=args.fb_n)
+    N, K = X.shape[0], cfg["K_hd"]
+    rng = np.random.default_rng(11)
+    q = np.sort(rng.choice(N, min(1000, N), replace=False))
+    ex, _ = exact_knn(X, q, K)
+    out = {"metric": "HD-list AUC of R_NX(K), K=1..32, fixed vs optimised embedding",
+           "config": {"workload": f"manifold rows, N={N}, D=128 FP32, K_hd=K_ld=32, 16 negatives, "
+                                  f"alpha=1, perplexity 10, HD refinement by the coin",
+                      "iters": args.fb_iters, "every": args.fb_every, "queries": int(q.size)},
+           "curves": {}}
+    for d in (2, 8):
+        for mode in ("fixed", "optimised"):
+            lr = 0.0 if mode == "fixed" else N / 12.0
+            base = dict(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=lr,
+                        n_neg=cfg["n_neg"], hd_mode=0)
+            emb = F.Embedding(X, y_init(N, d), d, K, cfg["K_ld"], seed=RUN_SEED,
+                              hp=schedule(F, base, 0))
+            curve, done = [], 0
+            while True:
+                idx, _ = emb.knn(0)
+                curve.append([done, round(rnx_auc(rnx_curve(idx[q], ex, N)), 4)])
+                if done >= args.fb_iters:
+                    break
+                n = min(args.fb_every, args.fb_iters - done)
+                if done < 250 < done + n:
+                    n = 250 - done
+                emb.set_hyperparams(schedule(F, base, done))
+                emb.step(n)
+                done += n
+            emb.close()
+            out["curves"][f"d{d}_{mode}"] = curve
+    return out
+
+
+def gather_probe(row_bytes, rows_per_wave, table_bytes, nwaves=1_000_000, reps=5):
+    """Random-row gather ceiling: rows/s and bytes/s at which the GPU gathers
+    rows of row_bytes from random positions of a table, one wave per point as
+    the step kernels do (the probe library, not the method)."""
+    import ctypes as C
+
+    lib = C.CDLL(os.path.join(ROOT, "paper_2509_07681_amd", "libfsne_probe.so"))
+    lib.fsne_probe_gather.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_float)]
+    lib.fsne_probe_gather.restype = C.c_int
+    ms = C.c_float(0.0)
+    rc = lib.fsne_probe_gather(table_bytes, row_bytes, rows_per_wave, nwaves, reps, C.byref(ms))
+    if rc != 0:
+        raise RuntimeError(f"gather probe failed ({rc})")
+    rows = float(rows_per_wave) * nwaves / (ms.value * 1e-3)
+    return {"row_bytes": row_bytes, "rows_per_wave": rows_per_wave,
+            "table_MB": round(table_bytes / 2 ** 20, 1), "ms": round(ms.value, 4),
+            "G_rows_per_s": round(rows / 1e9, 2), "TBps": round(rows * row_bytes / 1e12, 3)}
+
+
 def mlp_flops(D, H1, H2, d, n):
     """Multiply-add flops of one training pass over n rows: the forward pass,
     the weight gradients of all three layers and the input gradients of the
@@ -321,6 +386,11 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device to device (counter calibration)")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the online-use experiment")
+    ap.add_argument("--feedback", action="store_true",
+                    help="run the feedback-loop experiment (fixed vs optimised embedding) instead")
+    ap.add_argument("--fb-n", type=int, default=50000)
+    ap.add_argument("--fb-iters", type=int, default=2000)
+    ap.add_argument("--fb-every", type=int, default=100)
     ap.add_argument("--dynamic", action="store_true",
                     help="run the online-use experiment (learned vs random placement) instead")
     ap.add_argument("--dyn-base", type=int, default=0, help="base points (0: 500,000)")
@@ -359,6 +429,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.dynamic:
         print(json.dumps(dynamic_run(F, args)))
+        return
+    if args.feedback:
+        print(json.dumps(feedback_run(F, args)))
         return
 
     X, _, cfg = make_workload("manifold_1m")
@@ -408,6 +481,17 @@ def main():
         kernels[k] = e
     kernels["hd_refine"]["candidate_rows_per_point"] = round(hd_cand, 3)
     kernels["ld_grad"]["candidate_rows_per_point"] = round(ld_cand, 3)
+    # the LD pass gathers one 4*DP-byte row per neighbour, candidate and
+    # negative: compare its row rate with the random-gather ceiling
+    dp = 2
+    while dp < cfg["d"]:
+        dp *= 2
+    ld_rows = 1 + cfg["K_ld"] + ld_cand + cfg["K_hd"] + cfg["n_neg"]
+    probe = gather_probe(4 * dp, 112, N * 4 * dp)
+    ld_rate = ld_rows * N / (kernels["ld_grad"]["avg_ms"] * 1e-3) / 1e9
+    kernels["ld_grad"]["rows_per_point"] = round(ld_rows, 2)
+    kernels["ld_grad"]["G_rows_per_s"] = round(ld_rate, 2)
+    kernels["ld_grad"]["frac_of_gather_ceiling"] = round(ld_rate / probe["G_rows_per_s"], 4)
     ld_only_ms = sum(kernels[k]["avg_ms"] for k in ("ld_grad", "reduce", "update"))
     dom = kernels["hd_refine"]
     traffic = None
@@ -439,6 +523,7 @@ def main():
                      "traffic": traffic, "traffic_unit": "GB per launch (FETCH_SIZE x2.0 "
                      "+ WRITE_SIZE x1.0, copy-calibrated)"},
         "kernels": kernels,
+        "gather_ceiling": probe,
         "ld_only_ms_per_step": round(ld_only_ms, 4),
         "ld_only_iters_per_s": round(1000.0 / ld_only_ms, 2),
     }

@@ -87,3 +87,36 @@ def set_recall(a, b):
     """Mean over rows of |a_r ∩ b_r| / K for two (n, K) index arrays."""
     K = a.shape[1]
     return float(np.mean([len(set(x.tolist()) & set(y.tolist())) / K for x, y in zip(a, b)]))
+
+
+def rnx_curve(est, exact, N):
+    """R_NX(K) for K = 1 .. Kmax of estimated neighbour lists against exact ones.
+
+    est, exact: (n, Kmax) index arrays, each row sorted nearest first (so its
+    first K entries are that row's K-neighbourhood).  With Q_NX(K) the mean
+    of |est_K ∩ exact_K| / K over the rows, R_NX(K) rescales it so that 0 is
+    a random neighbourhood and 1 a perfect one:
+        R_NX(K) = ((N - 1) Q_NX(K) - K) / (N - 1 - K)      (Lee and Verleysen)
+    """
+    est = np.asarray(est, dtype=np.int64)
+    exact = np.asarray(exact, dtype=np.int64)
+    n, Kmax = exact.shape
+    hits = np.zeros(Kmax + 1, dtype=np.float64)
+    for r in range(n):
+        pos = {int(j): k for k, j in enumerate(exact[r])}
+        # entry k of the estimate, at exact rank q, is shared by both
+        # K-neighbourhoods for every K > max(k, q)
+        for k, j in enumerate(est[r][:Kmax]):
+            q = pos.get(int(j))
+            if q is not None:
+                hits[max(k, q) + 1] += 1.0
+    shared = np.cumsum(hits)[1:]
+    K = np.arange(1, Kmax + 1, dtype=np.float64)
+    Q = shared / (n * K)
+    return ((N - 1) * Q - K) / (N - 1 - K)
+
+
+def rnx_auc(curve):
+    """Area under R_NX(K) on a log scale of K: sum R(K)/K over sum 1/K."""
+    K = np.arange(1, len(curve) + 1, dtype=np.float64)
+    return float(np.sum(np.asarray(curve) / K) / np.sum(1.0 / K))
