@@ -151,13 +151,17 @@ def feedback_run(F, args):
                                   f"alpha=1, perplexity 10, HD refinement by the coin",
                       "iters": args.fb_iters, "every": args.fb_every, "queries": int(q.size)},
            "curves": {}}
+    # jump start: two random projections, each held for js iterations at
+    # learning rate 0, then the usual schedule from its beginning
+    js = 100
     for d in (2, 8):
-        for mode in ("fixed", "optimised"):
+        for mode in ("fixed", "optimised", "jumpstart"):
             lr = 0.0 if mode == "fixed" else N / 12.0
             base = dict(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=lr,
                         n_neg=cfg["n_neg"], hd_mode=0)
             emb = F.Embedding(X, y_init(N, d), d, K, cfg["K_ld"], seed=RUN_SEED,
                               hp=schedule(F, base, 0))
+            t0 = 2 * js if mode == "jumpstart" else 0   # where the schedule starts
             curve, done = [], 0
             while True:
                 idx, _ = emb.knn(0)
@@ -165,9 +169,16 @@ def feedback_run(F, args):
                 if done >= args.fb_iters:
                     break
                 n = min(args.fb_every, args.fb_iters - done)
-                if done < 250 < done + n:
-                    n = 250 - done
-                emb.set_hyperparams(schedule(F, base, done))
+                for edge in (t0 + 250, js, 2 * js):
+                    if done < edge < done + n:
+                        n = edge - done
+                if mode == "jumpstart" and done < 2 * js:
+                    if done in (0, js):
+                        emb.jump_start(done // js, 1e-2)
+                    emb.set_hyperparams(F.fsne_default_hparams(**{**schedule(F, base, 0).as_dict(),
+                                                                  "lr": 0.0}))
+                else:
+                    emb.set_hyperparams(schedule(F, base, done - t0))
                 emb.step(n)
                 done += n
             emb.close()

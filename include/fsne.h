@@ -184,6 +184,19 @@ fsne_status fsne_drift_points(fsne_ctx *ctx, const int64_t *ids, const void *Xne
  * (Sec. 3, the "implosion" control).  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_implode(fsne_ctx *ctx, float factor);
 
+/* Jump start (Sec. 3, helping the first iterations): replace the embedding
+ * of the N live points by a random linear projection of the centred data,
+ *   y_ic = s sum_k (x_ik - mu_k) r_kc,  r_kc = -1 if bit 0 of the first word
+ *   of Philox block (k, c, 9, projection) under the context's seed is set,
+ *   else +1;  s = sigma / sqrt(tr Sigma), tr Sigma = (1/N) sum_i |x_i - mu|^2
+ *   (s = 0 if the data have no spread),
+ * so each coordinate has variance about sigma^2; V <- 0.  Means and the
+ * trace are summed in double.  Typical use: a few projections (projection =
+ * 0, 1, ...) each followed by some iterations at learning rate 0, before the
+ * gradient takes over.  Synchronises the stream.
+ * Errors: FSNE_EINVAL (projection < 0, sigma <= 0), FSNE_EHIP. */
+fsne_status fsne_jump_start(fsne_ctx *ctx, int32_t projection, float sigma);
+
 /* Kernels of one iteration, in launch order (indices of fsne_get_kernel_times). */
 enum {
     FSNE_K_HD_REFINE = 0, /* HD candidates, distances, merge, recalibration     */

@@ -767,6 +767,53 @@ int fsneo_drift(fsneo_state *S, const fsneo_hp *hp, const int64_t *ids, int64_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Jump start (Sec. 3, paragraph on helping the first iterations): the       */
+/* embedding becomes a random linear projection of the centred data,        */
+/*   y_ic = s sum_k (x_ik - mu_k) r_kc,                                      */
+/* r_kc = -1 if bit 0 of the first word of block (k, c, 9, projection) is   */
+/* set, else +1 (a Rademacher projection, Achlioptas 2003); s = sigma /      */
+/* sqrt(tr Sigma) with tr Sigma = (1/N) sum_i |x_i - mu|^2 (s = 0 when it is */
+/* 0), so every coordinate has variance about sigma^2.  V = 0.               */
+/* ------------------------------------------------------------------------ */
+void fsneo_jump_start(fsneo_state *S, int32_t projection, double sigma)
+{
+    const int64_t N = S->N;
+    const int32_t D = S->D, d = S->d;
+    double *mu = calloc((size_t)D, sizeof(double));
+    double *r = malloc(sizeof(double) * (size_t)D * (size_t)d);
+    for (int64_t i = 0; i < N; ++i)
+        for (int32_t k = 0; k < D; ++k) mu[k] += xval(S->X, S->xdtype, i * D + k);
+    for (int32_t k = 0; k < D; ++k) mu[k] /= (double)N;
+    double tr = 0.0;
+    for (int32_t k = 0; k < D; ++k) {
+        double v = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            double e = xval(S->X, S->xdtype, i * D + k) - mu[k];
+            v += e * e;
+        }
+        tr += v / (double)N;
+    }
+    const double scale = tr > 0.0 ? sigma / sqrt(tr) : 0.0;
+    for (int32_t k = 0; k < D; ++k)
+        for (int32_t c = 0; c < d; ++c) {
+            uint32_t u[4];
+            draw(S->seed, (uint32_t)k, (uint32_t)c, 9u, (uint32_t)projection, u);
+            r[k * d + c] = (u[0] & 1u) ? -1.0 : 1.0;
+        }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i)
+        for (int32_t c = 0; c < d; ++c) {
+            double y = 0.0;
+            for (int32_t k = 0; k < D; ++k)
+                y += (xval(S->X, S->xdtype, i * D + k) - mu[k]) * r[k * d + c];
+            S->Y[i * d + c] = scale * y;
+            S->V[i * d + c] = 0.0;
+        }
+    free(mu);
+    free(r);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exact references, O(N^2), used to pin the method.                          */
 /* ------------------------------------------------------------------------ */
 

@@ -100,6 +100,8 @@ def lib():
         L.fsneo_drift.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P, C.c_int64, P]
         L.fsneo_drift.restype = C.c_int
         L.fsneo_num_threads.restype = C.c_int
+        L.fsneo_jump_start.argtypes = [C.POINTER(_State), C.c_int32, C.c_double]
+        L.fsneo_jump_start.restype = None
         L.fsneo_mlp_nparams.argtypes = [C.POINTER(_MlpDims)]
         L.fsneo_mlp_nparams.restype = C.c_int64
         L.fsneo_mlp_init.argtypes = [C.POINTER(_MlpDims), C.c_uint64, P]
@@ -284,6 +286,10 @@ class OracleState:
         s = self.cstate()
         lib().fsneo_drift(C.byref(s), C.byref(hp.c()), _p(ids), ids.size,
                           None if Yn is None else _p(Yn))
+
+    def jump_start(self, projection: int = 0, sigma: float = 1e-2):
+        s = self.cstate()
+        lib().fsneo_jump_start(C.byref(s), int(projection), float(sigma))
 
     # -- views --------------------------------------------------------------
     def live(self, name):

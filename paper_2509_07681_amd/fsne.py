@@ -73,6 +73,7 @@ def load_library(path: str = LIB_PATH):
     L.fsne_insert_points.argtypes = [P, P, I64, P]
     L.fsne_drift_points.argtypes = [P, P, P, I64, P]
     L.fsne_implode.argtypes = [P, F]
+    L.fsne_jump_start.argtypes = [P, I32, F]
     L.fsne_destroy.argtypes = [P]
     L.fsne_destroy.restype = None
     L.fsne_last_error.argtypes = [P]
@@ -80,7 +81,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("fsne_default_hparams", "fsne_init", "fsne_step", "fsne_set_hyperparams",
                  "fsne_get_hyperparams", "fsne_get_Y", "fsne_get_knn", "fsne_get_state",
                  "fsne_set_state", "fsne_get_stats", "fsne_sync", "fsne_insert_points",
-                 "fsne_drift_points", "fsne_implode"):
+                 "fsne_drift_points", "fsne_implode", "fsne_jump_start"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -248,6 +249,10 @@ def fsne_implode(ctx, factor: float):
     _check(ctx, load_library().fsne_implode(ctx, float(factor)))
 
 
+def fsne_jump_start(ctx, projection: int, sigma: float):
+    _check(ctx, load_library().fsne_jump_start(ctx, int(projection), float(sigma)))
+
+
 def fsne_destroy(ctx):
     if ctx:
         load_library().fsne_destroy(ctx)
@@ -297,6 +302,9 @@ class Embedding:
 
     def implode(self, factor):
         fsne_implode(self.ctx, factor)
+
+    def jump_start(self, projection=0, sigma=1e-2):
+        fsne_jump_start(self.ctx, projection, sigma)
 
     def profile(self, enable=True):
         fsne_profile(self.ctx, enable)

@@ -391,3 +391,57 @@ def test_insert_and_drift(oracle_lib):
     assert np.all(S.V[ids] == 0)
     for _ in range(5):
         S.step(hp)
+
+
+# --- jump start by a random linear projection --------------------------------
+def _js_state(O, X, d=3, seed=5):
+    N = X.shape[0]
+    S = O.OracleState(X, d, 8, 8, seed, np.zeros((N, d), np.float32))
+    return S
+
+
+def test_jump_start_centring_scale_and_distances(oracle_lib):
+    """Centred (mean exactly 0), each coordinate of variance about sigma^2 on
+    isotropic data, and squared distances preserved on average up to the
+    factor d s^2 of a +-1 projection (Johnson-Lindenstrauss)."""
+    O = oracle_lib
+    rng = np.random.default_rng(3)
+    N, D, d, sigma = 6000, 48, 3, 0.05
+    X = (rng.normal(size=(N, D)) * 2.0 + 7.0).astype(np.float32)
+    S = _js_state(O, X, d)
+    S.jump_start(0, sigma)
+    Y = S.live("Y")
+    assert np.all(S.live("V") == 0.0)
+    assert np.all(np.abs(Y.mean(0)) < 1e-12 * sigma * N)
+    assert np.all(np.abs(Y.std(0) / sigma - 1.0) < 0.06), Y.std(0) / sigma
+    Xc = X.astype(np.float64) - X.astype(np.float64).mean(0)
+    s2 = sigma ** 2 / (Xc ** 2).sum(1).mean()
+    a, b = rng.integers(0, N, 4000), rng.integers(0, N, 4000)
+    keep = a != b
+    ratio = ((Y[a] - Y[b]) ** 2).sum(1)[keep] / (d * s2 * ((Xc[a] - Xc[b]) ** 2).sum(1)[keep])
+    assert abs(ratio.mean() - 1.0) < 0.05, ratio.mean()
+
+
+def test_jump_start_invariances_and_projections(oracle_lib):
+    """Shifting or rescaling the data leaves the projection unchanged; the
+    projection index selects a different sign matrix; a constant data set
+    maps to 0."""
+    O = oracle_lib
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(500, 20)).astype(np.float32)
+    S = _js_state(O, X)
+    S.jump_start(0, 1.0)
+    Y0 = S.live("Y").copy()
+    S2 = _js_state(O, X * np.float32(4.0))
+    S2.jump_start(0, 1.0)
+    np.testing.assert_allclose(S2.live("Y"), Y0, rtol=1e-12, atol=1e-12)
+    S3 = _js_state(O, X + np.float32(0.5))
+    S3.jump_start(0, 1.0)
+    np.testing.assert_allclose(S3.live("Y"), Y0, rtol=1e-5, atol=1e-5)
+    S.jump_start(1, 1.0)
+    assert not np.allclose(S.live("Y"), Y0)
+    S.jump_start(0, 1.0)
+    np.testing.assert_array_equal(S.live("Y"), Y0)
+    S4 = _js_state(O, np.ones((50, 20), np.float32))
+    S4.jump_start(0, 1.0)
+    assert np.all(S4.live("Y") == 0.0)
