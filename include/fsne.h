@@ -180,6 +180,19 @@ fsne_status fsne_insert_points(fsne_ctx *ctx, const void *Xnew, int64_t n, const
 fsne_status fsne_drift_points(fsne_ctx *ctx, const int64_t *ids, const void *Xnew, int64_t n,
                               const float *Yinit);
 
+/* Remove n points (host ids, distinct, 0 <= id < N; at least
+ * max(K_hd, K_ld) + 1 points must remain) -- online use, Sec. 3.  Ids stay
+ * dense: with N' = N - n, the surviving points at or beyond N' move, in
+ * increasing order, into the freed ids below N', in increasing order; every
+ * other survivor keeps its id.  Each survivor's lists are rewritten:
+ * entries of deleted points are dropped, the rest take the new ids; an HD
+ * list refills with random points (draws (i, t, 10, s)), gets their
+ * distances, is re-sorted by (d2, id) and recalibrated (flag set); an LD list
+ * keeps its surviving entries in order and appends random refills (draws
+ * (i, t, 11, s)).  Affinities are recomputed.  Synchronises the stream.
+ * Errors: FSNE_EINVAL, FSNE_ESTATE (X borrowed), FSNE_ENOMEM, FSNE_EHIP. */
+fsne_status fsne_delete_points(fsne_ctx *ctx, const int64_t *ids, int64_t n);
+
 /* Scale the embedding down by factor (> 0): Y <- Y / factor, V <- V / factor
  * (Sec. 3, the "implosion" control).  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_implode(fsne_ctx *ctx, float factor);

@@ -487,13 +487,17 @@ void fsneo_ld_refine_grad_point(const fsneo_state *S, const fsneo_hp *hp, int64_
 /* fill the rest); HD lists sorted by distance; every point calibrated;      */
 /* E = 1 so the first iteration refines the HD lists; V = 0; t = 0.          */
 /* ------------------------------------------------------------------------ */
-static void random_list(int64_t i, int64_t N, int32_t K, uint32_t stream, uint64_t seed,
-                        int32_t *out)
+/* out[0..n_have) already holds list ids; fill up to K with the first      */
+/* distinct other points among the draws (i, t, stream, s), s = 0, 1, ...  */
+/* < 64K, then the next indices i+1, i+2, ... (initial lists: t = 0 and    */
+/* n_have = 0).                                                             */
+static void random_list(int64_t i, int64_t N, int32_t K, uint32_t stream, uint32_t t,
+                        uint64_t seed, int32_t *out, int n_have)
 {
-    int n = 0;
+    int n = n_have;
     for (uint32_t s = 0; n < K && s < 64u * (uint32_t)K; ++s) {
         uint32_t u[4];
-        draw(seed, (uint32_t)i, 0, stream, s, u);
+        draw(seed, (uint32_t)i, t, stream, s, u);
         int64_t c = uniform_other(u[0], i, N);
         if (!contains(out, n, c)) out[n++] = (int32_t)c;
     }
@@ -504,8 +508,8 @@ static void random_list(int64_t i, int64_t N, int32_t K, uint32_t stream, uint64
 static void init_point_lists(fsneo_state *S, int64_t i, int64_t N)
 {
     const int32_t K = S->K_hd;
-    random_list(i, N, K, FSNEO_S_INIT_HD, S->seed, S->hd_idx + i * K);
-    random_list(i, N, S->K_ld, FSNEO_S_INIT_LD, S->seed, S->ld_idx + i * S->K_ld);
+    random_list(i, N, K, FSNEO_S_INIT_HD, 0, S->seed, S->hd_idx + i * K, 0);
+    random_list(i, N, S->K_ld, FSNEO_S_INIT_LD, 0, S->seed, S->ld_idx + i * S->K_ld, 0);
     entry e[64];
     for (int32_t k = 0; k < K; ++k) {
         e[k].idx = S->hd_idx[i * K + k];
@@ -767,6 +771,67 @@ int fsneo_drift(fsneo_state *S, const fsneo_hp *hp, const int64_t *ids, int64_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Point deletion (Sec. 3: points can be removed on the fly).  The caller   */
+/* has already compacted the per-point rows (survivors at or beyond the new */
+/* N moved into the freed ids below it) and set N; newid maps every old id  */
+/* to its new one, or to -1 for a deleted point.  For each survivor i:      */
+/*   LD list: surviving entries (new ids) in their order, then refills from */
+/*   the draws (i, t, 11, s);                                               */
+/*   HD list: if any entry was deleted or renumbered, surviving entries keep */
+/*   their distances, refills from the draws (i, t, 10, s) get theirs, the  */
+/*   row is sorted by (d2, id), and if an entry was deleted it is          */
+/*   recalibrated and flagged.                                              */
+/* P is then recomputed for every point.                                    */
+/* ------------------------------------------------------------------------ */
+void fsneo_delete_fix(fsneo_state *S, const fsneo_hp *hp, const int32_t *newid)
+{
+    const int64_t N = S->N;
+    const int32_t Kh = S->K_hd, Kl = S->K_ld;
+    const uint32_t t = *S->t;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < N; ++i) {
+        int32_t ids[64];
+        int nk = 0;
+        for (int32_t k = 0; k < Kl; ++k) {
+            int32_t nj = newid[S->ld_idx[i * Kl + k]];
+            if (nj >= 0) ids[nk++] = nj;
+        }
+        random_list(i, N, Kl, FSNEO_S_DEL_LD, t, S->seed, ids, nk);
+        for (int32_t k = 0; k < Kl; ++k) S->ld_idx[i * Kl + k] = ids[k];
+
+        entry e[64];
+        int changed = 0;
+        nk = 0;
+        for (int32_t k = 0; k < Kh; ++k) {
+            int32_t j = S->hd_idx[i * Kh + k], nj = newid[j];
+            changed |= nj != j;
+            if (nj >= 0) {
+                ids[nk] = nj;
+                e[nk].idx = nj;
+                e[nk].key = S->hd_d2[i * Kh + k];
+                ++nk;
+            }
+        }
+        if (!changed) continue;
+        random_list(i, N, Kh, FSNEO_S_DEL_HD, t, S->seed, ids, nk);
+        for (int32_t k = nk; k < Kh; ++k) {
+            e[k].idx = ids[k];
+            e[k].key = fsneo_hd_dist2(S->X, S->xdtype, S->D, i, ids[k]);
+        }
+        sort_entries(e, Kh);
+        for (int32_t k = 0; k < Kh; ++k) {
+            S->hd_idx[i * Kh + k] = (int32_t)e[k].idx;
+            S->hd_d2[i * Kh + k] = e[k].key;
+        }
+        if (nk < Kh) {
+            calibrate_point(S, i, hp->perplexity);
+            S->flags[i] = 1;
+        }
+    }
+    all_psym(S);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Jump start (Sec. 3, paragraph on helping the first iterations): the       */
 /* embedding becomes a random linear projection of the centred data,        */
 /*   y_ic = s sum_k (x_ik - mu_k) r_kc,                                      */
@@ -797,7 +862,7 @@ void fsneo_jump_start(fsneo_state *S, int32_t projection, double sigma)
     for (int32_t k = 0; k < D; ++k)
         for (int32_t c = 0; c < d; ++c) {
             uint32_t u[4];
-            draw(S->seed, (uint32_t)k, (uint32_t)c, 9u, (uint32_t)projection, u);
+            draw(S->seed, (uint32_t)k, (uint32_t)c, FSNEO_S_JUMP, (uint32_t)projection, u);
             r[k * d + c] = (u[0] & 1u) ? -1.0 : 1.0;
         }
 #pragma omp parallel for schedule(static)

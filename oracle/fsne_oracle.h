@@ -28,7 +28,8 @@ extern "C" {
 
 /* Counter-stream ids of the random draws (third counter word). */
 enum { FSNEO_S_HDC = 1, FSNEO_S_LDC = 2, FSNEO_S_NEG = 3, FSNEO_S_INIT_HD = 4,
-       FSNEO_S_INIT_LD = 5, FSNEO_S_COIN = 7 };
+       FSNEO_S_INIT_LD = 5, FSNEO_S_COIN = 7, FSNEO_S_JUMP = 9, FSNEO_S_DEL_HD = 10,
+       FSNEO_S_DEL_LD = 11 };
 
 typedef struct {
     int64_t N;          /* live number of points                              */
@@ -95,6 +96,7 @@ int fsneo_insert(fsneo_state *S, const fsneo_hp *hp, int64_t n_new, const double
 int fsneo_drift(fsneo_state *S, const fsneo_hp *hp, const int64_t *ids, int64_t n,
                 const double *Y_new);
 void fsneo_jump_start(fsneo_state *S, int32_t projection, double sigma);
+void fsneo_delete_fix(fsneo_state *S, const fsneo_hp *hp, const int32_t *newid);
 int fsneo_num_threads(void);
 
 #ifdef __cplusplus

@@ -102,6 +102,8 @@ def lib():
         L.fsneo_num_threads.restype = C.c_int
         L.fsneo_jump_start.argtypes = [C.POINTER(_State), C.c_int32, C.c_double]
         L.fsneo_jump_start.restype = None
+        L.fsneo_delete_fix.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P]
+        L.fsneo_delete_fix.restype = None
         L.fsneo_mlp_nparams.argtypes = [C.POINTER(_MlpDims)]
         L.fsneo_mlp_nparams.restype = C.c_int64
         L.fsneo_mlp_init.argtypes = [C.POINTER(_MlpDims), C.c_uint64, P]
@@ -286,6 +288,28 @@ class OracleState:
         s = self.cstate()
         lib().fsneo_drift(C.byref(s), C.byref(hp.c()), _p(ids), ids.size,
                           None if Yn is None else _p(Yn))
+
+    def delete(self, hp: Hyper, ids):
+        """Remove points: survivors at or beyond the new N move, in increasing
+        order, into the freed ids below it, in increasing order; then the
+        lists are rewritten (fsneo_delete_fix)."""
+        ids = np.unique(np.asarray(ids, dtype=np.int64))
+        N0 = self.N
+        N1 = N0 - ids.size
+        dead = np.zeros(N0, bool)
+        dead[ids] = True
+        src = np.nonzero(~dead[N1:])[0] + N1
+        dst = np.nonzero(dead[:N1])[0]
+        newid = np.where(dead, -1, np.arange(N0)).astype(np.int32)
+        newid[src] = dst
+        for name in ("X", "Y", "V", "hd_idx", "hd_d2", "ld_idx", "beta", "m", "r", "invS",
+                     "flags"):
+            a = getattr(self, name)
+            a[dst] = a[src]
+        self.N = N1
+        s = self.cstate()
+        lib().fsneo_delete_fix(C.byref(s), C.byref(hp.c()), _p(newid))
+        return newid
 
     def jump_start(self, projection: int = 0, sigma: float = 1e-2):
         s = self.cstate()

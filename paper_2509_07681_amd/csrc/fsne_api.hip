@@ -657,6 +657,90 @@ fsne_status fsne_drift_points(fsne_ctx* c, const int64_t* ids, const void* Xnew,
   return st;
 }
 
+fsne_status fsne_delete_points(fsne_ctx* c, const int64_t* ids, int64_t n) {
+  if (!c) return FSNE_EINVAL;
+  if (!ids || n < 0) return fail(c, FSNE_EINVAL, "bad arguments to fsne_delete_points");
+  if (n == 0) return FSNE_OK;
+  if (!c->own_X) return fail(c, FSNE_ESTATE, "X is borrowed; create the context with capacity");
+  const int64_t N = c->N, N1 = N - n;
+  if (N1 <= std::max(c->Kh, c->Kl)) return fail(c, FSNE_EINVAL, "too few points would remain");
+  std::vector<uint8_t> del((size_t)N, 0);
+  for (int64_t k = 0; k < n; ++k) {
+    if (ids[k] < 0 || ids[k] >= N) return fail(c, FSNE_EINVAL, "delete id out of range");
+    if (del[(size_t)ids[k]]) return fail(c, FSNE_EINVAL, "duplicate delete id");
+    del[(size_t)ids[k]] = 1;
+  }
+  // survivors at or beyond N1 move, in increasing order, into the deleted
+  // slots below N1, in increasing order
+  std::vector<int32_t> newid((size_t)N), src, dst;
+  for (int64_t j = N1; j < N; ++j)
+    if (!del[(size_t)j]) src.push_back((int32_t)j);
+  for (int64_t j = 0; j < N1; ++j)
+    if (del[(size_t)j]) dst.push_back((int32_t)j);
+  for (int64_t j = 0; j < N; ++j) newid[(size_t)j] = del[(size_t)j] ? -1 : (int32_t)j;
+  for (size_t k = 0; k < src.size(); ++k) newid[(size_t)src[k]] = dst[k];
+  Scalars s;
+  TRY(read_scalars(c, &s));
+  const int32_t m = (int32_t)src.size();
+  int32_t *dnew = nullptr, *dsrc = nullptr, *ddst = nullptr;
+  fsne_status st = FSNE_OK;
+  if (hipMalloc(&dnew, sizeof(int32_t) * N) != hipSuccess ||
+      hipMalloc(&dsrc, sizeof(int32_t) * (m + 1)) != hipSuccess ||
+      hipMalloc(&ddst, sizeof(int32_t) * (m + 1)) != hipSuccess) {
+    st = fail(c, FSNE_ENOMEM, "delete staging allocation failed");
+  }
+  do {
+    if (st != FSNE_OK) break;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dnew, newid.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice,
+                            c->stream)) != hipSuccess ||
+        (m > 0 && (e = hipMemcpyAsync(dsrc, src.data(), sizeof(int32_t) * m,
+                                      hipMemcpyHostToDevice, c->stream)) != hipSuccess) ||
+        (m > 0 && (e = hipMemcpyAsync(ddst, dst.data(), sizeof(int32_t) * m,
+                                      hipMemcpyHostToDevice, c->stream)) != hipSuccess)) {
+      st = hip_fail(c, e, "delete upload");
+      break;
+    }
+    struct Rows {
+      void* base;
+      size_t bytes;
+    };
+    const Rows rows[] = {
+        {c->X, (size_t)c->D * xbytes(c)},
+        {c->Y, sizeof(float) * c->DP},
+        {c->V, sizeof(float) * c->DP},
+        {c->rec, sizeof(float4)},
+        {c->hd_idx[s.hd_cur], sizeof(int32_t) * c->Kh},
+        {c->hd_d2[s.hd_cur], sizeof(float) * c->Kh},
+        {c->ld_idx[s.t & 1u], sizeof(int32_t) * c->Kl},
+        {c->flags, 1},
+        {c->xdtype == FSNE_BF16 ? (void*)c->xnorm : nullptr, sizeof(float)},
+    };
+    for (const Rows& r : rows) {
+      if (!r.base) continue;
+      if ((e = fsne::launch_move_rows(r.base, dsrc, ddst, m, (int32_t)r.bytes, c->stream)) !=
+          hipSuccess)
+        break;
+    }
+    if (e != hipSuccess) {
+      st = hip_fail(c, e, "delete moves");
+      break;
+    }
+    c->N = N1;
+    StepArgs a = make_args(c);
+    if ((e = fsne::launch_delete_fix(a, dnew, c->stream)) != hipSuccess) {
+      st = hip_fail(c, e, "delete lists");
+      break;
+    }
+    st = refresh_affinities(c, false);
+  } while (false);
+  (void)hipStreamSynchronize(c->stream);
+  if (dnew) (void)hipFree(dnew);
+  if (dsrc) (void)hipFree(dsrc);
+  if (ddst) (void)hipFree(ddst);
+  return st;
+}
+
 fsne_status fsne_profile(fsne_ctx* c, int32_t enable) {
   if (!c) return FSNE_EINVAL;
   TRY(drain_timings(c));

@@ -46,6 +46,9 @@ hipError_t launch_set_fire(Scalars* sc, const Hyper& h, hipStream_t s);
 hipError_t launch_scale(float* Y, float* V, int64_t n, float inv, hipStream_t s);
 hipError_t launch_calibrate_all(const StepArgs& a, hipStream_t s);
 hipError_t launch_drift_rows(const StepArgs& a, const uint8_t* moved, hipStream_t s);
+hipError_t launch_delete_fix(const StepArgs& a, const int32_t* newid, hipStream_t s);
+hipError_t launch_move_rows(void* base, const int32_t* src, const int32_t* dst, int32_t m,
+                            int32_t row_bytes, hipStream_t s);
 hipError_t launch_xnorm(const StepArgs& a, float* xnorm, int32_t i0, int32_t n, hipStream_t s);
 hipError_t launch_scatter_rows(void* dst, const void* src, const int32_t* ids, int32_t n,
                                int32_t row_bytes, hipStream_t s);

@@ -191,18 +191,19 @@ __device__ __forceinline__ int make_candidate(int32_t i, uint32_t t, uint32_t st
 }
 
 // ---------------------------------------------------------------------------
-// Initial lists: for point i, the first K distinct other points among the
-// draws (i, 0, stream, s), s = 0, 1, ... < 64K, completed if need be by
-// i+1, i+2, ... (mod N).  Draws are taken 64 at a time; a draw is a
-// duplicate if it repeats an accepted id or an earlier draw of its round.
-// The list goes to lst[0..K) (LDS).
+// Random list completion: lst[0..n_have) holds ids already in the list; it
+// is filled up to K distinct other points with the draws (i, t, stream, s),
+// s = 0, 1, ... < 64K, completed if need be by i+1, i+2, ... (mod N).
+// Draws are taken 64 at a time; a draw is a duplicate if it repeats an id of
+// the list or an earlier draw of its round.  Initial lists are the case
+// t = 0, n_have = 0.  The list goes to lst[0..K) (LDS).
 // ---------------------------------------------------------------------------
-__device__ void random_list(int32_t i, int32_t N, int K, uint32_t stream, const Hyper& h,
-                            int* lst) {
+__device__ void random_list(int32_t i, int32_t N, int K, uint32_t stream, uint32_t t,
+                            const Hyper& h, int* lst, int n_have) {
   const int lane = lane_id();
-  int n = 0;
+  int n = n_have;
   for (int base = 0; n < K && base < kWave * K; base += kWave) {
-    const uint4 u = philox((uint32_t)i, 0u, stream, (uint32_t)(base + lane), h.key0, h.key1);
+    const uint4 u = philox((uint32_t)i, t, stream, (uint32_t)(base + lane), h.key0, h.key1);
     const int c = draw_other(u.x, i, N);
     bool dup = false;
     for (int k = 0; k < n; ++k) dup |= (lst[k] == c);
@@ -246,10 +247,10 @@ __global__ __launch_bounds__(kBlock) void k_init_lists(const TX* __restrict__ X,
   const int32_t i = i0 + (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   if (i >= N) return;
   const int lane = lane_id();
-  random_list(i, N, Kl, kStreamInitLD, h, S.lst);
+  random_list(i, N, Kl, kStreamInitLD, 0u, h, S.lst, 0);
   if (lane < Kl) ld_idx[(int64_t)i * Kl + lane] = S.lst[lane];
   wave_lds_sync();
-  random_list(i, N, Kh, kStreamInitHD, h, S.lst);
+  random_list(i, N, Kh, kStreamInitHD, 0u, h, S.lst, 0);
   const int id = lane < Kh ? S.lst[lane] : -1;
   hd_dist_rows<TX, VEC, CH>(X, D, i, id, Kh, S.d2);
   const float dd = lane < Kh ? S.d2[lane] : kInf;
@@ -1031,6 +1032,91 @@ __global__ __launch_bounds__(kBlock) void k_drift_rows(StepArgs a, const uint8_t
 }
 
 // ---------------------------------------------------------------------------
+// Point deletion.  Rows moved by the compaction (see fsne_delete_points) are
+// copied first; then every surviving point i < N' has its lists rewritten:
+// ids pass through newid (deleted points map to -1).  HD: deleted entries
+// are dropped and the row is refilled with random points (draws (i, t, 10,
+// s)), whose distances are computed; the row is re-sorted by (d2, id) when
+// anything in it changed, and recalibrated (flag set) when an entry was
+// dropped.  LD: surviving entries keep their order, refills (draws
+// (i, t, 11, s)) follow.
+// ---------------------------------------------------------------------------
+__global__ void k_move_rows(uint8_t* base, const int32_t* src, const int32_t* dst, int32_t m,
+                            int32_t rowbytes) {
+  const int64_t total = (int64_t)m * rowbytes;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = q / rowbytes, b = q % rowbytes;
+    base[(int64_t)dst[k] * rowbytes + b] = base[(int64_t)src[k] * rowbytes + b];
+  }
+}
+
+template <typename TX, int VEC, int CH>
+__global__ __launch_bounds__(kBlock) void k_delete_fix(StepArgs a, const int32_t* newid) {
+  __shared__ WaveLds lds_all[kWavesPerBlock];
+  WaveLds& S = lds_all[threadIdx.x / kWave];
+  const int32_t i = (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  if (i >= a.N) return;
+  const int lane = lane_id();
+  const int Kh = a.Kh, Kl = a.Kl;
+  const uint32_t t = a.sc->t;
+  int32_t* hl = a.hd_idx[a.sc->hd_cur];
+  float* hd = a.hd_d2[a.sc->hd_cur];
+  int32_t* ll = a.ld_idx[t & 1u];
+  // LD list: survivors in order, then refills
+  {
+    const int id = lane < Kl ? ll[(int64_t)i * Kl + lane] : -1;
+    const int nid = id >= 0 ? newid[id] : -1;
+    const uint64_t keep = __ballot(nid >= 0);
+    const int nk = __popcll(keep);
+    if (nid >= 0) S.lst[popc_below(keep, lane)] = nid;
+    wave_lds_sync();
+    if (nk < Kl) random_list(i, a.N, Kl, kStreamDelLD, t, a.h, S.lst, nk);
+    if (lane < Kl) ll[(int64_t)i * Kl + lane] = S.lst[lane];
+    wave_lds_sync();
+  }
+  // HD list
+  const int id = lane < Kh ? hl[(int64_t)i * Kh + lane] : -1;
+  const int nid = id >= 0 ? newid[id] : -1;
+  const float od2 = lane < Kh ? hd[(int64_t)i * Kh + lane] : kInf;
+  const uint64_t keep = __ballot(nid >= 0);
+  const int nk = __popcll(keep);
+  const bool remapped = __ballot(lane < Kh && nid != id) != 0ull;
+  if (!remapped) return;
+  if (nid >= 0) {
+    S.lst[popc_below(keep, lane)] = nid;
+    S.row[popc_below(keep, lane)] = od2;
+  }
+  wave_lds_sync();
+  if (nk < Kh) random_list(i, a.N, Kh, kStreamDelHD, t, a.h, S.lst, nk);
+  const int e = lane < Kh ? S.lst[lane] : -1;
+  const float keptd = lane < nk ? S.row[lane] : kInf;
+  wave_lds_sync();
+  // distances of the refills (lanes nk .. Kh-1), packed to lanes 0 .. Kh-nk-1
+  const int fresh = (lane >= nk && lane < Kh) ? e : -1;
+  int cid = __shfl(fresh, (lane + nk) & (kWave - 1));
+  if (lane >= Kh - nk) cid = -1;
+  hd_dist_rows<TX, VEC, CH>(static_cast<const TX*>(a.X), a.D, i, cid, Kh - nk, S.d2);
+  const float dd = lane < nk ? keptd : (lane < Kh ? S.d2[(lane - nk) & (kWave - 1)] : kInf);
+  int ra, rb;
+  rank_two(dd, lane < Kh ? e : kNoId, kInf, kNoId, Kh, 0, S.key, ra, rb);
+  if (lane < Kh) {
+    hl[(int64_t)i * Kh + ra] = e;
+    hd[(int64_t)i * Kh + ra] = dd;
+    S.d2[ra] = dd;
+  }
+  wave_lds_sync();
+  if (nk < Kh) {
+    const float sorted = lane < Kh ? S.d2[lane] : 0.0f;
+    const float4 r = calibrate_row(sorted, Kh, a.h, a.rec[i].x);
+    if (lane == 0) {
+      a.rec[i] = r;
+      a.flags[i] = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
 static inline unsigned wave_blocks(int64_t n) {
@@ -1105,6 +1191,27 @@ struct DriftLaunch {
     return hipGetLastError();
   }
 };
+
+template <typename TX, int VEC, int CH>
+struct DeleteLaunch {
+  static hipError_t run(const StepArgs& a, const int32_t* newid, hipStream_t s) {
+    hipLaunchKernelGGL((k_delete_fix<TX, VEC, CH>), dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a,
+                       newid);
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_delete_fix(const StepArgs& a, const int32_t* newid, hipStream_t s) {
+  return dispatch_x<DeleteLaunch>(a, newid, s);
+}
+
+hipError_t launch_move_rows(void* base, const int32_t* src, const int32_t* dst, int32_t m,
+                            int32_t row_bytes, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_move_rows, dim3(1024), dim3(256), 0, s, static_cast<uint8_t*>(base), src,
+                     dst, m, row_bytes);
+  return hipGetLastError();
+}
 
 hipError_t launch_init_lists(const StepArgs& a, int32_t i0, int32_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

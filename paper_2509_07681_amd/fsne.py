@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH):
     L.fsne_drift_points.argtypes = [P, P, P, I64, P]
     L.fsne_implode.argtypes = [P, F]
     L.fsne_jump_start.argtypes = [P, I32, F]
+    L.fsne_delete_points.argtypes = [P, P, I64]
     L.fsne_destroy.argtypes = [P]
     L.fsne_destroy.restype = None
     L.fsne_last_error.argtypes = [P]
@@ -81,7 +82,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("fsne_default_hparams", "fsne_init", "fsne_step", "fsne_set_hyperparams",
                  "fsne_get_hyperparams", "fsne_get_Y", "fsne_get_knn", "fsne_get_state",
                  "fsne_set_state", "fsne_get_stats", "fsne_sync", "fsne_insert_points",
-                 "fsne_drift_points", "fsne_implode", "fsne_jump_start"):
+                 "fsne_drift_points", "fsne_implode", "fsne_jump_start", "fsne_delete_points"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -249,6 +250,11 @@ def fsne_implode(ctx, factor: float):
     _check(ctx, load_library().fsne_implode(ctx, float(factor)))
 
 
+def fsne_delete_points(ctx, ids):
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    _check(ctx, load_library().fsne_delete_points(ctx, _ptr(ids), ids.size))
+
+
 def fsne_jump_start(ctx, projection: int, sigma: float):
     _check(ctx, load_library().fsne_jump_start(ctx, int(projection), float(sigma)))
 
@@ -302,6 +308,10 @@ class Embedding:
 
     def implode(self, factor):
         fsne_implode(self.ctx, factor)
+
+    def delete(self, ids):
+        fsne_delete_points(self.ctx, ids)
+        self.N -= np.asarray(ids).size
 
     def jump_start(self, projection=0, sigma=1e-2):
         fsne_jump_start(self.ctx, projection, sigma)

@@ -319,3 +319,39 @@ def test_bf16_screen_against_direct_and_oracle(oracle_lib, fsne_lib, name):
     assert lost_rows <= 0.005 * 4 * X.shape[0], lost_rows
     direct.close()
     screened.close()
+
+
+@pytest.mark.parametrize("name", ["blobs_2000", "manifold_4003_bf16", "odd_dims_777"])
+def test_delete_matches_oracle(oracle_lib, fsne_lib, name):
+    """Deleting points: the same renumbering, list rewrite and recalibration
+    on both sides, then one more iteration from the reduced state."""
+    O, F = oracle_lib, fsne_lib
+    X, c, S, emb, hp_o, hp_g = _setup(O, F, name, hd_mode=1)
+    for _ in range(3):
+        S.step(hp_o)
+    emb.set_state(S.as_gpu_state())
+    rng = np.random.default_rng(5)
+    N0 = S.N
+    ids = rng.choice(N0, N0 // 7, replace=False)
+    S.delete(hp_o, ids)
+    emb.delete(ids)
+    assert emb.stats()["N"] == S.N
+    g = emb.state()
+    Xl = S.X[:S.N]
+    np.testing.assert_array_equal(g["Y"], S.live("Y").astype(np.float32))
+    np.testing.assert_array_equal(g["ld_idx"], S.live("ld_idx"))
+    same = _check_hd(Xl, c, g, S, X.dtype == np.uint16)
+    np.testing.assert_array_equal(g["flags"][same], S.live("flags")[same])
+    rec_o = np.stack([S.live("beta"), S.live("m"), S.live("r"), S.live("invS")], 1)
+    assert rel_l2(g["rec"][same, 0], rec_o[same, 0]) < 1e-4
+    clean = _clean_affinity(S, g["hd_idx"], same)
+    assert clean.mean() > 0.95
+    assert rel_l2(g["P"][clean], S.live("P")[clean]) < 1e-4
+    # the next iteration from the reduced state
+    emb.set_state(S.as_gpu_state())
+    S.step(hp_o)
+    emb.step(1)
+    g = emb.state()
+    same = _check_hd(Xl, c, g, S, X.dtype == np.uint16)
+    assert np.all(np.isfinite(g["Y"])) and emb.stats()["nonfinite"] == 0
+    emb.close()

@@ -445,3 +445,48 @@ def test_jump_start_invariances_and_projections(oracle_lib):
     S4 = _js_state(O, np.ones((50, 20), np.float32))
     S4.jump_start(0, 1.0)
     assert np.all(S4.live("Y") == 0.0)
+
+
+# --- point deletion ------------------------------------------------------------
+def test_delete_keeps_a_consistent_state(oracle_lib):
+    """After deleting points every list entry is a live point other than the
+    row's own, rows are unique and sorted by (d2, id), every HD distance is
+    the true distance between the renumbered rows, survivors keep their
+    coordinates, and recalibrated rows hit the perplexity."""
+    O = oracle_lib
+    rng = np.random.default_rng(8)
+    N, D, d, Kh, Kl, perp = 600, 12, 2, 16, 8, 5.0
+    X = rng.normal(size=(N, D)).astype(np.float32)
+    Y0 = rng.normal(size=(N, d)).astype(np.float32)
+    hp = O.Hyper(perplexity=perp, lr=50.0, n_neg=4, hd_mode=1)
+    S = O.OracleState(X, d, Kh, Kl, 9, Y0).init(hp)
+    for _ in range(5):
+        S.step(hp)
+    Yb, Xb = S.live("Y").copy(), S.live("X").copy()
+    ids = rng.choice(N, 90, replace=False)
+    newid = S.delete(hp, ids)
+    N1 = N - 90
+    assert S.N == N1
+    alive = newid >= 0
+    assert alive.sum() == N1 and np.all(newid[ids] == -1)
+    np.testing.assert_array_equal(np.sort(newid[alive]), np.arange(N1))
+    np.testing.assert_array_equal(S.live("Y")[newid[alive]], Yb[alive])
+    np.testing.assert_array_equal(S.live("X")[newid[alive]], Xb[alive])
+    H, Hd, L = S.live("hd_idx"), S.live("hd_d2"), S.live("ld_idx")
+    for i in range(N1):
+        for row in (H[i], L[i]):
+            assert np.all((row >= 0) & (row < N1)) and i not in row
+            assert len(set(row.tolist())) == row.size
+        Xl = S.live("X").astype(np.float64)
+        true = ((Xl[H[i]] - Xl[i]) ** 2).sum(1)
+        np.testing.assert_allclose(Hd[i], true, rtol=1e-12, atol=1e-12)
+        order = np.lexsort((H[i], Hd[i]))
+        np.testing.assert_array_equal(order, np.arange(Kh))
+    flagged = np.nonzero(S.live("flags") == 1)[0]
+    assert flagged.size > 0
+    for i in flagged[:50]:
+        p = np.exp(-S.beta[i] * (Hd[i] - S.m[i])) * S.invS[i]
+        assert abs(-(p * np.log(p)).sum() - np.log(perp)) < 1e-8
+    assert S.live("P").sum() <= 1.0 + 1e-9
+    S.step(hp)          # the state still steps
+    assert np.all(np.isfinite(S.live("Y")))
