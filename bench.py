@@ -186,6 +186,68 @@ def feedback_run(F, args):
     return out
 
 
+def hierarchy_run(F, args):
+    """The hierarchy graph of Sec. 4.2 on a two-level Gaussian mixture (4 top
+    clusters of 4 sub-clusters, 1000 points each, D = 50) embedded in d = 4:
+    after 1000 iterations at alpha = 1, alpha is lowered level by level (the
+    LD tails get heavier); at each level the embedding runs 400 iterations
+    and is clustered (DBSCAN on the LD lists, min_pts 20, eps twice the
+    median distance to the 30th nearest neighbour in the embedding, measured
+    on a sample); edges link clusters of consecutive levels with weight
+    |A and B| / min(|A|, |B|).  Each level also reports the agreement (ARI)
+    of the list-based clusters with exact DBSCAN on the same snapshot."""
+    import numpy as np
+    from sklearn.cluster import DBSCAN
+    from sklearn.metrics import adjusted_rand_score
+
+    from inputs.generators import RUN_SEED, hierarchy_mixture, y_init
+
+    X, top, leaf = hierarchy_mixture()
+    N, d, K = X.shape[0], 4, 32
+    alphas = [1.0, 0.7, 0.5, 0.35, 0.25, 0.18]
+    base = dict(alpha=1.0, perplexity=10.0, lr=N / 12.0, n_neg=16, hd_mode=0)
+    emb = F.Embedding(X, y_init(N, d), d, K, K, seed=RUN_SEED, hp=schedule(F, base, 0))
+    emb.step(250)
+    emb.set_hyperparams(schedule(F, base, 250))
+    emb.step(750)
+    rng = np.random.default_rng(5)
+    sample = rng.choice(N, 2000, replace=False)
+    levels, labels = [], []
+    for a in alphas:
+        emb.set_hyperparams(F.fsne_default_hparams(**{**schedule(F, base, 1000).as_dict(),
+                                                      "alpha": a}))
+        emb.step(400)
+        Y = emb.Y().astype(np.float64)
+        d2 = ((Y[sample][:, None, :] - Y[None, :, :]) ** 2).sum(-1)
+        kth = np.sqrt(np.sort(d2, axis=1)[:, 30])         # column 0 is the point itself
+        eps = float(2.0 * np.median(kth))
+        t0 = time.perf_counter()
+        lab, nc = emb.cluster(eps, 20)
+        ms = (time.perf_counter() - t0) * 1e3
+        ok = lab >= 0
+        exact = DBSCAN(eps=eps, min_samples=20).fit(Y).labels_
+        levels.append({"alpha": a, "eps": round(eps, 4), "clusters": nc,
+                       "noise": round(float(1 - ok.mean()), 4),
+                       "ari_top": round(adjusted_rand_score(top[ok], lab[ok]), 4),
+                       "ari_leaf": round(adjusted_rand_score(leaf[ok], lab[ok]), 4),
+                       "exact_dbscan_clusters": int(exact.max() + 1),
+                       "ari_vs_exact_dbscan": round(adjusted_rand_score(exact, lab), 4),
+                       "cluster_ms": round(ms, 2)})
+        labels.append((lab, nc))
+    edges = []
+    for g in range(len(labels) - 1):
+        (la, ca), (lb, cb) = labels[g], labels[g + 1]
+        E = F.fsne_hierarchy_edges(la, ca, lb, cb)
+        for i, j in zip(*np.nonzero(E >= 0.5)):
+            edges.append([g, int(i), g + 1, int(j), round(float(E[i, j]), 3),
+                          int((la == i).sum()), int((lb == j).sum())])
+    emb.close()
+    return {"metric": "alpha-sweep hierarchy graph: clusters per level and edges",
+            "config": {"workload": f"two-level Gaussian mixture, N={N}, D=50, 4 x 4 clusters, "
+                                   f"d={d}, K_hd=K_ld={K}"},
+            "levels": levels, "edges_ge_0.5": edges}
+
+
 def gather_probe(row_bytes, rows_per_wave, table_bytes, nwaves=1_000_000, reps=5):
     """Random-row gather ceiling: rows/s and bytes/s at which the GPU gathers
     rows of row_bytes from random positions of a table, one wave per point as
@@ -399,6 +461,8 @@ def main():
     ap.add_argument("--no-dynamic", action="store_true", help="skip the online-use experiment")
     ap.add_argument("--feedback", action="store_true",
                     help="run the feedback-loop experiment (fixed vs optimised embedding) instead")
+    ap.add_argument("--hierarchy", action="store_true",
+                    help="run the alpha-sweep hierarchy graph experiment instead")
     ap.add_argument("--fb-n", type=int, default=50000)
     ap.add_argument("--fb-iters", type=int, default=2000)
     ap.add_argument("--fb-every", type=int, default=100)
@@ -443,6 +507,9 @@ def main():
         return
     if args.feedback:
         print(json.dumps(feedback_run(F, args)))
+        return
+    if args.hierarchy:
+        print(json.dumps(hierarchy_run(F, args)))
         return
 
     X, _, cfg = make_workload("manifold_1m")

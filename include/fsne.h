@@ -193,6 +193,31 @@ fsne_status fsne_drift_points(fsne_ctx *ctx, const int64_t *ids, const void *Xne
  * Errors: FSNE_EINVAL, FSNE_ESTATE (X borrowed), FSNE_ENOMEM, FSNE_EHIP. */
 fsne_status fsne_delete_points(fsne_ctx *ctx, const int64_t *ids, int64_t n);
 
+/* Clusters of the current embedding for the hierarchy graph (Sec. 4.2):
+ * DBSCAN (Ester et al. 1996) with each point's eps-neighbourhood read from
+ * its LD neighbour list:
+ *   N(i) = {i} + {j in LD list of i : |y_i - y_j|^2 <= eps^2},
+ *   core points: |N(i)| >= min_pts (1 <= min_pts <= K_ld + 1);
+ *   clusters: connected components of the core points, linked when either
+ *   lies in the other's N; a non-core point within eps of a core point (in
+ *   either list) joins the nearest one's cluster (ties: smaller cluster);
+ *   the rest is noise.
+ * Squared distances are summed in index order in FP32 without fused
+ * multiply-add.  labels (host, N) get 0 .. n_clusters-1, numbered by the
+ * smallest index among each cluster's core points, or -1 for noise;
+ * *n_clusters (may be NULL) gets the count.  Synchronises the stream.
+ * Errors: FSNE_EINVAL, FSNE_EHIP. */
+fsne_status fsne_cluster(fsne_ctx *ctx, float eps, int32_t min_pts, int32_t *labels,
+                         int32_t *n_clusters);
+
+/* Edges of the hierarchy graph between two clusterings of the same n points
+ * (levels g and h = g + 1, Sec. 4.2): E[i cb + j] = |A_i and B_j| /
+ * min(|A_i|, |B_j|) for cluster i of la (ca clusters) and j of lb (cb
+ * clusters), 0 when either is empty; label -1 (noise) belongs to no
+ * cluster.  Host arrays; pure host code.  Errors: FSNE_EINVAL. */
+fsne_status fsne_hierarchy_edges(const int32_t *la, int32_t ca, const int32_t *lb, int32_t cb,
+                                 int64_t n, float *E);
+
 /* Scale the embedding down by factor (> 0): Y <- Y / factor, V <- V / factor
  * (Sec. 3, the "implosion" control).  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_implode(fsne_ctx *ctx, float factor);

@@ -24,6 +24,7 @@ __all__ = [
     "image_like",
     "image_like_prototypes",
     "image_styles",
+    "hierarchy_mixture",
     "manifolds",
     "zipf_mixture",
     "y_init",
@@ -133,6 +134,21 @@ def image_styles(classes: np.ndarray, seed: int, proto_seed: int = 1002, D: int 
             x = proto[c] + z[r] @ S[c].T + rng.normal(0.0, jitter, size=(r.size, D))
             X[r] = np.where(on[c], np.clip(x, 0.0, 1.0), 0.0)
     return X, lab.astype(np.int32)
+
+
+def hierarchy_mixture(n_top: int = 4, n_sub: int = 4, per_leaf: int = 1000, D: int = 50,
+                      top_scale: float = 10.0, sub_scale: float = 0.6, seed: int = 1006):
+    """Two-level Gaussian mixture (a hierarchy of clusters): top centres
+    ~ N(0, top_scale^2 I), each with n_sub sub-centres ~ top + N(0, sub_scale^2 I),
+    points ~ sub-centre + N(0, I).  Returns X (float32) and the top and leaf
+    labels, rows shuffled."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    top = rng.normal(0.0, top_scale, size=(n_top, D))
+    sub = top[:, None, :] + rng.normal(0.0, sub_scale, size=(n_top, n_sub, D))
+    leaf = np.repeat(np.arange(n_top * n_sub), per_leaf)
+    X = sub.reshape(-1, D)[leaf] + rng.normal(size=(leaf.size, D))
+    X, leaf = _shuffle(rng, X.astype(np.float32), leaf.astype(np.int32))
+    return np.ascontiguousarray(X), (leaf // n_sub).astype(np.int32), leaf
 
 
 def manifolds(n_manifolds: int = 50, per_manifold: int = 20000, D: int = 128,

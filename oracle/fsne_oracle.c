@@ -832,6 +832,86 @@ void fsneo_delete_fix(fsneo_state *S, const fsneo_hp *hp, const int32_t *newid)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Clustering for the hierarchy graph (Sec. 4.2): DBSCAN (Ester, Kriegel,   */
+/* Sander, Xu 1996) with each point's eps-neighbourhood taken from its LD   */
+/* list: N(i) = {i} + {j in L_i : d2(i, j) <= eps^2} (d2 as the LD          */
+/* decision distance), core points have |N(i)| >= min_pts, clusters are the */
+/* connected components of the core points (linked when either is in the   */
+/* other's N), a non-core point within eps of a core point (in either list) */
+/* joins the cluster of the nearest one (ties: smaller cluster), the rest   */
+/* is noise (-1).  Clusters are numbered 0, 1, ... by the smallest index  */
+/* among their core points.  Returns the number of clusters.                */
+/* ------------------------------------------------------------------------ */
+static int64_t uf_find(int64_t *parent, int64_t a)
+{
+    while (parent[a] != a) {
+        parent[a] = parent[parent[a]];
+        a = parent[a];
+    }
+    return a;
+}
+
+int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t *labels)
+{
+    const int64_t N = S->N;
+    const int32_t K = S->K_ld, d = S->d;
+    volatile float e = eps;
+    const float eps2 = e * e;
+    uint8_t *core = calloc((size_t)N, 1);
+    int64_t *parent = malloc(sizeof(int64_t) * (size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        int cnt = 1;
+        for (int32_t k = 0; k < K; ++k)
+            cnt += ld_dist2_decision(S->Y, d, i, S->ld_idx[i * K + k]) <= eps2;
+        core[i] = cnt >= min_pts;
+        parent[i] = i;
+    }
+    /* union by smaller root: every root is its component's smallest index */
+    for (int64_t i = 0; i < N; ++i) {
+        if (!core[i]) continue;
+        for (int32_t k = 0; k < K; ++k) {
+            int64_t j = S->ld_idx[i * K + k];
+            if (!core[j] || ld_dist2_decision(S->Y, d, i, j) > eps2) continue;
+            int64_t a = uf_find(parent, i), b = uf_find(parent, j);
+            if (a < b) parent[b] = a;
+            else if (b < a) parent[a] = b;
+        }
+    }
+    float *bd = malloc(sizeof(float) * (size_t)N);
+    int64_t *bl = malloc(sizeof(int64_t) * (size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        bd[i] = INFINITY;
+        bl[i] = -1;
+    }
+    for (int64_t i = 0; i < N; ++i)
+        for (int32_t k = 0; k < K; ++k) {
+            int64_t j = S->ld_idx[i * K + k];
+            if (core[i] == core[j]) continue;
+            float q = ld_dist2_decision(S->Y, d, i, j);
+            if (q > eps2) continue;
+            int64_t border = core[i] ? j : i, owner = core[i] ? i : j;
+            int64_t lab = uf_find(parent, owner);
+            if (q < bd[border] || (q == bd[border] && lab < bl[border])) {
+                bd[border] = q;
+                bl[border] = lab;
+            }
+        }
+    int64_t *dense = malloc(sizeof(int64_t) * (size_t)N);
+    int32_t nc = 0;
+    for (int64_t i = 0; i < N; ++i) dense[i] = (core[i] && uf_find(parent, i) == i) ? nc++ : -1;
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t root = core[i] ? uf_find(parent, i) : bl[i];
+        labels[i] = root >= 0 ? (int32_t)dense[root] : -1;
+    }
+    free(core);
+    free(parent);
+    free(bd);
+    free(bl);
+    free(dense);
+    return nc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Jump start (Sec. 3, paragraph on helping the first iterations): the       */
 /* embedding becomes a random linear projection of the centred data,        */
 /*   y_ic = s sum_k (x_ik - mu_k) r_kc,                                      */

@@ -104,6 +104,8 @@ def lib():
         L.fsneo_jump_start.restype = None
         L.fsneo_delete_fix.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P]
         L.fsneo_delete_fix.restype = None
+        L.fsneo_cluster.argtypes = [C.POINTER(_State), C.c_float, C.c_int32, P]
+        L.fsneo_cluster.restype = C.c_int32
         L.fsneo_mlp_nparams.argtypes = [C.POINTER(_MlpDims)]
         L.fsneo_mlp_nparams.restype = C.c_int64
         L.fsneo_mlp_init.argtypes = [C.POINTER(_MlpDims), C.c_uint64, P]
@@ -310,6 +312,12 @@ class OracleState:
         s = self.cstate()
         lib().fsneo_delete_fix(C.byref(s), C.byref(hp.c()), _p(newid))
         return newid
+
+    def cluster(self, eps: float, min_pts: int):
+        labels = np.empty(self.N, dtype=np.int32)
+        s = self.cstate()
+        nc = lib().fsneo_cluster(C.byref(s), float(eps), int(min_pts), _p(labels))
+        return labels, int(nc)
 
     def jump_start(self, projection: int = 0, sigma: float = 1e-2):
         s = self.cstate()

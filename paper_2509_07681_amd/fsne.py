@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     L.fsne_implode.argtypes = [P, F]
     L.fsne_jump_start.argtypes = [P, I32, F]
     L.fsne_delete_points.argtypes = [P, P, I64]
+    L.fsne_cluster.argtypes = [P, F, I32, P, P]
+    L.fsne_hierarchy_edges.argtypes = [P, I32, P, I32, I64, P]
     L.fsne_destroy.argtypes = [P]
     L.fsne_destroy.restype = None
     L.fsne_last_error.argtypes = [P]
@@ -82,7 +84,8 @@ def load_library(path: str = LIB_PATH):
     for name in ("fsne_default_hparams", "fsne_init", "fsne_step", "fsne_set_hyperparams",
                  "fsne_get_hyperparams", "fsne_get_Y", "fsne_get_knn", "fsne_get_state",
                  "fsne_set_state", "fsne_get_stats", "fsne_sync", "fsne_insert_points",
-                 "fsne_drift_points", "fsne_implode", "fsne_jump_start", "fsne_delete_points"):
+                 "fsne_drift_points", "fsne_implode", "fsne_jump_start", "fsne_delete_points",
+                 "fsne_cluster", "fsne_hierarchy_edges"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -255,6 +258,23 @@ def fsne_delete_points(ctx, ids):
     _check(ctx, load_library().fsne_delete_points(ctx, _ptr(ids), ids.size))
 
 
+def fsne_cluster(ctx, N, eps: float, min_pts: int):
+    labels = np.empty(N, dtype=np.int32)
+    nc = np.zeros(1, dtype=np.int32)
+    _check(ctx, load_library().fsne_cluster(ctx, float(eps), int(min_pts), _ptr(labels), _ptr(nc)))
+    return labels, int(nc[0])
+
+
+def fsne_hierarchy_edges(la, ca: int, lb, cb: int):
+    la = np.ascontiguousarray(la, dtype=np.int32)
+    lb = np.ascontiguousarray(lb, dtype=np.int32)
+    E = np.zeros((ca, cb), dtype=np.float32)
+    st = load_library().fsne_hierarchy_edges(_ptr(la), int(ca), _ptr(lb), int(cb), la.size, _ptr(E))
+    if st != FSNE_OK:
+        raise FsneError(st, "fsne_hierarchy_edges: bad arguments")
+    return E
+
+
 def fsne_jump_start(ctx, projection: int, sigma: float):
     _check(ctx, load_library().fsne_jump_start(ctx, int(projection), float(sigma)))
 
@@ -312,6 +332,9 @@ class Embedding:
     def delete(self, ids):
         fsne_delete_points(self.ctx, ids)
         self.N -= np.asarray(ids).size
+
+    def cluster(self, eps, min_pts):
+        return fsne_cluster(self.ctx, self.N, eps, min_pts)
 
     def jump_start(self, projection=0, sigma=1e-2):
         fsne_jump_start(self.ctx, projection, sigma)

@@ -71,3 +71,17 @@ def test_defaults_and_argument_checks(fsne_lib):
     assert L.fsne_sync(None) == F.FSNE_EINVAL
     L.fsne_destroy(None)
     assert L.fsne_last_error(None) == b"null context"
+
+
+def test_hierarchy_edges_worked_example(fsne_lib):
+    """Host-only entry point: overlap of clusters over the smaller size.
+    Level g: A0 = {0,1,2,3}, A1 = {4,5}; level h: B0 = {0,1}, B1 = {2,3,4},
+    B2 = {5}; point 6 is noise at both levels.  By hand:
+      E[A0,B0] = 2/2, E[A0,B1] = 2/3, E[A0,B2] = 0/1,
+      E[A1,B0] = 0/2, E[A1,B1] = 1/2, E[A1,B2] = 1/1."""
+    F = fsne_lib
+    la = [0, 0, 0, 0, 1, 1, -1]
+    lb = [0, 0, 1, 1, 1, 2, -1]
+    E = F.fsne_hierarchy_edges(la, 2, lb, 3)
+    want = np.array([[1.0, 2 / 3, 0.0], [0.0, 0.5, 1.0]], dtype=np.float32)
+    np.testing.assert_allclose(E, want, rtol=1e-7)

@@ -490,3 +490,44 @@ def test_delete_keeps_a_consistent_state(oracle_lib):
     assert S.live("P").sum() <= 1.0 + 1e-9
     S.step(hp)          # the state still steps
     assert np.all(np.isfinite(S.live("Y")))
+
+
+# --- clustering for the hierarchy graph ----------------------------------------
+def test_cluster_equals_dbscan_on_exact_lists(oracle_lib):
+    """With exact LD neighbour lists holding every eps-neighbour, the clusters
+    are DBSCAN's (scikit-learn): same noise, same partition of the core
+    points, border points in the cluster of a core point within eps."""
+    from sklearn.cluster import DBSCAN
+
+    O = oracle_lib
+    rng = np.random.default_rng(12)
+    d, K, min_pts = 4, 48, 5
+    cent = rng.normal(scale=12.0, size=(5, d))
+    Y = np.concatenate([c + rng.normal(scale=s, size=(250, d))
+                        for c, s in zip(cent, (0.3, 0.4, 0.5, 0.4, 0.3))] +
+                       [rng.uniform(-25, 25, size=(60, d))])
+    Y = Y.astype(np.float32).astype(np.float64)
+    N = Y.shape[0]
+    D2 = ((Y[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(D2, np.inf)
+    knn = np.argsort(D2, axis=1, kind="stable")[:, :K]
+    eps = 0.33
+    assert ((D2 <= eps * eps).sum(1) <= K).all()           # lists hold every eps-neighbour
+    assert np.abs(np.sqrt(D2[np.isfinite(D2)]) - eps).min() > 1e-5   # no pair at the boundary
+    S = O.OracleState(np.zeros((N, 3), np.float32), d, 8, K, 1, Y.astype(np.float32))
+    S.ld_idx[:N] = knn
+    labels, nc = S.cluster(eps, min_pts)
+    ref = DBSCAN(eps=eps, min_samples=min_pts).fit(Y)
+    core = np.zeros(N, bool)
+    core[ref.core_sample_indices_] = True
+    np.testing.assert_array_equal(labels == -1, ref.labels_ == -1)
+    assert nc == len(set(ref.labels_[core]))
+    pairs = {(a, b) for a, b in zip(labels[core], ref.labels_[core])}
+    assert len(pairs) == nc                                   # a one-to-one renaming
+    for i in np.nonzero(~core & (labels >= 0))[0]:
+        near = core & (D2[i] <= eps * eps)
+        assert labels[i] in set(labels[near])
+    assert nc > 5 and core.sum() > 500
+    # clusters are numbered by the smallest index among their core points
+    firsts = [np.nonzero((labels == k) & core)[0].min() for k in range(nc)]
+    assert firsts == sorted(firsts)
