@@ -463,6 +463,8 @@ def main():
                     help="run the feedback-loop experiment (fixed vs optimised embedding) instead")
     ap.add_argument("--hierarchy", action="store_true",
                     help="run the alpha-sweep hierarchy graph experiment instead")
+    ap.add_argument("--gather-table", action="store_true",
+                    help="print the random-gather ceiling for several row sizes instead")
     ap.add_argument("--fb-n", type=int, default=50000)
     ap.add_argument("--fb-iters", type=int, default=2000)
     ap.add_argument("--fb-every", type=int, default=100)
@@ -510,6 +512,13 @@ def main():
         return
     if args.hierarchy:
         print(json.dumps(hierarchy_run(F, args)))
+        return
+    if args.gather_table:
+        # random-gather ceilings for the row sizes the step kernels gather
+        for rb, rows, table in ((16, 128, 2 ** 24), (64, 112, 2 ** 26), (128, 64, 2 ** 27),
+                                (256, 32, 2 ** 28), (256, 32, 2 ** 31), (512, 32, 2 ** 29),
+                                (512, 32, 2 ** 32)):
+            print(json.dumps(gather_probe(rb, rows, table)), flush=True)
         return
 
     X, _, cfg = make_workload("manifold_1m")
