@@ -568,7 +568,11 @@ int fsneo_step(fsneo_state *S, const fsneo_hp *hp, fsneo_stats *st, double *A_ou
     if (fired) {
         int32_t *ni = malloc(sizeof(int32_t) * N * Kh);
         double *nd = malloc(sizeof(double) * N * Kh);
-        if (!ni || !nd) return -2;
+        if (!ni || !nd) {
+            free(ni);
+            free(nd);
+            return -2;
+        }
 #pragma omp parallel for schedule(dynamic, 256)
         for (int64_t i = 0; i < N; ++i)
             fsneo_hd_refine_point(S, i, t, ni + i * Kh, nd + i * Kh, S->flags + i);
@@ -586,7 +590,13 @@ int fsneo_step(fsneo_state *S, const fsneo_hp *hp, fsneo_stats *st, double *A_ou
     double *A = malloc(sizeof(double) * N * d);
     double *R = malloc(sizeof(double) * N * d);
     double *Zh = malloc(sizeof(double) * N);
-    if (!nl || !A || !R || !Zh) return -2;
+    if (!nl || !A || !R || !Zh) {
+        free(nl);
+        free(A);
+        free(R);
+        free(Zh);
+        return -2;
+    }
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < N; ++i)
         fsneo_ld_refine_grad_point(S, hp, i, t, S->hd_idx, S->P, nl + i * Kl, A + i * d,
@@ -840,7 +850,8 @@ void fsneo_delete_fix(fsneo_state *S, const fsneo_hp *hp, const int32_t *newid)
 /* other's N), a non-core point within eps of a core point (in either list) */
 /* joins the cluster of the nearest one (ties: smaller cluster), the rest   */
 /* is noise (-1).  Clusters are numbered 0, 1, ... by the smallest index  */
-/* among their core points.  Returns the number of clusters.                */
+/* among their core points.  Returns the number of clusters (-2: out of   */
+/* memory).                                                                 */
 /* ------------------------------------------------------------------------ */
 static int64_t uf_find(int64_t *parent, int64_t a)
 {
@@ -859,6 +870,17 @@ int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t 
     const float eps2 = e * e;
     uint8_t *core = calloc((size_t)N, 1);
     int64_t *parent = malloc(sizeof(int64_t) * (size_t)N);
+    float *bd = malloc(sizeof(float) * (size_t)N);
+    int64_t *bl = malloc(sizeof(int64_t) * (size_t)N);
+    int64_t *dense = malloc(sizeof(int64_t) * (size_t)N);
+    if (!core || !parent || !bd || !bl || !dense) {
+        free(core);
+        free(parent);
+        free(bd);
+        free(bl);
+        free(dense);
+        return -2;
+    }
     for (int64_t i = 0; i < N; ++i) {
         int cnt = 1;
         for (int32_t k = 0; k < K; ++k)
@@ -877,8 +899,6 @@ int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t 
             else if (b < a) parent[a] = b;
         }
     }
-    float *bd = malloc(sizeof(float) * (size_t)N);
-    int64_t *bl = malloc(sizeof(int64_t) * (size_t)N);
     for (int64_t i = 0; i < N; ++i) {
         bd[i] = INFINITY;
         bl[i] = -1;
@@ -896,7 +916,6 @@ int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t 
                 bl[border] = lab;
             }
         }
-    int64_t *dense = malloc(sizeof(int64_t) * (size_t)N);
     int32_t nc = 0;
     for (int64_t i = 0; i < N; ++i) dense[i] = (core[i] && uf_find(parent, i) == i) ? nc++ : -1;
     for (int64_t i = 0; i < N; ++i) {
@@ -920,12 +939,17 @@ int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t 
 /* sqrt(tr Sigma) with tr Sigma = (1/N) sum_i |x_i - mu|^2 (s = 0 when it is */
 /* 0), so every coordinate has variance about sigma^2.  V = 0.               */
 /* ------------------------------------------------------------------------ */
-void fsneo_jump_start(fsneo_state *S, int32_t projection, double sigma)
+int fsneo_jump_start(fsneo_state *S, int32_t projection, double sigma)
 {
     const int64_t N = S->N;
     const int32_t D = S->D, d = S->d;
     double *mu = calloc((size_t)D, sizeof(double));
     double *r = malloc(sizeof(double) * (size_t)D * (size_t)d);
+    if (!mu || !r) {
+        free(mu);
+        free(r);
+        return -2;
+    }
     for (int64_t i = 0; i < N; ++i)
         for (int32_t k = 0; k < D; ++k) mu[k] += xval(S->X, S->xdtype, i * D + k);
     for (int32_t k = 0; k < D; ++k) mu[k] /= (double)N;
@@ -956,6 +980,7 @@ void fsneo_jump_start(fsneo_state *S, int32_t projection, double sigma)
         }
     free(mu);
     free(r);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -95,7 +95,7 @@ void fsneo_knn_exact(const void *X, int32_t xdtype, int64_t N, int32_t D,
 int fsneo_insert(fsneo_state *S, const fsneo_hp *hp, int64_t n_new, const double *Y_new);
 int fsneo_drift(fsneo_state *S, const fsneo_hp *hp, const int64_t *ids, int64_t n,
                 const double *Y_new);
-void fsneo_jump_start(fsneo_state *S, int32_t projection, double sigma);
+int fsneo_jump_start(fsneo_state *S, int32_t projection, double sigma);
 void fsneo_delete_fix(fsneo_state *S, const fsneo_hp *hp, const int32_t *newid);
 int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t *labels);
 int fsneo_num_threads(void);

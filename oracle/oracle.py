@@ -101,7 +101,7 @@ def lib():
         L.fsneo_drift.restype = C.c_int
         L.fsneo_num_threads.restype = C.c_int
         L.fsneo_jump_start.argtypes = [C.POINTER(_State), C.c_int32, C.c_double]
-        L.fsneo_jump_start.restype = None
+        L.fsneo_jump_start.restype = C.c_int
         L.fsneo_delete_fix.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P]
         L.fsneo_delete_fix.restype = None
         L.fsneo_cluster.argtypes = [C.POINTER(_State), C.c_float, C.c_int32, P]
@@ -317,11 +317,14 @@ class OracleState:
         labels = np.empty(self.N, dtype=np.int32)
         s = self.cstate()
         nc = lib().fsneo_cluster(C.byref(s), float(eps), int(min_pts), _p(labels))
+        if nc < 0:
+            raise MemoryError("fsneo_cluster")
         return labels, int(nc)
 
     def jump_start(self, projection: int = 0, sigma: float = 1e-2):
         s = self.cstate()
-        lib().fsneo_jump_start(C.byref(s), int(projection), float(sigma))
+        if lib().fsneo_jump_start(C.byref(s), int(projection), float(sigma)) != 0:
+            raise MemoryError("fsneo_jump_start")
 
     # -- views --------------------------------------------------------------
     def live(self, name):
