@@ -72,7 +72,7 @@ def schedule(F, base, t):
                                      "momentum": 0.5 if early else 0.8})
 
 
-def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=100):
+def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=50):
     """n_iter iterations under the coin with the standard schedule; HD recall@K
     on the query sample every ``every`` iterations (the clock is stopped while
     the recall is measured)."""
@@ -106,10 +106,15 @@ def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=
 
 
 def seconds_to(curve, target):
-    """Step seconds at the first checkpoint whose recall reaches target (None if never)."""
+    """Step seconds at which the recall curve first reaches target, linearly
+    interpolated between the two checkpoints around the crossing (None if it
+    never does)."""
+    prev = (0, 0.0, 0.0)
     for it, secs, rec in curve:
         if rec >= target:
-            return secs
+            _, s0, r0 = prev
+            return round(s0 + (secs - s0) * (target - r0) / (rec - r0), 4) if rec > r0 else secs
+        prev = (it, secs, rec)
     return None
 
 

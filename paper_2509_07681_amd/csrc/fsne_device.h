@@ -378,4 +378,68 @@ __device__ inline float4 calibrate_row(float d2, int K, const Hyper& h, float be
   return make_float4(beta, m, r, 1.0f / S);
 }
 
+// ---------------------------------------------------------------------------
+// The same calibration for two rows at once, one per 32-lane half of the
+// wave (lanes < K of each half; K <= 32).  Every quantity of a half is
+// uniform within it; the sums over a half add the same values in the same
+// order as the single-row version, so a row gets the same result bit for
+// bit.  active: this half has a row to calibrate.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float half_sum_uniform(float v) {
+  v = group_sum_dpp(v, 32);   // lane 31 of each half holds the half's sum
+  return __shfl(v, (lane_id() & 32) + 31);
+}
+
+__device__ inline float4 calibrate_row_half(float d2, int K, const Hyper& h, float beta_prev,
+                                            bool active) {
+  const int lane = lane_id(), hbase = lane & 32, hl = lane & 31;
+  const bool act = hl < K;
+  const float m = __shfl(d2, hbase);
+  const float r = __shfl(d2, hbase + K - 1);
+  const float D = act ? d2 - m : 0.0f;
+  const int ties = __popc((uint32_t)(__ballot(act && D == 0.0f) >> hbase));
+  float4 special = make_float4(0.0f, m, r, 1.0f / (float)K);
+  bool done = !active, fixed = false;
+  if (!done && !(r > m)) {
+    done = fixed = true;
+  } else if (!done && (float)ties >= h.perplexity) {
+    special = make_float4(1e30f, m, r, 1.0f / (float)ties);
+    done = fixed = true;
+  }
+  const float target = h.ln_perp;
+  float beta = __shfl(beta_prev, hbase);
+  const float sD = half_sum_uniform(D);
+  if (!(beta > 0.0f && beta < 1e29f)) beta = (float)K / sD;
+  float lo = 0.0f, hi = __int_as_float(0x7f800000);
+  for (int it = 0; it < 48; ++it) {
+    if (__ballot(!done) == 0ull) break;
+    const float bl = beta * 1.44269504f;   // exp(-beta D) = 2^(-beta log2(e) D)
+    const float e = act ? exp2f(-bl * D) : 0.0f;
+    const float S = half_sum_uniform(e);
+    const float T = half_sum_uniform(e * D);
+    const float U = half_sum_uniform(e * D * D);
+    if (done) continue;
+    const float mean = T / S;
+    const float f = logf(S) + beta * mean - target;
+    if (fabsf(f) <= 1e-6f) {
+      done = true;
+      continue;
+    }
+    if (f > 0.0f)
+      lo = beta;
+    else
+      hi = beta;
+    if (hi < 3e38f && hi - lo <= 2e-7f * hi) {
+      done = true;
+      continue;
+    }
+    const float var = U / S - mean * mean;
+    float bn = beta + f / (beta * var);
+    if (!(bn > lo && bn < hi)) bn = (hi < 3e38f) ? 0.5f * (lo + hi) : 2.0f * beta;
+    beta = bn;
+  }
+  const float S = half_sum_uniform(act ? expf(-beta * D) : 0.0f);
+  return fixed ? special : make_float4(beta, m, r, 1.0f / S);
+}
+
 }  // namespace fsne

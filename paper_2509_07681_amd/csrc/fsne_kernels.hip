@@ -417,6 +417,199 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// The HD refinement for two points per wave (K_hd, K_ld <= 32; rows that fit
+// one vector per lane).  Half h = lane / 32 handles point 2 w + h; every
+// phase that needs at most 32 lanes per point (candidates, de-duplication,
+// sorting, ranking, calibration) runs for both points in the same
+// instructions, while the candidate rows of both points share the row
+// groups of the distance pass.  Each point gets exactly what the one-point
+// kernel computes: the same draws, the same per-row arithmetic and the same
+// order of additions.
+// ---------------------------------------------------------------------------
+struct WaveLds2 {
+  int tab[2 * kHashSlots];   // one hash set per half
+  float d2[kWave];           // candidate distances, point 0's slots first
+  float row[kWave];          // new list distances, 32 per half
+  int lst[kWave];            // compaction scratch, 32 per half
+  uint64_t ck[kWave];        // sorted candidate keys, 32 per half
+  uint64_t ok[kWave];        // old list keys, 32 per half
+};
+
+// Squared distances for the candidates of both points: slots 0..n0-1 are the
+// ids in lanes 0..n0-1 (point i0), slots n0..n0+n1-1 those in lanes
+// 32..32+n1-1 (point i1).  Results go to sd2[slot].
+template <typename TX, int VEC>
+__device__ void hd_dist_rows2(const TX* __restrict__ X, int D, int32_t i0, int32_t i1, int cid,
+                              int n0, int n1, float* sd2) {
+  constexpr int U = VEC >= 8 ? 2 : 4;   // loads in flight per lane, within the register budget
+  const int lane = lane_id();
+  const RowGeom geo = row_geom(D, VEC);
+  const int g = lane >> geo.lg, sl = lane & (geo.G - 1);
+  const int R = kWave >> geo.lg;
+  const int e = sl * VEC;
+  const bool in_row = e < D;
+  float xa[VEC], xb[VEC];
+  if (in_row) {
+    VecLoad<TX, VEC>::load(X + (int64_t)i0 * D + e, xa);
+    VecLoad<TX, VEC>::load(X + (int64_t)i1 * D + e, xb);
+  } else {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) xa[v] = xb[v] = 0.0f;
+  }
+  const int nrows = n0 + n1;
+  for (int p = 0; p < nrows; p += R * U) {
+    float xc[U][VEC];
+    bool second[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int slot = p + u * R + g;
+      second[u] = slot >= n0;
+      const int src = second[u] ? 32 + slot - n0 : slot;
+      const int c = __shfl(cid, src & (kWave - 1));
+      const bool ok = slot < nrows && c >= 0;
+      if (in_row) {
+        VecLoad<TX, VEC>::load(X + (int64_t)(ok ? c : i0) * D + e, xc[u]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) xc[u][v] = second[u] ? xb[v] : xa[v];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float s = 0.0f;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const float df = (second[u] ? xb[v] : xa[v]) - xc[u][v];
+        s = fmaf(df, df, s);
+      }
+      const float acc = group_sum_dpp(s, geo.G);
+      const int slot = p + u * R + g;
+      if (sl == geo.G - 1 && slot < nrows) sd2[slot] = acc;
+    }
+  }
+  wave_lds_sync();
+}
+
+template <typename TX, int VEC>
+__global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
+  const Scalars* sc = a.sc;
+  if (!sc->fire) return;
+  __shared__ WaveLds2 lds_all[kWavesPerBlock];
+  WaveLds2& S = lds_all[threadIdx.x / kWave];
+  const int32_t w = (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  if (2 * w >= a.N) return;
+  const int lane = lane_id(), h = lane >> 5, hl = lane & 31, hb = h * 32;
+  const int32_t i = 2 * w + h;
+  const bool live = i < a.N;                 // the last wave may hold one point
+  const int32_t i0 = 2 * w, i1 = i0 + 1 < a.N ? i0 + 1 : i0;   // wave-uniform
+  const uint32_t t = sc->t;
+  const int cur = sc->hd_cur;
+  const int Kh = a.Kh, Kl = a.Kl;
+  const int32_t* hin = a.hd_idx[cur];
+  const float* din = a.hd_d2[cur];
+  const int32_t* lin = a.ld_idx[t & 1];
+  const int own = (live && hl < Kh) ? hin[(int64_t)i * Kh + hl] : -1;
+  const float od2 = (live && hl < Kh) ? din[(int64_t)i * Kh + hl] : kInf;
+  const int oth = (live && hl < Kl) ? lin[(int64_t)i * Kl + hl] : -1;
+
+  // candidates (the one-point rule, per half)
+  int c = -1;
+  {
+    const uint4 u = philox((uint32_t)i, t, kStreamHDC, (uint32_t)hl, a.h.key0, a.h.key1);
+    const int a_own = (int)draw_index(u.x, (uint32_t)Kh);
+    const int a_oth = (int)draw_index(u.x, (uint32_t)Kl);
+    const int j_own = __shfl(own, hb + a_own);
+    const int j_oth = __shfl(oth, hb + a_oth);
+    if (live) {
+      if (hl < kSameNoN)
+        c = hin[(int64_t)j_own * Kh + draw_index(u.y, (uint32_t)Kh)];
+      else if (hl < kCrossDir)
+        c = j_oth;
+      else if (hl < kCrossNoN)
+        c = lin[(int64_t)j_oth * Kl + draw_index(u.y, (uint32_t)Kl)];
+      else
+        c = draw_other(u.x, i, a.N);
+    }
+    int* tab = S.tab + h * kHashSlots;
+#pragma unroll
+    for (int k = 0; k < kHashSlots / 32; ++k) tab[k * 32 + hl] = -1;
+    wave_lds_sync();
+    hash_insert(tab, nullptr, hl < Kh ? own : -1, 0);
+    const bool fresh = hash_insert(tab, nullptr, c != i ? c : -1, 0);
+    c = fresh ? c : -1;
+  }
+  // compact each half's candidates to its first lanes
+  int n;
+  {
+    const uint32_t m = (uint32_t)(__ballot(c >= 0) >> hb);
+    n = __popc(m);
+    if (c >= 0) S.lst[hb + __popc(m & ((1u << hl) - 1u))] = c;
+    wave_lds_sync();
+    c = hl < n ? S.lst[hb + hl] : -1;
+    wave_lds_sync();
+  }
+  const int nload = n;
+  const int n0 = __shfl(n, 0), n1 = __shfl(n, 32);
+  hd_dist_rows2<TX, VEC>(static_cast<const TX*>(a.X), a.D, i0, i1, c, n0, n1, S.d2);
+  uint64_t ck = c >= 0 ? pack_key(S.d2[(h ? n0 : 0) + hl], c) : kNoKey;
+  uint32_t aux = 0;
+  bitonic_sort<32>(ck, aux);
+  const int ncand = n;
+  const uint64_t ko = (live && hl < Kh) ? pack_key(od2, own) : kNoKey;
+  S.ck[lane] = ck;
+  S.ok[lane] = ko;
+  wave_lds_sync();
+  int32_t* hout = a.hd_idx[cur ^ 1];
+  float* dout = a.hd_d2[cur ^ 1];
+  // a stored list that is not in key order (after a state load) is sorted first
+  uint32_t below = (uint32_t)hl;
+  {
+    const uint32_t nlo = (uint32_t)__shfl_down((int)(uint32_t)ko, 1);
+    const uint32_t nhi = (uint32_t)__shfl_down((int)(uint32_t)(ko >> 32), 1);
+    const uint64_t next = ((uint64_t)nhi << 32) | nlo;
+    const uint64_t bad = __ballot(hl + 1 < Kh && !(ko < next));
+    if (bad != 0ull) {
+      const bool mine = ((uint32_t)(bad >> hb)) != 0u;
+      uint64_t sk = ko;
+      uint32_t src = (uint32_t)hl;
+      bitonic_sort<32>(sk, src);
+      if (mine) S.ok[lane] = sk;
+      wave_lds_sync();
+      uint32_t pos = (uint32_t)hl;
+      for (int k = 0; k < Kh; ++k)
+        if ((uint32_t)__shfl((int)src, hb + k) == (uint32_t)hl) pos = (uint32_t)k;
+      if (mine) below = pos;
+    }
+  }
+  if (live && hl < Kh) {
+    const int ro = (int)below + count_below(S.ck + hb, ncand, ko);
+    if (ro < Kh) {
+      hout[(int64_t)i * Kh + ro] = own;
+      dout[(int64_t)i * Kh + ro] = od2;
+      S.row[hb + ro] = od2;
+    }
+  }
+  bool enter = false;
+  if (live && hl < ncand) {
+    const int rc = hl + count_below(S.ok + hb, Kh, ck);
+    enter = rc < Kh;
+    if (enter) {
+      hout[(int64_t)i * Kh + rc] = key_id(ck);
+      dout[(int64_t)i * Kh + rc] = key_d2(ck);
+      S.row[hb + rc] = key_d2(ck);
+    }
+  }
+  wave_lds_sync();
+  const bool changed = ((uint32_t)(__ballot(enter) >> hb)) != 0u;
+  if (live && hl == 0) a.flags[i] = (uint8_t)((changed ? 1 : 0) | (nload << 1));
+  if (__ballot(changed) != 0ull) {
+    const float sorted = hl < Kh ? S.row[hb + hl] : 0.0f;
+    const float4 r = calibrate_row_half(sorted, Kh, a.h, live ? a.rec[i].x : 0.0f, changed);
+    if (changed && hl == 0) a.rec[i] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Symmetrised affinities of point i (eq. (1)) over its HD list:
 //   P_ik = (p_{j|i} + p_{i|j}) / (2N), j = HD[i][k],
 //   p_{j|i} = exp(-beta_i (d2 - m_i)) invS_i,
@@ -1162,8 +1355,12 @@ struct InitLaunch {
 template <typename TX, int VEC, int CH>
 struct RefineLaunch {
   static hipError_t run(const StepArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_hd_refine<TX, VEC, CH, false>), dim3(wave_blocks(a.N)), dim3(kBlock),
-                       0, s, a);
+    if (CH == 1 && a.Kh <= 32 && a.Kl <= 32)
+      hipLaunchKernelGGL((k_hd_refine2<TX, VEC>), dim3(wave_blocks((a.N + 1) / 2)),
+                         dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_hd_refine<TX, VEC, CH, false>), dim3(wave_blocks(a.N)),
+                         dim3(kBlock), 0, s, a);
     return hipGetLastError();
   }
 };
