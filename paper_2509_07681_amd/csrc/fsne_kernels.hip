@@ -620,16 +620,16 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
   const Scalars* sc = a.sc;
   const int fire = standalone ? 0 : sc->fire;
   if (!standalone && !fire) return;
-  const int32_t i = (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
-  if (i >= a.N) return;
-  const int lane = lane_id();
+  // one thread per list entry, so that no lane idles whatever K_hd is
   const int Kh = a.Kh;
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= (int64_t)a.N * Kh) return;
+  const int32_t i = (int32_t)(q / Kh);
   const int buf = sc->hd_cur ^ fire;
   const int32_t* hl = a.hd_idx[buf];
   const float* hd = a.hd_d2[buf];
-  if (lane >= Kh) return;
-  const int32_t j = hl[(int64_t)i * Kh + lane];
-  const float d2 = hd[(int64_t)i * Kh + lane];
+  const int32_t j = hl[q];
+  const float d2 = hd[q];
   const float4 ri = a.rec[i];
   const float4 rj = a.rec[j];
   const float pji = expf(-ri.x * (d2 - ri.y)) * ri.w;
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
     }
   }
   const float pij = member ? expf(-rj.x * (d2 - rj.y)) * rj.w : 0.0f;
-  a.P[(int64_t)i * Kh + lane] = (pji + pij) / (2.0f * (float)a.N);
+  a.P[q] = (pji + pij) / (2.0f * (float)a.N);
 }
 
 // ---------------------------------------------------------------------------
@@ -1425,7 +1425,9 @@ hipError_t launch_drift_rows(const StepArgs& a, const uint8_t* moved, hipStream_
 }
 
 hipError_t launch_psym(const StepArgs& a, int standalone, hipStream_t s) {
-  hipLaunchKernelGGL(k_psym, dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a, standalone);
+  const int64_t entries = (int64_t)a.N * a.Kh;
+  hipLaunchKernelGGL(k_psym, dim3((unsigned)((entries + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, a, standalone);
   return hipGetLastError();
 }
 
