@@ -253,6 +253,72 @@ def hierarchy_run(F, args):
             "levels": levels, "edges_ge_0.5": edges}
 
 
+def large_run(F, args):
+    """The large BF16 workload: 4,000,000 points of a 1,000-cluster Zipf
+    mixture in R^256 (BF16 rows), d = 32, K_hd = 64, K_ld = 32, 32 negatives,
+    alpha = 0.5, perplexity 20.  Reports the step time with the HD refinement
+    on and off, the per-kernel times, and a 500-iteration run under the coin
+    with HD recall@64 of 500 query points against exact neighbours."""
+    import numpy as np
+    import torch
+
+    from inputs.generators import RUN_SEED, bf16_bits_to_f32, f32_to_bf16_bits, make_workload, y_init
+    from inputs.knn_metrics import exact_knn_device, recall_at_k
+
+    t_gen = time.perf_counter()
+    X, _, cfg = make_workload("zipf_4m")
+    Xb = f32_to_bf16_bits(X)
+    del X
+    t_gen = time.perf_counter() - t_gen
+    N, K = Xb.shape[0], cfg["K_hd"]
+    Y0 = y_init(N, cfg["d"])
+    base = dict(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=N / 12.0,
+                n_neg=cfg["n_neg"], dist_mode=0)
+    out = {"metric": "large BF16 workload: iters/s and HD recall@64",
+           "config": {"workload": "zipf_4m: N=4,000,000 points of a 1000-cluster Zipf(1.1) mixture "
+                                  "in R^256 (BF16 rows), d=32, K_hd=64, K_ld=32, 32 negatives, "
+                                  "alpha=0.5, perplexity 20"},
+           "data_gen_seconds": round(t_gen, 1)}
+    for mode, name in ((1, "hd_always"), (2, "ld_only")):
+        emb = F.Embedding(Xb, Y0, cfg["d"], K, cfg["K_ld"], seed=RUN_SEED,
+                          hp=F.fsne_default_hparams(**{**schedule(F, base, 0).as_dict(),
+                                                       "hd_mode": mode}))
+        emb.step(5)
+        emb.sync()
+        t0 = time.perf_counter()
+        emb.step(20)
+        emb.sync()
+        ms = (time.perf_counter() - t0) * 1e3 / 20
+        emb.profile(True)
+        emb.step(10)
+        kt = emb.kernel_times()
+        emb.close()
+        out[name] = {"ms_per_step": round(ms, 3), "iters_per_s": round(1e3 / ms, 2),
+                     "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]}}
+    rng = np.random.default_rng(7)
+    q = np.sort(rng.choice(N, 500, replace=False))
+    Xd = torch.from_numpy(bf16_bits_to_f32(Xb)).cuda()
+    _, ex = exact_knn_device(Xd, Xb, q, K)
+    del Xd
+    torch.cuda.empty_cache()
+    emb = F.Embedding(Xb, Y0, cfg["d"], K, cfg["K_ld"], seed=RUN_SEED,
+                      hp=schedule(F, {**base, "hd_mode": 0}, 0))
+    emb.sync()
+    t0 = time.perf_counter()
+    emb.step(250)
+    emb.set_hyperparams(schedule(F, {**base, "hd_mode": 0}, 250))
+    emb.step(250)
+    emb.sync()
+    secs = time.perf_counter() - t0
+    idx, _ = emb.knn(0)
+    st = emb.stats()
+    emb.close()
+    out["run_500"] = {"seconds": round(secs, 3), "iters_per_s": round(500 / secs, 2),
+                      "recall_at_64": round(recall_at_k(idx, Xb, q, ex), 4),
+                      "final_E": round(float(st["E"]), 4), "nonfinite": int(st["nonfinite"])}
+    return out
+
+
 def gather_probe(row_bytes, rows_per_wave, table_bytes, nwaves=1_000_000, reps=5):
     """Random-row gather ceiling: rows/s and bytes/s at which the GPU gathers
     rows of row_bytes from random positions of a table, one wave per point as
@@ -468,6 +534,8 @@ def main():
                     help="run the feedback-loop experiment (fixed vs optimised embedding) instead")
     ap.add_argument("--hierarchy", action="store_true",
                     help="run the alpha-sweep hierarchy graph experiment instead")
+    ap.add_argument("--large", action="store_true",
+                    help="run the 4M-point BF16 workload instead")
     ap.add_argument("--gather-table", action="store_true",
                     help="print the random-gather ceiling for several row sizes instead")
     ap.add_argument("--fb-n", type=int, default=50000)
@@ -517,6 +585,9 @@ def main():
         return
     if args.hierarchy:
         print(json.dumps(hierarchy_run(F, args)))
+        return
+    if args.large:
+        print(json.dumps(large_run(F, args)))
         return
     if args.gather_table:
         # random-gather ceilings for the row sizes the step kernels gather

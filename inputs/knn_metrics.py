@@ -120,3 +120,22 @@ def rnx_auc(curve):
     """Area under R_NX(K) on a log scale of K: sum R(K)/K over sum 1/K."""
     K = np.arange(1, len(curve) + 1, dtype=np.float64)
     return float(np.sum(np.asarray(curve) / K) / np.sum(1.0 / K))
+
+
+def exact_knn_device(Xd, X_host, queries, K, chunk=128):
+    """exact_knn for large sets: candidates (2K + 8 per query) from the
+    expanded form on the device (float32 tensor Xd), then their distances
+    recomputed in float64 on the host from X_host (float32 rows or bf16 bits)
+    so the order is exact.  Returns (idx, d2 float64)."""
+    q = np.asarray(queries, dtype=np.int64)
+    cand = knn_on_device(Xd, q, min(Xd.shape[0] - 1, 2 * K + 8), chunk=chunk)
+    out_i = np.empty((q.size, K), dtype=np.int64)
+    out_d = np.empty((q.size, K), dtype=np.float64)
+    for r, i in enumerate(q):
+        c = cand[r]
+        d = ((_as_f32(X_host[c]).astype(np.float64) -
+              _as_f32(X_host[i:i + 1]).astype(np.float64)) ** 2).sum(1)
+        order = np.lexsort((c, d))[:K]
+        out_i[r] = c[order]
+        out_d[r] = d[order]
+    return out_i, out_d
