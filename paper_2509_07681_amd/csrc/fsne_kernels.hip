@@ -664,15 +664,17 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
 // ---------------------------------------------------------------------------
 // Row-group layout: a row of DP floats is spread over G lanes, VEC floats
 // each, so one load instruction fetches RPI whole rows (coalesced per row).
-template <int DP>
+template <int DP, int KLM = kWave>
 struct LdGeom {
   static constexpr int VEC = DP >= 4 ? 4 : DP;
   static constexpr int G = DP / VEC;
   static constexpr int LG = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : 4;
   static constexpr int RPI = kWave / G;
-  static constexpr int MAXE = kWave + kCand;                 // LD entries: old list + slots
+  static constexpr int MAXE = KLM + kCand;                  // LD entries: old list + slots
   static constexpr int MAXP = (MAXE + RPI - 1) / RPI;         // passes over the entries
-  static constexpr bool CACHE = MAXP * VEC <= 48;             // keep entry rows in registers
+  // keep entry rows in registers only while they are few: at wider rows the
+  // registers cost more occupancy than the second read of the kept entries
+  static constexpr bool CACHE = MAXP * VEC <= 24;
 };
 
 template <int VEC>
@@ -769,12 +771,13 @@ __device__ __forceinline__ float pair_terms(const float* yi, const float* yj, fl
   return scale * w;
 }
 
-template <int DP>
+// KLM bounds the LD list length (32 or 64), which sizes the entry passes.
+template <int DP, int KLM>
 __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
-  using Geo = LdGeom<DP>;
+  using Geo = LdGeom<DP, KLM>;
   constexpr int VEC = Geo::VEC, G = Geo::G, RPI = Geo::RPI;
   constexpr int LP = (kWave + RPI - 1) / RPI;   // passes over a list of <= 64 rows
-  constexpr bool PRE_H = LP * VEC <= 32;        // HD rows kept in registers
+  constexpr bool PRE_H = LP * VEC <= 16;        // HD rows kept in registers
   constexpr bool PRE_E = Geo::CACHE;            // entry rows kept in registers
   __shared__ LdLds lds_all[kWavesPerBlock];
   LdLds& S = lds_all[threadIdx.x / kWave];
@@ -874,7 +877,7 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   // merge: order the entries by (distance, index) and keep the first Kl
   bool keep = false;
   int kid = -1;
-  if (ne <= kWave) {
+  if (Geo::MAXE <= kWave || ne <= kWave) {
     const int e = lane;
     const int id = e < ne ? S.ent[e] : -1;
     uint64_t key = id >= 0 ? pack_key(S.dd[e], id) : kNoKey;
@@ -1438,15 +1441,24 @@ hipError_t launch_calibrate_all(const StepArgs& a, hipStream_t s) {
 
 hipError_t launch_ld_grad(const StepArgs& a, hipStream_t s) {
   const dim3 g(wave_blocks(a.N)), b(kBlock);
+  const bool short_list = a.Kl <= 32;
+#define FSNE_LD_CASE(DPV)                                                        \
+  case DPV:                                                                      \
+    if (short_list)                                                              \
+      hipLaunchKernelGGL((k_ld_grad<DPV, 32>), g, b, 0, s, a);                   \
+    else                                                                         \
+      hipLaunchKernelGGL((k_ld_grad<DPV, kWave>), g, b, 0, s, a);                \
+    break;
   switch (a.DP) {
-    case 2: hipLaunchKernelGGL((k_ld_grad<2>), g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_ld_grad<4>), g, b, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_ld_grad<8>), g, b, 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_ld_grad<16>), g, b, 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_ld_grad<32>), g, b, 0, s, a); break;
-    case 64: hipLaunchKernelGGL((k_ld_grad<64>), g, b, 0, s, a); break;
+    FSNE_LD_CASE(2)
+    FSNE_LD_CASE(4)
+    FSNE_LD_CASE(8)
+    FSNE_LD_CASE(16)
+    FSNE_LD_CASE(32)
+    FSNE_LD_CASE(64)
     default: return hipErrorInvalidValue;
   }
+#undef FSNE_LD_CASE
   return hipGetLastError();
 }
 

@@ -45,6 +45,13 @@ WORKLOADS = {
                                         perplexity=10.0)),
     "zipf_3000_bf16": lambda: (f32_to_bf16_bits(zipf_mixture(N=3000, n_clusters=30, seed=1005)[0]),
                                dict(d=32, K_hd=64, K_ld=32, n_neg=32, alpha=0.5, perplexity=20.0)),
+    # LD lists longer than one wave's candidate merge (K_ld > 32)
+    "long_ld_1500": lambda: (manifolds(per_manifold=30, seed=1007)[0][:1500],
+                             dict(d=8, K_hd=40, K_ld=48, n_neg=12, alpha=1.0, perplexity=12.0)),
+    "wide_ld_1100_bf16": lambda: (f32_to_bf16_bits(zipf_mixture(N=1100, n_clusters=12,
+                                                                seed=1008)[0]),
+                                  dict(d=32, K_hd=48, K_ld=64, n_neg=24, alpha=0.5,
+                                       perplexity=15.0)),
     "odd_dims_777": lambda: (np.random.default_rng(3).normal(size=(777, 13)).astype(np.float32),
                              dict(d=5, K_hd=10, K_ld=7, n_neg=3, alpha=1.7, perplexity=4.0)),
 }
