@@ -257,8 +257,9 @@ def large_run(F, args):
     """The large BF16 workload: 4,000,000 points of a 1,000-cluster Zipf
     mixture in R^256 (BF16 rows), d = 32, K_hd = 64, K_ld = 32, 32 negatives,
     alpha = 0.5, perplexity 20.  Reports the step time with the HD refinement
-    on and off, the per-kernel times, and a 500-iteration run under the coin
-    with HD recall@64 of 500 query points against exact neighbours."""
+    on and off (and with the BF16 MFMA screen), the per-kernel times, and
+    500-iteration runs, under the coin and with every iteration refining, with
+    HD recall@64 of 500 query points against exact neighbours."""
     import numpy as np
     import torch
 
@@ -279,10 +280,10 @@ def large_run(F, args):
                                   "in R^256 (BF16 rows), d=32, K_hd=64, K_ld=32, 32 negatives, "
                                   "alpha=0.5, perplexity 20"},
            "data_gen_seconds": round(t_gen, 1)}
-    for mode, name in ((1, "hd_always"), (2, "ld_only")):
+    for mode, dm, name in ((1, 0, "hd_always"), (2, 0, "ld_only"), (1, 1, "hd_always_mfma_screen")):
         emb = F.Embedding(Xb, Y0, cfg["d"], K, cfg["K_ld"], seed=RUN_SEED,
                           hp=F.fsne_default_hparams(**{**schedule(F, base, 0).as_dict(),
-                                                       "hd_mode": mode}))
+                                                       "hd_mode": mode, "dist_mode": dm}))
         emb.step(5)
         emb.sync()
         t0 = time.perf_counter()
@@ -301,21 +302,23 @@ def large_run(F, args):
     _, ex = exact_knn_device(Xd, Xb, q, K)
     del Xd
     torch.cuda.empty_cache()
-    emb = F.Embedding(Xb, Y0, cfg["d"], K, cfg["K_ld"], seed=RUN_SEED,
-                      hp=schedule(F, {**base, "hd_mode": 0}, 0))
-    emb.sync()
-    t0 = time.perf_counter()
-    emb.step(250)
-    emb.set_hyperparams(schedule(F, {**base, "hd_mode": 0}, 250))
-    emb.step(250)
-    emb.sync()
-    secs = time.perf_counter() - t0
-    idx, _ = emb.knn(0)
-    st = emb.stats()
-    emb.close()
-    out["run_500"] = {"seconds": round(secs, 3), "iters_per_s": round(500 / secs, 2),
-                      "recall_at_64": round(recall_at_k(idx, Xb, q, ex), 4),
-                      "final_E": round(float(st["E"]), 4), "nonfinite": int(st["nonfinite"])}
+    # 500 iterations under the coin, then the same with every iteration refining
+    for hd_mode, name in ((0, "run_500"), (1, "run_500_hd_always")):
+        emb = F.Embedding(Xb, Y0, cfg["d"], K, cfg["K_ld"], seed=RUN_SEED,
+                          hp=schedule(F, {**base, "hd_mode": hd_mode}, 0))
+        emb.sync()
+        t0 = time.perf_counter()
+        emb.step(250)
+        emb.set_hyperparams(schedule(F, {**base, "hd_mode": hd_mode}, 250))
+        emb.step(250)
+        emb.sync()
+        secs = time.perf_counter() - t0
+        idx, _ = emb.knn(0)
+        st = emb.stats()
+        emb.close()
+        out[name] = {"seconds": round(secs, 3), "iters_per_s": round(500 / secs, 2),
+                     "recall_at_64": round(recall_at_k(idx, Xb, q, ex), 4),
+                     "final_E": round(float(st["E"]), 4), "nonfinite": int(st["nonfinite"])}
     return out
 
 
