@@ -133,7 +133,8 @@ fsne_status fsne_init(fsne_ctx **out, const void *X, int64_t N, int32_t D, int32
 
 /* Run n_iters iterations (Sec. 3), asynchronously on the context stream.
  * Per iteration: [if the coin fires] HD refinement + recalibration of changed
- * points + affinities; LD refinement + gradient partials; Z; momentum update;
+ * points + affinities of the list entries with a changed point at either end
+ * (the others keep their values); LD refinement + gradient partials; Z; momentum update;
  * E and the next coin.  Errors: FSNE_EINVAL (n_iters < 0), FSNE_EHIP. */
 fsne_status fsne_step(fsne_ctx *ctx, int32_t n_iters);
 
@@ -154,7 +155,10 @@ fsne_status fsne_get_knn(fsne_ctx *ctx, int32_t which, int32_t *idx, float *dist
 
 /* Copy the state to / from host memory (checkpoint, resume, checks).  set
  * reads every non-NULL field except A, R, Zh and recomputes the coin of the
- * next iteration from E and t.  Synchronises.  Errors: FSNE_EINVAL, FSNE_EHIP. */
+ * next iteration from E and t.  If it sets HD lists, distances or records
+ * but no affinities P, it recomputes P from the new state (eq. (1), reading
+ * restricted to the lists): refinements only update the entries of points
+ * whose lists changed.  Synchronises.  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_get_state(fsne_ctx *ctx, const fsne_state_view *s);
 fsne_status fsne_set_state(fsne_ctx *ctx, const fsne_state_view *s);
 

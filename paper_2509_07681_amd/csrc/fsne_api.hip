@@ -536,6 +536,9 @@ fsne_status fsne_set_state(fsne_ctx* c, const fsne_state_view* v) {
   s.nonfinite = 0;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   TRY(write_scalars(c, s));
+  // refinements update the affinities only where a list changed, so lists or
+  // records set without their affinities get theirs recomputed here
+  if (!v->P && (v->hd_idx || v->hd_d2 || v->rec)) TRY(refresh_affinities(c, false));
   HIPCHK(c, fsne::launch_set_fire(c->sc, make_hyper(c), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return FSNE_OK;

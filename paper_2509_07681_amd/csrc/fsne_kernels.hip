@@ -629,6 +629,11 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
   const int32_t* hl = a.hd_idx[buf];
   const float* hd = a.hd_d2[buf];
   const int32_t j = hl[q];
+  // After a refinement an entry's value can only change if point i or point j
+  // changed its list, and so its record (the flag bit 0 of this refinement):
+  // other entries keep the value they hold.  A standalone pass recomputes all.
+  // (j's flag is read only when i's is clear: early on nearly every point changes)
+  if (!standalone && !(a.flags[i] & 1u) && !(a.flags[j] & 1u)) return;
   const float d2 = hd[q];
   const float4 ri = a.rec[i];
   const float4 rj = a.rec[j];
