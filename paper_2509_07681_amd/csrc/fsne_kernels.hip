@@ -67,6 +67,44 @@ struct VecLoad<uint16_t, 1> {
   static __device__ __forceinline__ void load(const uint16_t* p, float* o) { o[0] = to_f32(*p); }
 };
 
+// A lane's chunk of a row kept as loaded (BF16 rows stay packed, two values
+// per register) and widened to FP32 element by element where it is used.
+template <typename TX, int VEC>
+struct RawChunk;
+template <>
+struct RawChunk<float, 4> {
+  float4 r;
+  __device__ __forceinline__ void load(const float* p) { r = *reinterpret_cast<const float4*>(p); }
+  __device__ __forceinline__ void zero() { r = make_float4(0.0f, 0.0f, 0.0f, 0.0f); }
+  __device__ __forceinline__ float at(int v) const {
+    return v == 0 ? r.x : v == 1 ? r.y : v == 2 ? r.z : r.w;
+  }
+};
+template <>
+struct RawChunk<float, 1> {
+  float r;
+  __device__ __forceinline__ void load(const float* p) { r = *p; }
+  __device__ __forceinline__ void zero() { r = 0.0f; }
+  __device__ __forceinline__ float at(int) const { return r; }
+};
+template <>
+struct RawChunk<uint16_t, 8> {
+  uint4 r;
+  __device__ __forceinline__ void load(const uint16_t* p) { r = *reinterpret_cast<const uint4*>(p); }
+  __device__ __forceinline__ void zero() { r = make_uint4(0u, 0u, 0u, 0u); }
+  __device__ __forceinline__ float at(int v) const {
+    const uint32_t w = (v >> 1) == 0 ? r.x : (v >> 1) == 1 ? r.y : (v >> 1) == 2 ? r.z : r.w;
+    return __uint_as_float((v & 1) ? (w & 0xFFFF0000u) : (w << 16));
+  }
+};
+template <>
+struct RawChunk<uint16_t, 1> {
+  uint16_t r;
+  __device__ __forceinline__ void load(const uint16_t* p) { r = *p; }
+  __device__ __forceinline__ void zero() { r = 0; }
+  __device__ __forceinline__ float at(int) const { return __uint_as_float((uint32_t)r << 16); }
+};
+
 struct RowGeom {
   int G;       // lanes per row
   int lg;      // log2 G
@@ -94,21 +132,20 @@ __device__ void hd_dist_rows(const TX* __restrict__ X, int D, int32_t i, int cid
   const RowGeom geo = row_geom(D, VEC);
   const int g = lane >> geo.lg, sl = lane & (geo.G - 1);
   const int R = kWave >> geo.lg;
-  float xi[CH][VEC];
+  // chunks stay as loaded (packed BF16: half the registers), widened at use
+  RawChunk<TX, VEC> xi[CH];
   const TX* xr = X + (int64_t)i * D;
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
     const int e = (sl + k * geo.G) * VEC;
-    if (k < geo.chunks && e < D) {
-      VecLoad<TX, VEC>::load(xr + e, xi[k]);
-    } else {
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) xi[k][v] = 0.0f;
-    }
+    if (k < geo.chunks && e < D)
+      xi[k].load(xr + e);
+    else
+      xi[k].zero();
   }
   for (int p = 0; p < nrows; p += R * U) {
     float acc[U];
-    float xc[U][CH][VEC];
+    RawChunk<TX, VEC> xc[U][CH];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int slot = p + u * R + g;
@@ -118,12 +155,10 @@ __device__ void hd_dist_rows(const TX* __restrict__ X, int D, int32_t i, int cid
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int e = (sl + k * geo.G) * VEC;
-        if (k < geo.chunks && e < D) {
-          VecLoad<TX, VEC>::load(cr + e, xc[u][k]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) xc[u][k][v] = xi[k][v];
-        }
+        if (k < geo.chunks && e < D)
+          xc[u][k].load(cr + e);
+        else
+          xc[u][k] = xi[k];
       }
     }
 #pragma unroll
@@ -133,7 +168,7 @@ __device__ void hd_dist_rows(const TX* __restrict__ X, int D, int32_t i, int cid
       for (int k = 0; k < CH; ++k)
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
-          const float df = xi[k][v] - xc[u][k][v];
+          const float df = xi[k].at(v) - xc[u][k].at(v);
           s = fmaf(df, df, s);
         }
       acc[u] = group_sum_dpp(s, geo.G);
@@ -448,17 +483,18 @@ __device__ void hd_dist_rows2(const TX* __restrict__ X, int D, int32_t i0, int32
   const int R = kWave >> geo.lg;
   const int e = sl * VEC;
   const bool in_row = e < D;
-  float xa[VEC], xb[VEC];
+  // the two points' chunks stay as loaded: packed BF16 needs half the registers
+  RawChunk<TX, VEC> xa, xb;
   if (in_row) {
-    VecLoad<TX, VEC>::load(X + (int64_t)i0 * D + e, xa);
-    VecLoad<TX, VEC>::load(X + (int64_t)i1 * D + e, xb);
+    xa.load(X + (int64_t)i0 * D + e);
+    xb.load(X + (int64_t)i1 * D + e);
   } else {
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) xa[v] = xb[v] = 0.0f;
+    xa.zero();
+    xb.zero();
   }
   const int nrows = n0 + n1;
   for (int p = 0; p < nrows; p += R * U) {
-    float xc[U][VEC];
+    RawChunk<TX, VEC> xc[U];
     bool second[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -467,19 +503,17 @@ __device__ void hd_dist_rows2(const TX* __restrict__ X, int D, int32_t i0, int32
       const int src = second[u] ? 32 + slot - n0 : slot;
       const int c = __shfl(cid, src & (kWave - 1));
       const bool ok = slot < nrows && c >= 0;
-      if (in_row) {
-        VecLoad<TX, VEC>::load(X + (int64_t)(ok ? c : i0) * D + e, xc[u]);
-      } else {
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) xc[u][v] = second[u] ? xb[v] : xa[v];
-      }
+      if (in_row)
+        xc[u].load(X + (int64_t)(ok ? c : i0) * D + e);
+      else
+        xc[u].zero();
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       float s = 0.0f;
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
-        const float df = (second[u] ? xb[v] : xa[v]) - xc[u][v];
+        const float df = (second[u] ? xb.at(v) : xa.at(v)) - xc[u].at(v);
         s = fmaf(df, df, s);
       }
       const float acc = group_sum_dpp(s, geo.G);
