@@ -317,6 +317,27 @@ def test_refined_lists_converge_to_exact(oracle_lib):
     np.testing.assert_allclose(S.hd_d2[:N], exd, rtol=1e-15)
 
 
+def test_ld_lists_converge_to_exact_in_a_fixed_embedding(oracle_lib):
+    """With the learning rate at 0 the embedding stays where it is, and the
+    LD refinement (old list plus candidates, kept by distance in Y) must end
+    on the exact K_ld nearest neighbours in Y, nearest first."""
+    O = oracle_lib
+    X, _ = blobs(n_clusters=3, per_cluster=50, D=6, seed=12)
+    N, Kh, Kl = X.shape[0], 10, 7
+    Y0 = np.random.default_rng(4).normal(size=(N, 3))
+    S = O.OracleState(X, 3, Kh, Kl, 17, Y0).init(
+        O.Hyper(alpha=1.0, perplexity=5.0, lr=0.0, momentum=0.5, n_neg=4, hd_mode=0))
+    hp = O.Hyper(alpha=1.0, perplexity=5.0, lr=0.0, momentum=0.5, n_neg=4, hd_mode=0)
+    for _ in range(250):
+        S.step(hp)
+    Y = S.live("Y")
+    np.testing.assert_array_equal(Y, Y0)
+    d2 = ((Y[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, np.inf)
+    exact = np.argsort(d2, axis=1, kind="stable")[:, :Kl]
+    np.testing.assert_array_equal(S.live("ld_idx"), exact)
+
+
 # --- refinement probability and its smoothing (Sec. 3) -----------------------
 def test_coin_probability(oracle_lib):
     O = oracle_lib
