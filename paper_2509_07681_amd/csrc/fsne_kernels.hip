@@ -816,7 +816,7 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   using Geo = LdGeom<DP, KLM>;
   constexpr int VEC = Geo::VEC, G = Geo::G, RPI = Geo::RPI;
   constexpr int LP = (kWave + RPI - 1) / RPI;   // passes over a list of <= 64 rows
-  constexpr bool PRE_H = LP * VEC <= 16;        // HD rows kept in registers
+  constexpr bool PRE_H = LP * VEC <= 8;         // HD rows kept in registers
   constexpr bool PRE_E = Geo::CACHE;            // entry rows kept in registers
   __shared__ LdLds lds_all[kWavesPerBlock];
   LdLds& S = lds_all[threadIdx.x / kWave];
