@@ -322,6 +322,49 @@ def large_run(F, args):
     return out
 
 
+def scaling_run(F, args):
+    """Time per iteration across dataset sizes at a fixed input dimensionality
+    of 32 (the setting of the paper's timing figure, Sec. 4): manifold rows
+    (50 linear 8-dim manifolds in R^32, FP32), d = 2, K_hd = K_ld = 32, 16
+    negatives, alpha = 1, perplexity 10.  For each N: ms per iteration with
+    the HD refinement on every step and with it off, and the mean over a
+    500-iteration run under the coin with the standard schedule."""
+    from inputs.generators import RUN_SEED, manifolds, y_init
+
+    out = {"metric": "ms per iteration vs N at D = 32",
+           "config": {"workload": "manifold rows, 50 linear 8-dim manifolds in R^32 (FP32), d=2, "
+                                  "K_hd=K_ld=32, 16 negatives, alpha=1, perplexity 10"},
+           "sizes": []}
+    for N in args.scaling_sizes:
+        X, _ = manifolds(n_manifolds=50, per_manifold=N // 50, D=32)
+        N = X.shape[0]
+        Y0 = y_init(N, 2)
+        base = dict(alpha=1.0, perplexity=10.0, lr=N / 12.0, n_neg=16)
+        row = {"N": N}
+        for mode, name in ((1, "hd_always_ms"), (2, "ld_only_ms")):
+            emb = F.Embedding(X, Y0, 2, 32, 32, seed=RUN_SEED,
+                              hp=schedule(F, {**base, "hd_mode": mode}, 0))
+            emb.step(10)
+            emb.sync()
+            t0 = time.perf_counter()
+            emb.step(50)
+            emb.sync()
+            row[name] = round((time.perf_counter() - t0) * 1e3 / 50, 4)
+            emb.close()
+        emb = F.Embedding(X, Y0, 2, 32, 32, seed=RUN_SEED, hp=schedule(F, {**base, "hd_mode": 0}, 0))
+        emb.sync()
+        t0 = time.perf_counter()
+        emb.step(250)
+        emb.set_hyperparams(schedule(F, {**base, "hd_mode": 0}, 250))
+        emb.step(250)
+        emb.sync()
+        row["run_500_mean_ms"] = round((time.perf_counter() - t0) * 1e3 / 500, 4)
+        emb.close()
+        out["sizes"].append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    return out
+
+
 def gather_probe(row_bytes, rows_per_wave, table_bytes, nwaves=1_000_000, reps=5):
     """Random-row gather ceiling: rows/s and bytes/s at which the GPU gathers
     rows of row_bytes from random positions of a table, one wave per point as
@@ -537,6 +580,10 @@ def main():
                     help="run the feedback-loop experiment (fixed vs optimised embedding) instead")
     ap.add_argument("--hierarchy", action="store_true",
                     help="run the alpha-sweep hierarchy graph experiment instead")
+    ap.add_argument("--scaling", action="store_true",
+                    help="time per iteration across N at D = 32 (the paper's timing figure)")
+    ap.add_argument("--scaling-sizes", type=int, nargs="+",
+                    default=[10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000])
     ap.add_argument("--large", action="store_true",
                     help="run the 4M-point BF16 workload instead")
     ap.add_argument("--gather-table", action="store_true",
@@ -591,6 +638,9 @@ def main():
         return
     if args.large:
         print(json.dumps(large_run(F, args)))
+        return
+    if args.scaling:
+        print(json.dumps(scaling_run(F, args)))
         return
     if args.gather_table:
         # random-gather ceilings for the row sizes the step kernels gather
