@@ -1367,7 +1367,9 @@ static hipError_t dispatch_ch(int D, Args&&... args) {
   const int chunks = V <= 64 ? 1 : (V + 63) / 64;
   if (chunks <= 1) return F<TX, VEC, 1>::run(args...);
   if (chunks <= 4) return F<TX, VEC, 4>::run(args...);
-  if constexpr (VEC * sizeof(TX) <= 4) {
+  // 16 chunks: single elements, or FP32 rows up to 4096 wide (BF16 rows stop
+  // at 4 chunks of 8, the widest the MFMA screen takes)
+  if constexpr (VEC * sizeof(TX) <= 4 || std::is_same<TX, float>::value) {
     if (chunks <= 16) return F<TX, VEC, 16>::run(args...);
   }
   return hipErrorInvalidValue;
