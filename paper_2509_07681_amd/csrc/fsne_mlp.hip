@@ -39,7 +39,7 @@ using namespace fsne;
 constexpr int kBM = 64, kBN = 64, kBK = 32, kLDP = kBK + 8;
 constexpr int kTM = 64, kTN = 64, kTK = 64, kTP = kTK + 8;   // vector-staged tiles
 constexpr int kMaxSplit = 8;      // split-K factor limit of the weight-gradient products
-constexpr int kRowChunk = 64;     // rows per partial sum of the column reductions
+constexpr int kRowChunk = 16;     // rows per partial sum of the column reductions
 constexpr int kLossBlocks = 256;
 enum { kEpiBias = 1, kEpiRelu = 2, kEpiMask = 4 };
 
@@ -131,8 +131,10 @@ __device__ __forceinline__ uint2 pack4_bf16(float4 v) {
 }
 
 // One 64 x 64 FP32 tile of an operand as 4 float4 per thread.  KC: the
-// operand is contiguous along k (rows r of the tile are its m or n index);
-// otherwise it is contiguous along m / n.
+// operand is contiguous along k (rows r of the tile are its m or n index),
+// and each thread loads 4 rows of 4 k; otherwise it is contiguous along
+// m / n, and each thread loads a 4 (k) x 4 (r) block, so that it can store
+// 4 consecutive k of one row at once.
 template <bool KC>
 __device__ __forceinline__ void tile_load(const float* __restrict__ P, int64_t s_r, int64_t s_k,
                                           int r0, int rlim, int k0, int klim, float4* v) {
@@ -146,7 +148,7 @@ __device__ __forceinline__ void tile_load(const float* __restrict__ P, int64_t s
       v[j] = gr < rlim ? load4(P + (int64_t)gr * s_r + gk, gk, klim)
                        : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     } else {
-      const int k = idx >> 4, r = (idx & 15) << 2;
+      const int k = ((tid >> 4) << 2) + j, r = (tid & 15) << 2;
       const int gr = r0 + r, gk = k0 + k;
       v[j] = gk < klim ? load4(P + (int64_t)gk * s_k + gr, gr, rlim)
                        : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -164,13 +166,17 @@ __device__ __forceinline__ void tile_store(uint16_t (*L)[kTP], const float4* v) 
     if constexpr (KC) {
       const int r = idx >> 4, k = (idx & 15) << 2;
       *reinterpret_cast<uint2*>(&L[r][k]) = pack4_bf16(v[j]);
-    } else {
-      const int k = idx >> 4, r = (idx & 15) << 2;
-      L[r][k] = to_bf16(v[j].x);
-      L[r + 1][k] = to_bf16(v[j].y);
-      L[r + 2][k] = to_bf16(v[j].z);
-      L[r + 3][k] = to_bf16(v[j].w);
     }
+  }
+  if constexpr (!KC) {
+    // v[j] holds rows r .. r+3 at k + j: row r + i gets k .. k+3 in one store
+    const int k = (tid >> 4) << 2, r = (tid & 15) << 2;
+    const float c[4][4] = {{v[0].x, v[1].x, v[2].x, v[3].x}, {v[0].y, v[1].y, v[2].y, v[3].y},
+                           {v[0].z, v[1].z, v[2].z, v[3].z}, {v[0].w, v[1].w, v[2].w, v[3].w}};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      *reinterpret_cast<uint2*>(&L[r + i][k]) =
+          pack4_bf16(make_float4(c[i][0], c[i][1], c[i][2], c[i][3]));
   }
 }
 
@@ -285,17 +291,25 @@ hipError_t gemm(hipStream_t s, const float* A, int64_t sam, int64_t sak, const f
 
 // Batch rows: row k is source row (off + k) mod N of X (FP32 or BF16 bits),
 // converted to FP32; targets (y - mean) / std from Y (padded stride DP).
+// One block per row at a time.
 __global__ void k_gather(const void* X, int xdtype, int D, int64_t N, int64_t off, int n,
                          const float* Y, int DP, int d, const float* mean, const float* sd,
                          float* Xb, float* Tb) {
-  const int64_t total = (int64_t)n * D;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = q / D, c = q % D;
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
     const int64_t r = (off + k) % N;
-    Xb[q] = xdtype == 0 ? static_cast<const float*>(X)[r * D + c]
-                        : __uint_as_float((uint32_t) static_cast<const uint16_t*>(X)[r * D + c] << 16);
-    if (Y && c < d) Tb[k * d + c] = (Y[r * DP + c] - mean[c]) / sd[c];
+    float* dst = Xb + (int64_t)k * D;
+    if (xdtype == 0) {
+      const float* src = static_cast<const float*>(X) + r * D;
+      for (int c = threadIdx.x; c < D; c += blockDim.x) dst[c] = src[c];
+    } else {
+      const uint16_t* src = static_cast<const uint16_t*>(X) + r * D;
+      for (int c = threadIdx.x; c < D; c += blockDim.x)
+        dst[c] = __uint_as_float((uint32_t)src[c] << 16);
+    }
+    if (Y && (int)threadIdx.x < d) {
+      const int c = threadIdx.x;
+      Tb[(int64_t)k * d + c] = (Y[r * DP + c] - mean[c]) / sd[c];
+    }
   }
 }
 
@@ -352,14 +366,23 @@ __global__ void k_grad_out_part(const float* dO, const float* H2, int n, int H, 
   part[(int64_t)blockIdx.y * Q + q] = s;
 }
 
-// gW3 / gb3 from the chunk partials, summed in chunk order.
+// Sum over the nchunk partials part[c * stride + q] of one output q: one
+// wave, lane l taking chunks l, l + 64, ... in order, then a fixed tree.
+__device__ __forceinline__ float sum_chunks(const float* part, int nchunk, int64_t stride,
+                                            int q) {
+  float s = 0.0f;
+  for (int c = lane_id(); c < nchunk; c += kWave) s += part[(int64_t)c * stride + q];
+  return wave_sum_uniform(s);
+}
+
+// gW3 / gb3 from the chunk partials; one wave per output.
 __global__ void k_grad_out_sum(const float* part, int nchunk, int H, int d, float* gW3,
                                float* gb3) {
   const int Q = d * (H + 1);
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (q >= Q) return;
-  float s = 0.0f;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * Q + q];
+  const float s = sum_chunks(part, nchunk, Q, q);
+  if (lane_id() != 0) return;
   const int j = q / (H + 1), k = q % (H + 1);
   if (k < H)
     gW3[(int64_t)j * H + k] = s;
@@ -390,13 +413,12 @@ __global__ void k_colsum_part(const float* M, int n, int cols, float* part) {
   part[(int64_t)blockIdx.y * cols + c] = s;
 }
 
-// out[c] = sum of the chunk partials, in chunk order.
+// out[c] = sum of the chunk partials of column c; one wave per column.
 __global__ void k_sum_parts(const float* part, int nchunk, int cols, float* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (c >= cols) return;
-  float s = 0.0f;
-  for (int k = 0; k < nchunk; ++k) s += part[(int64_t)k * cols + c];
-  out[c] = s;
+  const float s = sum_chunks(part, nchunk, cols, c);
+  if (lane_id() == 0) out[c] = s;
 }
 
 // Adam (Kingma and Ba 2015) with bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t.
@@ -527,7 +549,8 @@ fsne_status colsum(fsne_mlp* m, const float* M, int n, int cols, float* out) {
   hipLaunchKernelGGL(k_colsum_part, dim3(gx, (unsigned)nchunk), dim3(256), 0, m->stream, M, n,
                      cols, m->part);
   MCHK(m, hipGetLastError());
-  hipLaunchKernelGGL(k_sum_parts, dim3(gx), dim3(256), 0, m->stream, m->part, nchunk, cols, out);
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((cols + 3) / 4)), dim3(256), 0, m->stream,
+                     m->part, nchunk, cols, out);
   MCHK(m, hipGetLastError());
   return FSNE_OK;
 }
@@ -547,7 +570,7 @@ fsne_status backward(fsne_mlp* m, int n, int accumulate = 0) {
   hipLaunchKernelGGL(k_grad_out_part, dim3((unsigned)((q + 255) / 256), (unsigned)nchunk),
                      dim3(256), 0, s, m->dOb, m->H2b, n, m->H2, m->d, m->part);
   MCHK(m, hipGetLastError());
-  hipLaunchKernelGGL(k_grad_out_sum, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, m->part,
+  hipLaunchKernelGGL(k_grad_out_sum, dim3((unsigned)((q + 3) / 4)), dim3(256), 0, s, m->part,
                      nchunk, m->H2, m->d, Gv.W3, Gv.b3);
   MCHK(m, hipGetLastError());
   hipLaunchKernelGGL(k_back_out, dim3(1024), dim3(256), 0, s, m->dOb, P.W3, m->H2b, n, m->H2,
