@@ -16,7 +16,6 @@ the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -31,10 +30,18 @@ PEAK_HBM_GBS = 8000.0
 C_SLOTS = 32
 
 
+# Sources the step's kernels and their launches are built from; the placement
+# network, clustering and jump-start files hold kernels of their own.
+STEP_SOURCES = ("fsne_api.hip", "fsne_bf16.hip", "fsne_context.h", "fsne_device.h",
+                "fsne_kernels.h", "fsne_kernels.hip")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the step kernels' sources: counter readings taken with other
+    sources are not reported."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2509_07681_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for name in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2509_07681_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
