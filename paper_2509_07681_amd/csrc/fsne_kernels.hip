@@ -337,12 +337,25 @@ __device__ __forceinline__ float screen_dots(const uint16_t* __restrict__ X, int
   const uint16_t* ar = X + (int64_t)(cr >= 0 ? cr : i) * D + half * 8;
   const uint16_t* br = X + (int64_t)i * D + half * 8;
   f32x16_t acc = {};
-  for (int k = 0; k < D; k += 16) {
-    uint4 av = make_uint4(0, 0, 0, 0);
-    if (cr >= 0) av = *reinterpret_cast<const uint4*>(ar + k);
-    const uint4 bv = *reinterpret_cast<const uint4*>(br + k);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av),
-                                                  __builtin_bit_cast(bf16x8_t, bv), acc, 0, 0, 0);
+  // four k-steps per round: all their loads go out before the first product
+  constexpr int kSteps = 4;
+  for (int k0 = 0; k0 < D; k0 += 16 * kSteps) {
+    uint4 av[kSteps], bv[kSteps];
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u) {
+      const int k = k0 + 16 * u;
+      av[u] = make_uint4(0, 0, 0, 0);
+      bv[u] = make_uint4(0, 0, 0, 0);
+      if (k < D) {
+        if (cr >= 0) av[u] = *reinterpret_cast<const uint4*>(ar + k);
+        bv[u] = *reinterpret_cast<const uint4*>(br + k);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av[u]),
+                                                    __builtin_bit_cast(bf16x8_t, bv[u]), acc,
+                                                    0, 0, 0);
   }
   if (row == 0) {
 #pragma unroll
