@@ -537,7 +537,56 @@ __device__ void hd_dist_rows2(const TX* __restrict__ X, int D, int32_t i0, int32
   wave_lds_sync();
 }
 
-template <typename TX, int VEC>
+// The BF16 screen for two points at once.  Slots 0..n0-1 are the ids in
+// lanes 0..n0-1 (candidates of point i0), slots n0..n0+n1-1 those in lanes
+// 32..32+n1-1 (point i1).  Each pass takes 32 slots as the rows of A; the
+// columns of B hold x_i0 (0..15) and x_i1 (16..31), so the product of slot s
+// with its own point is column 0 or 16 of its row.  sdot[slot] gets it.
+__device__ void screen_dots2(const uint16_t* __restrict__ X, int D, int32_t i0, int32_t i1,
+                             int cid, int n0, int n1, float* sdot) {
+  const int lane = lane_id(), row = lane & 31, half = lane >> 5;
+  const uint16_t* br = X + (int64_t)(row < 16 ? i0 : i1) * D + half * 8;
+  const int nrows = n0 + n1;
+  constexpr int kSteps = 4;
+  for (int p = 0; p < nrows; p += 32) {
+    const int slot = p + row;
+    const int src = slot >= n0 ? 32 + slot - n0 : slot;
+    const int cs = __shfl(cid, src & (kWave - 1));
+    const int cr = slot < nrows ? cs : -1;
+    const uint16_t* ar = X + (int64_t)(cr >= 0 ? cr : i0) * D + half * 8;
+    f32x16_t acc = {};
+    for (int k0 = 0; k0 < D; k0 += 16 * kSteps) {
+      uint4 av[kSteps], bv[kSteps];
+#pragma unroll
+      for (int u = 0; u < kSteps; ++u) {
+        const int k = k0 + 16 * u;
+        av[u] = make_uint4(0, 0, 0, 0);
+        bv[u] = make_uint4(0, 0, 0, 0);
+        if (k < D) {
+          if (cr >= 0) av[u] = *reinterpret_cast<const uint4*>(ar + k);
+          bv[u] = *reinterpret_cast<const uint4*>(br + k);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSteps; ++u)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av[u]),
+                                                      __builtin_bit_cast(bf16x8_t, bv[u]), acc,
+                                                      0, 0, 0);
+    }
+    // lanes 0 / 32 hold column 0 and lanes 16 / 48 column 16, for rows
+    // 4 half + 8 (r / 4) + r mod 4 in register r
+    if (row == 0 || row == 16) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int s = p + 4 * half + 8 * (r >> 2) + (r & 3);
+        if (s < nrows && ((s < n0) == (row == 0))) sdot[s] = acc[r];
+      }
+    }
+  }
+  wave_lds_sync();
+}
+
+template <typename TX, int VEC, bool SCREEN = false>
 __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
   const Scalars* sc = a.sc;
   if (!sc->fire) return;
@@ -596,7 +645,25 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
     wave_lds_sync();
   }
   const int nload = n;
-  const int n0 = __shfl(n, 0), n1 = __shfl(n, 32);
+  int n0 = __shfl(n, 0), n1 = __shfl(n, 32);
+  if constexpr (SCREEN) {
+    // keep the candidates whose expanded-form distance
+    // |x_i|^2 + |x_c|^2 - 2 x_i.x_c is within the current K-th distance (1 + margin)
+    screen_dots2(static_cast<const uint16_t*>(a.X), a.D, i0, i1, c, n0, n1, S.d2);
+    const float r_i = __shfl(od2, hb + Kh - 1);
+    const float dot = hl < n ? S.d2[(h ? n0 : 0) + hl] : 0.0f;
+    const float approx = (live ? a.xnorm[i] : 0.0f) + (c >= 0 ? a.xnorm[c] : 0.0f) - 2.0f * dot;
+    c = (c >= 0 && approx <= r_i * (1.0f + a.h.margin)) ? c : -1;
+    wave_lds_sync();
+    const uint32_t m = (uint32_t)(__ballot(c >= 0) >> hb);
+    n = __popc(m);
+    if (c >= 0) S.lst[hb + __popc(m & ((1u << hl) - 1u))] = c;
+    wave_lds_sync();
+    c = hl < n ? S.lst[hb + hl] : -1;
+    wave_lds_sync();
+    n0 = __shfl(n, 0);
+    n1 = __shfl(n, 32);
+  }
   hd_dist_rows2<TX, VEC>(static_cast<const TX*>(a.X), a.D, i0, i1, c, n0, n1, S.d2);
   uint64_t ck = c >= 0 ? pack_key(S.d2[(h ? n0 : 0) + hl], c) : kNoKey;
   uint32_t aux = 0;
@@ -1426,7 +1493,10 @@ struct RefineLaunch {
 hipError_t launch_hd_refine_bf16(const StepArgs& a, hipStream_t s) {
   if (a.xdtype != 1 || a.D % 16 != 0 || !a.xvec_ok) return hipErrorInvalidValue;
   const int chunks = (a.D / 8 + 63) / 64;
-  if (chunks <= 1)
+  if (chunks <= 1 && a.Kh <= 32 && a.Kl <= 32)
+    hipLaunchKernelGGL((k_hd_refine2<uint16_t, 8, true>), dim3(wave_blocks((a.N + 1) / 2)),
+                       dim3(kBlock), 0, s, a);
+  else if (chunks <= 1)
     hipLaunchKernelGGL((k_hd_refine<uint16_t, 8, 1, true>), dim3(wave_blocks(a.N)), dim3(kBlock),
                        0, s, a);
   else if (chunks <= 4)
