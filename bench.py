@@ -652,8 +652,8 @@ def main():
     if args.gather_table:
         # random-gather ceilings for the row sizes the step kernels gather
         for rb, rows, table in ((16, 128, 2 ** 24), (64, 112, 2 ** 26), (128, 64, 2 ** 27),
-                                (256, 32, 2 ** 28), (256, 32, 2 ** 31), (512, 32, 2 ** 29),
-                                (512, 32, 2 ** 32)):
+                                (128, 64, 2 ** 29), (256, 32, 2 ** 28), (256, 32, 2 ** 31),
+                                (512, 32, 2 ** 29), (512, 32, 2 ** 32)):
             print(json.dumps(gather_probe(rb, rows, table)), flush=True)
         return
 
