@@ -60,6 +60,12 @@ def test_defaults_and_argument_checks(fsne_lib):
     assert init(xdt=7) == F.FSNE_EINVAL
     assert init(X=None) == F.FSNE_EINVAL
     assert init(cap=50) == F.FSNE_EINVAL
+    # widest rows: FP32 4096 (D % 4 == 0), BF16 2048 (D % 8 == 0), else 1024
+    assert L.fsne_max_dim(0, 4096) == 4096 and L.fsne_max_dim(0, 1023) == 1024
+    assert L.fsne_max_dim(1, 2048) == 2048 and L.fsne_max_dim(1, 1020) == 1024
+    assert init(D=4100) == F.FSNE_EINVAL
+    assert init(D=1025) == F.FSNE_EINVAL
+    assert init(D=2056, xdt=1) == F.FSNE_EINVAL
     for bad in (dict(alpha=0.0), dict(alpha=-1.0), dict(perplexity=16.0), dict(perplexity=1.0),
                 dict(momentum=1.0), dict(n_neg=65), dict(hd_mode=3), dict(dist_mode=1),
                 dict(e_smooth=0.0), dict(lr=float("nan"))):
