@@ -125,9 +125,26 @@ double fsneo_hd_dist2(const void *X, int32_t xdtype, int32_t D, int64_t a, int64
 }
 
 /* LD squared distance used to decide LD list membership.  The decision is  */
-/* taken in single precision on the single-precision coordinates, summing    */
-/* (y_jc - y_ic)^2 over c in index order without fused multiply-add.         */
+/* taken in single precision on the single-precision coordinates: the       */
+/* squares (y_jc - y_ic)^2, each rounded, are summed pairwise, leaves in     */
+/* index order, as a balanced binary tree over 64 leaves (components beyond */
+/* d are zero): adjacent pairs are added level by level, each sum rounded.  */
 static float ld_dist2_decision(const double *Y, int32_t d, int64_t i, int64_t j)
+{
+    volatile float t[64];
+    for (int32_t c = 0; c < 64; ++c) {
+        volatile float diff = c < d ? (float)Y[j * d + c] - (float)Y[i * d + c] : 0.0f;
+        t[c] = diff * diff;
+    }
+    for (int w = 64; w > 1; w /= 2)
+        for (int k = 0; k < w / 2; ++k) t[k] = t[2 * k] + t[2 * k + 1];
+    return t[0];
+}
+
+/* Squared distance of the clustering's eps test: single precision on the  */
+/* single-precision coordinates, summed over c in index order, each         */
+/* operation rounded, no fused multiply-add.                                */
+static float cluster_dist2(const double *Y, int32_t d, int64_t i, int64_t j)
 {
     volatile float acc = 0.0f;
     for (int32_t c = 0; c < d; ++c) {
@@ -533,7 +550,7 @@ int fsneo_init(fsneo_state *S, const fsneo_hp *hp)
 {
     const int64_t N = S->N;
     if (S->K_hd < 2 || S->K_hd > 64 || S->K_ld < 1 || S->K_ld > 64 || S->K_hd >= N ||
-        S->K_ld >= N)
+        S->K_ld >= N || S->d < 1 || S->d > 64)
         return -1;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < N; ++i) {
@@ -884,7 +901,7 @@ int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t 
     for (int64_t i = 0; i < N; ++i) {
         int cnt = 1;
         for (int32_t k = 0; k < K; ++k)
-            cnt += ld_dist2_decision(S->Y, d, i, S->ld_idx[i * K + k]) <= eps2;
+            cnt += cluster_dist2(S->Y, d, i, S->ld_idx[i * K + k]) <= eps2;
         core[i] = cnt >= min_pts;
         parent[i] = i;
     }
@@ -893,7 +910,7 @@ int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t 
         if (!core[i]) continue;
         for (int32_t k = 0; k < K; ++k) {
             int64_t j = S->ld_idx[i * K + k];
-            if (!core[j] || ld_dist2_decision(S->Y, d, i, j) > eps2) continue;
+            if (!core[j] || cluster_dist2(S->Y, d, i, j) > eps2) continue;
             int64_t a = uf_find(parent, i), b = uf_find(parent, j);
             if (a < b) parent[b] = a;
             else if (b < a) parent[a] = b;
@@ -907,7 +924,7 @@ int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t 
         for (int32_t k = 0; k < K; ++k) {
             int64_t j = S->ld_idx[i * K + k];
             if (core[i] == core[j]) continue;
-            float q = ld_dist2_decision(S->Y, d, i, j);
+            float q = cluster_dist2(S->Y, d, i, j);
             if (q > eps2) continue;
             int64_t border = core[i] ? j : i, owner = core[i] ? i : j;
             int64_t lab = uf_find(parent, owner);

@@ -807,10 +807,13 @@ __device__ __forceinline__ void load_chunk(const float* __restrict__ p, float* r
   }
 }
 
-// The LD distance that decides list membership: components summed in index
-// order, each square and each sum rounded separately.  The row is split over
-// G lanes, so the running sum is handed from lane to lane in component order;
-// the last lane of the group ends with the total.
+// The LD distance that decides list membership: the squares, each rounded,
+// summed pairwise as a balanced binary tree with the components in index
+// order at the leaves (padding components are zero and change nothing).  A
+// lane holds VEC consecutive components, the row's G lanes hold the row in
+// order, so the lane's pairs come first, then lanes are paired by xor
+// butterflies (x + y = y + x exactly, so both lanes of a pair get the same
+// node); every lane of the group ends with the total.
 template <int DP>
 __device__ __forceinline__ float ld_decision_d2(const float* yi, const float* yj, int q) {
 #pragma clang fp contract(off)
@@ -821,18 +824,15 @@ __device__ __forceinline__ float ld_decision_d2(const float* yi, const float* yj
     const float df = yj[v] - yi[v];
     sq[v] = df * df;
   }
-  float acc = 0.0f;
+  float s;
+  if constexpr (Geo::VEC == 4)
+    s = (sq[0] + sq[1]) + (sq[2] + sq[3]);
+  else
+    s = sq[0] + sq[1];
 #pragma unroll
-  for (int k = 0; k < Geo::G; ++k) {
-    const float prev = Geo::G > 1 ? dpp<0x111>(acc) : 0.0f;   // row_shr:1
-    if (q == k) {
-      float s = k == 0 ? 0.0f : prev;
-#pragma unroll
-      for (int v = 0; v < Geo::VEC; ++v) s = s + sq[v];
-      acc = s;
-    }
-  }
-  return acc;
+  for (int m = 1; m < Geo::G; m <<= 1) s = s + __shfl_xor(s, m);
+  (void)q;
+  return s;
 }
 
 // Sum over the G lanes of a row group (G <= 16: every lane gets it).
