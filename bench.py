@@ -91,6 +91,7 @@ def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=
     emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=seed,
                       hp=schedule(F, base, 0))
     emb.sync()
+    r0 = emb.stats()["hd_refinements"]
     done, secs, curve = 0, 0.0, []
     while done < n_iter:
         stop = min(n_iter, (done // every + 1) * every)
@@ -108,6 +109,7 @@ def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=
     st = emb.stats()
     emb.close()
     return dict(iters=n_iter, seconds=round(secs, 3), iters_per_s=round(n_iter / secs, 2),
+                hd_refinements=int(st["hd_refinements"] - r0),
                 recall_at_32=curve[-1][2], final_E=round(float(st["E"]), 4),
                 nonfinite=int(st["nonfinite"]), curve=curve)
 
@@ -788,6 +790,17 @@ def main():
         target = round(0.95 * runs["f32"]["recall_at_32"], 4)
         for r in runs.values():
             r["seconds_to_target"] = seconds_to(r["curve"], target)
+        # the FP32 run against HBM: algorithmic bytes of every launch of the
+        # run (candidate rows per point as in the profiled steps) over its time
+        r = runs["f32"]
+        gb = (r["hd_refinements"] * bpp["hd_refine"]
+              + r["iters"] * (bpp["ld_grad"] + bpp["update"])) * N / 1e9
+        r["roofline"] = {"algorithmic_GB": round(gb, 1),
+                         "GBps": round(gb / r["seconds"], 1),
+                         "frac": round(gb / r["seconds"] / PEAK_HBM_GBS, 4),
+                         "basis": "hd_refine bytes x refining iterations + (ld_grad + update) "
+                                  "bytes x iterations, candidate rows per point from the "
+                                  "profiled steps"}
         out["runs"] = runs
         out["runs_recall_target"] = target
     if not args.no_dynamic:

@@ -99,6 +99,7 @@ typedef struct fsne_stats {
     uint32_t hd_cand_rows; /* distinct HD candidate rows loaded by the last HD
                               refinement (duplicates are never loaded)             */
     uint32_t ld_cand_rows; /* distinct LD candidate rows of the last iteration     */
+    uint32_t hd_refinements; /* iterations that refined the HD lists since init    */
 } fsne_stats;
 
 /* Largest HD dimension D the library accepts for rows of xdtype: 4096 for

@@ -558,6 +558,7 @@ fsne_status fsne_get_stats(fsne_ctx* c, fsne_stats* st) {
   st->nonfinite = s.nonfinite;
   st->hd_cand_rows = s.hd_cand;
   st->ld_cand_rows = s.ld_cand;
+  st->hd_refinements = s.refinements;
   if (s.nonfinite) return fail(c, FSNE_ENONFINITE, "embedding holds a NaN or infinity");
   return FSNE_OK;
 }

@@ -38,6 +38,7 @@ struct Scalars {
   int32_t last_fired;  // whether iteration t-1 refined the HD lists
   uint32_t hd_cand;    // distinct HD candidate rows loaded in the last iteration
   uint32_t ld_cand;    // distinct LD candidate rows loaded in the last iteration
+  uint32_t refinements;  // iterations that refined the HD lists since init
 };
 
 // Hyperparameters in the form the kernels use.

@@ -1268,6 +1268,7 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a) {
         sc->n_new = sf[0];
         E = E_next(E, sf[0], a.N, a.h.e_smooth);
         sc->hd_cur ^= 1;
+        sc->refinements += 1u;
       }
       sc->E = E;
       sc->Z = Z;

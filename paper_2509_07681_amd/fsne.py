@@ -43,7 +43,7 @@ class fsne_stats(C.Structure):
     _fields_ = [("N", C.c_int64), ("t", C.c_uint32), ("E", C.c_float), ("next_fire", C.c_int32),
                 ("last_fired", C.c_int32), ("n_new", C.c_int32), ("Z", C.c_float),
                 ("nonfinite", C.c_int32), ("hd_cand_rows", C.c_uint32),
-                ("ld_cand_rows", C.c_uint32)]
+                ("ld_cand_rows", C.c_uint32), ("hd_refinements", C.c_uint32)]
 
 
 _lib = None

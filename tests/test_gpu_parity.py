@@ -145,6 +145,7 @@ def test_step_matches_oracle_with_injection(oracle_lib, fsne_lib, name, hd_mode)
     bf16 = X.dtype == np.uint16
     d = c["d"]
     fired_seen = set()
+    n_fired, r0 = 0, emb.stats()["hd_refinements"]
     for it in range(6):
         emb.set_state(S.as_gpu_state())
         Y0 = S.live("Y").copy()
@@ -154,6 +155,8 @@ def test_step_matches_oracle_with_injection(oracle_lib, fsne_lib, name, hd_mode)
         st = emb.stats()
         assert st["last_fired"] == out["fired"]
         fired_seen.add(out["fired"])
+        n_fired += int(out["fired"])
+        assert st["hd_refinements"] - r0 == n_fired
         g = emb.state()
         assert g["t"] == out["t"] and g["E"] == np.float32(out["E"])
         same = _check_hd(X, c, g, S, bf16)
