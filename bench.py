@@ -63,7 +63,7 @@ def bytes_per_point(cfg, xbytes, hd_cand, ld_cand):
     return dict(hd_refine=hd, ld_grad=ld, update=upd)
 
 
-def survey_bytes_per_point(cfg, xbytes):
+def all_slot_bytes_per_point(cfg, xbytes):
     """The same with every one of the 32 candidate slots counted."""
     D, d, Kh, Kl, nn = cfg["D"], cfg["d"], cfg["K_hd"], cfg["K_ld"], cfg["n_neg"]
     sx, sy = D * xbytes, 4 * d
@@ -693,7 +693,7 @@ def main():
 
     hd_cand, ld_cand = float(np.mean(hd_c)), float(np.mean(ld_c))
     bpp = bytes_per_point(cfg, 4, hd_cand, ld_cand)
-    sbpp = survey_bytes_per_point(cfg, 4)
+    sbpp = all_slot_bytes_per_point(cfg, 4)
     kernels = {}
     for k, (ms, n) in kt.items():
         avg = ms / max(n, 1)
