@@ -758,7 +758,25 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
   bool member = false;
   if (d2 <= rj.z * (1.0f + 1e-6f)) {
     const int32_t* row = hl + (int64_t)j * Kh;
-    if ((Kh & 3) == 0) {
+    if ((Kh & 7) == 0) {
+      int k0 = 0, k1 = Kh >> 2;   // in 4-entry groups
+      if (!standalone) {
+        // A refinement leaves every list sorted by (distance, index), and
+        // both lists of a pair hold the same distance (up to the rounding of
+        // an injected state, hence the band): i can only be in the half of
+        // j's list its distance falls in; near the middle both are scanned.
+        const float mid = hd[(int64_t)j * Kh + (Kh >> 1) - 1];
+        if (d2 < mid * (1.0f - 1e-5f))
+          k1 = Kh >> 3;
+        else if (d2 > mid * (1.0f + 1e-5f))
+          k0 = Kh >> 3;
+      }
+      const int4* r4 = reinterpret_cast<const int4*>(row);
+      for (int k = k0; k < k1; ++k) {
+        const int4 v = r4[k];
+        member |= (v.x == i) | (v.y == i) | (v.z == i) | (v.w == i);
+      }
+    } else if ((Kh & 3) == 0) {
       const int4* r4 = reinterpret_cast<const int4*>(row);
       for (int k = 0; k < (Kh >> 2); ++k) {
         const int4 v = r4[k];
