@@ -730,6 +730,8 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
 //   p_{i|j} = exp(-beta_j (d2 - m_j)) invS_j if i is in j's HD list, else 0.
 // standalone = 1: run regardless of the coin, on the current lists.
 // ---------------------------------------------------------------------------
+constexpr int kPsymHalvings = 2;   // range halvings of the membership scan
+
 __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
   const Scalars* sc = a.sc;
   const int fire = standalone ? 0 : sc->fire;
@@ -759,18 +761,25 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
   if (d2 <= rj.z * (1.0f + 1e-6f)) {
     const int32_t* row = hl + (int64_t)j * Kh;
     if ((Kh & 7) == 0) {
-      int k0 = 0, k1 = Kh >> 2;   // in 4-entry groups
+      int lo = 0, hi = Kh;   // entries that can hold i
       if (!standalone) {
         // A refinement leaves every list sorted by (distance, index), and
         // both lists of a pair hold the same distance (up to the rounding of
-        // an injected state, hence the band): i can only be in the half of
-        // j's list its distance falls in; near the middle both are scanned.
-        const float mid = hd[(int64_t)j * Kh + (Kh >> 1) - 1];
-        if (d2 < mid * (1.0f - 1e-5f))
-          k1 = Kh >> 3;
-        else if (d2 > mid * (1.0f + 1e-5f))
-          k0 = Kh >> 3;
+        // an injected state, hence the band): i can only be in the part of
+        // j's list its distance falls in, found by halving the range while
+        // the parts stay whole 4-entry groups; near a cut both are kept.
+        for (int h = 0; h < kPsymHalvings && ((hi - lo) & 7) == 0; ++h) {
+          const int m = (lo + hi) >> 1;
+          const float cut = hd[(int64_t)j * Kh + m - 1];
+          if (d2 < cut * (1.0f - 1e-5f))
+            hi = m;
+          else if (d2 > cut * (1.0f + 1e-5f))
+            lo = m;
+          else
+            break;
+        }
       }
+      const int k0 = lo >> 2, k1 = hi >> 2;   // in 4-entry groups
       const int4* r4 = reinterpret_cast<const int4*>(row);
       for (int k = k0; k < k1; ++k) {
         const int4 v = r4[k];
