@@ -79,14 +79,15 @@ def schedule(F, base, t):
                                      "momentum": 0.5 if early else 0.8})
 
 
-def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=50):
+def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=50,
+                labels=None, lr_div=12.0):
     """n_iter iterations under the coin with the standard schedule; HD recall@K
     on the query sample every ``every`` iterations (the clock is stopped while
     the recall is measured)."""
     from inputs.knn_metrics import recall_at_k
 
     N = X.shape[0]
-    base = dict(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=N / 12.0,
+    base = dict(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=N / lr_div,
                 n_neg=cfg["n_neg"], hd_mode=0, dist_mode=dist_mode)
     emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=seed,
                       hp=schedule(F, base, 0))
@@ -107,8 +108,12 @@ def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=
             idx, _ = emb.knn(0)
             curve.append([done, round(secs, 4), round(recall_at_k(idx, X, queries, ex_d2), 4)])
     st = emb.stats()
+    extra = {}
+    if labels is not None:
+        ld, _ = emb.knn(1)
+        extra["ld_same_class"] = round(float((labels[ld] == labels[:, None]).mean()), 4)
     emb.close()
-    return dict(iters=n_iter, seconds=round(secs, 3), iters_per_s=round(n_iter / secs, 2),
+    return dict(**extra, iters=n_iter, seconds=round(secs, 3), iters_per_s=round(n_iter / secs, 2),
                 hd_refinements=int(st["hd_refinements"] - r0),
                 recall_at_32=curve[-1][2], final_E=round(float(st["E"]), 4),
                 nonfinite=int(st["nonfinite"]), curve=curve)
@@ -328,6 +333,37 @@ def large_run(F, args):
         out[name] = {"seconds": round(secs, 3), "iters_per_s": round(500 / secs, 2),
                      "recall_at_64": round(recall_at_k(idx, Xb, q, ex), 4),
                      "final_E": round(float(st["E"]), 4), "nonfinite": int(st["nonfinite"])}
+    return out
+
+
+def image_run(F, args):
+    """The image-like workload: 70,000 rows of 784 values in [0, 1] (about 80 %
+    zeros) from 10 class prototypes, FP32, embedded in 2-D with K_hd = K_ld =
+    32, 16 negatives, perplexity 10, for each tail alpha in {0.5, 1, 4}:
+    2000 iterations under the coin with the standard schedule (learning rate
+    N/48, as for the 2-D online-use runs), wall seconds, HD recall@32 on
+    1,000 queries against exact neighbours, and the fraction of each point's
+    32 LD neighbours that share its class."""
+    import numpy as np
+
+    from inputs.generators import RUN_SEED, make_workload, y_init
+    from inputs.knn_metrics import exact_knn
+
+    X, lab, cfg = make_workload("image_70k")
+    N, K = X.shape[0], cfg["K_hd"]
+    rng = np.random.default_rng(3)
+    q = np.sort(rng.choice(N, 1000, replace=False))
+    _, ex = exact_knn(X, q, K)
+    out = {"metric": "iters/s and HD recall@32 per tail alpha",
+           "config": {"workload": "image_70k: N=70,000 image-like rows in [0,1]^784 (FP32), d=2, "
+                                  "K_hd=K_ld=32, 16 negatives, perplexity 10, 2000 iterations",
+                      "queries": int(q.size), "lr": "N/48"},
+           "alphas": {}}
+    for alpha in cfg["alpha"]:
+        cfg_a = {**cfg, "alpha": alpha}
+        r = quality_run(F, X, cfg_a, y_init(N, 2), cfg["n_iter"], RUN_SEED, q, ex, every=500,
+                        labels=lab, lr_div=48.0)
+        out["alphas"][str(alpha)] = r
     return out
 
 
@@ -589,6 +625,8 @@ def main():
                     help="run the feedback-loop experiment (fixed vs optimised embedding) instead")
     ap.add_argument("--hierarchy", action="store_true",
                     help="run the alpha-sweep hierarchy graph experiment instead")
+    ap.add_argument("--image", action="store_true",
+                    help="the 70k image-like workload for tail alphas 0.5, 1, 4")
     ap.add_argument("--scaling", action="store_true",
                     help="time per iteration across N at D = 32 (the paper's timing figure)")
     ap.add_argument("--scaling-sizes", type=int, nargs="+",
@@ -650,6 +688,9 @@ def main():
         return
     if args.scaling:
         print(json.dumps(scaling_run(F, args)))
+        return
+    if args.image:
+        print(json.dumps(image_run(F, args)))
         return
     if args.gather_table:
         # random-gather ceilings for the row sizes the step kernels gather
