@@ -19,6 +19,8 @@ pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarnin
 
 CASES = {
     "image_70k_f32": ("image_70k", False, 0, 1.0),
+    "image_70k_f32_a05": ("image_70k", False, 0, 0.5),
+    "image_70k_f32_a4": ("image_70k", False, 0, 4.0),
     "manifold_1m_f32": ("manifold_1m", False, 0, None),
     "manifold_1m_bf16_screen": ("manifold_1m", True, 1, None),
     "zipf_4m_bf16_screen": ("zipf_4m", True, 1, None),
