@@ -23,6 +23,7 @@ CASES = {
     "image_70k_f32_a4": ("image_70k", False, 0, 4.0),
     "manifold_1m_f32": ("manifold_1m", False, 0, None),
     "manifold_1m_bf16_screen": ("manifold_1m", True, 1, None),
+    "zipf_4m_bf16": ("zipf_4m", True, 0, None),
     "zipf_4m_bf16_screen": ("zipf_4m", True, 1, None),
 }
 
