@@ -659,8 +659,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 4}))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the step shards by point range; see the design notes).", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the library has no "
+              "multi-GPU path; the step would shard by point range.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
