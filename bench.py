@@ -46,18 +46,24 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def memo_width(D, xbytes, dist_mode=0):
+    """Remembered HD rejections per point (each read, then rewritten)."""
+    return 64 if dist_mode == 0 and D * xbytes >= 512 else 32
+
+
 def bytes_per_point(cfg, xbytes, hd_cand, ld_cand):
     """Bytes each kernel must move per point, no cache reuse assumed.
 
     hd_cand / ld_cand: mean number of distinct candidate rows per point that
-    the kernels loaded (duplicate slots are dropped before any row is read).
+    the kernels loaded (duplicate slots and remembered rejections are dropped
+    before any row is read).
     """
     D, d, Kh, Kl, nn = cfg["D"], cfg["d"], cfg["K_hd"], cfg["K_ld"], cfg["n_neg"]
     dp = 2
     while dp < d:
         dp *= 2
     sx, sy = D * xbytes, 4 * dp
-    hd = sx * (1 + hd_cand) + 16 * Kh + 4 * Kl + 96 + 33
+    hd = sx * (1 + hd_cand) + 16 * Kh + 4 * Kl + 96 + 33 + 8 * memo_width(D, xbytes)
     ld = sy * (1 + Kl + ld_cand + Kh + nn + 2) + 8 * Kh + 8 * Kl + 96 + 5
     upd = 6 * sy
     return dict(hd_refine=hd, ld_grad=ld, update=upd)
@@ -67,7 +73,7 @@ def all_slot_bytes_per_point(cfg, xbytes):
     """The same with every one of the 32 candidate slots counted."""
     D, d, Kh, Kl, nn = cfg["D"], cfg["d"], cfg["K_hd"], cfg["K_ld"], cfg["n_neg"]
     sx, sy = D * xbytes, 4 * d
-    hd = (C_SLOTS + 1) * sx + 96 + 16 * Kh + 12 + 24 * Kh + 12
+    hd = (C_SLOTS + 1) * sx + 96 + 16 * Kh + 12 + 24 * Kh + 12 + 8 * memo_width(D, xbytes)
     ld = sy + 8 * Kl + 8 * Kh + 96 + (Kl + C_SLOTS + Kh + nn) * sy + 2 * sy
     return dict(hd_refine=hd, ld_grad=ld, update=6 * sy)
 

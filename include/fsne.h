@@ -65,6 +65,18 @@ typedef struct fsne_hparams {
     float e_smooth;     /* smoothing weight lambda of E, in (0, 1]                 */
     float p_min;        /* refinement probability floor (0.05 in the paper)        */
     float rerank_margin;/* BF16 screen keeps candidates with d2~ <= r_i (1+margin)  */
+    int32_t reject_memo;/* 1: each point remembers the last candidates its HD
+                           refinements rejected (64 with direct distances on rows
+                           of 512 bytes or more, else 32) and does not evaluate
+                           them again; 0: every candidate is evaluated.  Both
+                           give the same
+                           lists: while X and the lists change only by
+                           refinement, a point's K-th HD distance never grows, so
+                           a rejected candidate would be rejected again.  The
+                           memory is cleared where that does not hold (drift,
+                           delete, a state load of the HD lists, a change of
+                           dist_mode or rerank_margin); inserted points start
+                           empty.                                               */
 } fsne_hparams;
 
 /* Host-side view of the iteration state for checkpoints and checks.  Every
@@ -108,7 +120,7 @@ int32_t fsne_max_dim(int32_t xdtype, int32_t D);
 
 /* Fill *hp with the defaults: alpha 1, perplexity 10, lr 100, momentum 0.5,
  * attr 1, rep 1, n_neg 16, hd_mode 0, dist_mode 0, e_smooth 0.1, p_min 0.05,
- * rerank_margin 2^-6.  Returns FSNE_EINVAL if hp is NULL. */
+ * rerank_margin 2^-6, reject_memo 1.  Returns FSNE_EINVAL if hp is NULL. */
 fsne_status fsne_default_hparams(fsne_hparams *hp);
 
 /* Create a context and its initial state (Sec. 3: optimisation starts right

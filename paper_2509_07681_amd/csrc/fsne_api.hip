@@ -95,6 +95,12 @@ StepArgs make_args(const fsne_ctx* c) {
   a.fpart = c->fpart;
   a.cpart = c->cpart;
   a.ldc = c->ldc;
+  a.memo = c->hp.reject_memo ? c->memo : nullptr;
+  // 64 remembered rejections pay where a saved row is large (direct distances
+  // on rows of 512 bytes or more); elsewhere the extra 256 bytes of memory
+  // traffic per point, or the screen kernel's registers, cost more than they save
+  const int64_t row_bytes = (int64_t)c->D * (c->xdtype == FSNE_F32 ? 4 : 2);
+  a.memo_w = (c->hp.dist_mode == 0 && row_bytes >= 512) ? 64 : 32;
   a.neg_scale = c->hp.n_neg > 0 ? (float)(c->N - 1) / (float)c->hp.n_neg : 0.0f;
   return a;
 }
@@ -124,6 +130,8 @@ fsne_status check_hparams(fsne_ctx* c, const fsne_hparams* hp, int32_t Kh, int32
     return fail(c, FSNE_EINVAL, "p_min must be in [0, 1]");
   if (!(hp->rerank_margin >= 0.0f) || !std::isfinite(hp->rerank_margin))
     return fail(c, FSNE_EINVAL, "rerank_margin must be >= 0");
+  if (hp->reject_memo < 0 || hp->reject_memo > 1)
+    return fail(c, FSNE_EINVAL, "reject_memo must be 0 or 1");
   return FSNE_OK;
 }
 
@@ -207,6 +215,14 @@ fsne_status refresh_affinities(fsne_ctx* c, bool recalibrate) {
   return FSNE_OK;
 }
 
+// Forget the rejected HD candidates of rows [r0, r0 + n).
+fsne_status clear_memo(fsne_ctx* c, int64_t r0, int64_t n) {
+  if (n > 0)
+    HIPCHK(c, hipMemsetAsync(c->memo + r0 * fsne::kMemo, 0xFF,
+                             sizeof(int32_t) * (size_t)n * fsne::kMemo, c->stream));
+  return FSNE_OK;
+}
+
 fsne_status alloc_state(fsne_ctx* c) {
   const size_t cap = (size_t)c->cap;
   TRY(dalloc(c, &c->Y, cap * c->DP));
@@ -227,7 +243,9 @@ fsne_status alloc_state(fsne_ctx* c) {
   TRY(dalloc(c, &c->rec, cap));
   TRY(dalloc(c, &c->flags, cap));
   TRY(dalloc(c, &c->moved, cap));
+  TRY(dalloc(c, &c->memo, cap * fsne::kMemo));
   TRY(dalloc(c, &c->sc, 1));
+  TRY(clear_memo(c, 0, c->cap));
   HIPCHK(c, hipMemsetAsync(c->A, 0, sizeof(float) * cap * c->DP, c->stream));
   HIPCHK(c, hipMemsetAsync(c->R, 0, sizeof(float) * cap * c->DP, c->stream));
   HIPCHK(c, hipMemsetAsync(c->Zh, 0, sizeof(float) * cap, c->stream));
@@ -353,6 +371,7 @@ fsne_status fsne_default_hparams(fsne_hparams* hp) {
   hp->e_smooth = 0.1f;
   hp->p_min = 0.05f;
   hp->rerank_margin = 1.0f / 64.0f;
+  hp->reject_memo = 1;
   return FSNE_OK;
 }
 
@@ -428,7 +447,11 @@ fsne_status fsne_set_hyperparams(fsne_ctx* c, const fsne_hparams* hp) {
   if (!c) return FSNE_EINVAL;
   TRY(check_hparams(c, hp, c->Kh, c->xdtype, c->D));
   const bool perp_changed = hp->perplexity != c->hp.perplexity;
+  // a rejection under one screen need not be one under another
+  const bool screen_changed =
+      hp->dist_mode != c->hp.dist_mode || hp->rerank_margin != c->hp.rerank_margin;
   c->hp = *hp;
+  if (screen_changed) TRY(clear_memo(c, 0, c->cap));
   if (perp_changed) {
     TRY(refresh_affinities(c, true));
   } else {
@@ -531,6 +554,9 @@ fsne_status fsne_set_state(fsne_ctx* c, const fsne_state_view* v) {
   if (v->rec) HIPCHK(c, hipMemcpyAsync(c->rec, v->rec, sizeof(float4) * N, k, c->stream));
   if (v->P) HIPCHK(c, hipMemcpyAsync(c->P, v->P, sizeof(float) * N * c->Kh, k, c->stream));
   if (v->flags) HIPCHK(c, hipMemcpyAsync(c->flags, v->flags, (size_t)N, k, c->stream));
+  // lists from outside may hold a larger K-th distance than the ones the
+  // remembered rejections were measured against
+  if (v->hd_idx || v->hd_d2) TRY(clear_memo(c, 0, c->cap));
   if (v->E) s.E = *v->E;
   s.t = t_new;
   s.nonfinite = 0;
@@ -577,6 +603,7 @@ fsne_status fsne_insert_points(fsne_ctx* c, const void* Xnew, int64_t n, const f
                            (size_t)n * c->D * xb, hipMemcpyHostToDevice, c->stream));
   TRY(put_Y(c, c->Y, Yinit, N0, n));
   HIPCHK(c, hipMemsetAsync(c->V + N0 * c->DP, 0, sizeof(float) * n * c->DP, c->stream));
+  TRY(clear_memo(c, N0, n));   // rows left by deleted points
   c->N = N0 + n;
   StepArgs a = make_args(c);
   a.hd_buf_host = s.hd_cur;
@@ -645,6 +672,8 @@ fsne_status fsne_drift_points(fsne_ctx* c, const int64_t* ids, const void* Xnew,
       st = hip_fail(c, e, "drift marks");
       break;
     }
+    // moved rows change distances in both directions: every rejection is void
+    if ((st = clear_memo(c, 0, c->cap)) != FSNE_OK) break;
     StepArgs a = make_args(c);
     if (c->xdtype == FSNE_BF16 &&
         (e = fsne::launch_xnorm(a, c->xnorm, 0, (int32_t)c->N, c->stream)) != hipSuccess) {
@@ -731,6 +760,8 @@ fsne_status fsne_delete_points(fsne_ctx* c, const int64_t* ids, int64_t n) {
       break;
     }
     c->N = N1;
+    // ids are renumbered and lists refilled at random: every rejection is void
+    if ((st = clear_memo(c, 0, c->cap)) != FSNE_OK) break;
     StepArgs a = make_args(c);
     if ((e = fsne::launch_delete_fix(a, dnew, c->stream)) != hipSuccess) {
       st = hip_fail(c, e, "delete lists");

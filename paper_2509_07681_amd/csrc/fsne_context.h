@@ -30,6 +30,7 @@ struct fsne_ctx {
   float4* rec = nullptr;
   uint8_t* flags = nullptr;
   uint8_t* moved = nullptr;
+  int32_t* memo = nullptr;   // cap x kMemo rejected HD candidates, -1 = empty
   fsne::Scalars* sc = nullptr;
   std::string err;
   std::vector<void*> owned;

@@ -7,6 +7,11 @@
 
 namespace fsne {
 
+// Rejected HD candidates remembered per point: a row of kMemo ids (the row
+// stride), of which the first memo_w are used, the most recent first, -1 =
+// empty; the valid entries are always a prefix.
+constexpr int kMemo = 64;
+
 // Everything a step kernel needs, passed by value as the kernel argument.
 struct StepArgs {
   const void* X;            // N x D, float or bfloat16 bits (xdtype 0 / 1)
@@ -30,6 +35,8 @@ struct StepArgs {
   int32_t* fpart;           // kReduceBlocks
   uint32_t* cpart;          // 2 x kReduceBlocks: candidate-row counts (HD, LD)
   uint8_t* ldc;             // N: LD candidate rows of each point in the last step
+  int32_t* memo;            // N x kMemo rejected HD candidates (nullptr: not used)
+  int32_t memo_w;           // entries of a row in use: 32 or 64
   float neg_scale;          // (N - 1) / n_neg
   int32_t hd_buf_host;      // HD buffer written by init / insert
   int32_t ld_buf_host;      // LD buffer written by init / insert

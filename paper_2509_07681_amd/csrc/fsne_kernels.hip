@@ -191,13 +191,17 @@ __device__ void hd_dist_rows(const TX* __restrict__ X, int D, int32_t i, int cid
 //   s 28..31  uniform other point
 // with a, b = floor(u * K / 2^32) from the block's first two words.  own /
 // other hold i's rows of L and Lx, one entry per lane.  A slot is dropped
-// if it gives i, an entry of i's own list, or the id of an earlier slot.
+// if it gives i, an entry of i's own list, or the id of an earlier slot, and
+// with MEMO also if it is one of the rejections i remembers (memo, one id
+// per lane, -1 for none): those would lose the merge again.
 // Returns the candidate id in lanes 0..31 (-1: dropped), -1 elsewhere.
 // ---------------------------------------------------------------------------
+template <bool MEMO = false>
 __device__ __forceinline__ int make_candidate(int32_t i, uint32_t t, uint32_t stream,
                                               const Hyper& h, const int32_t* __restrict__ L,
                                               int K, int own, const int32_t* __restrict__ Lx,
-                                              int Kx, int other, int32_t N, int* tab) {
+                                              int Kx, int other, int32_t N, int* tab,
+                                              int memo = -1) {
   const int lane = lane_id();
   const int s = lane & (kCand - 1);
   const uint4 u = philox((uint32_t)i, t, stream, (uint32_t)s, h.key0, h.key1);
@@ -221,6 +225,7 @@ __device__ __forceinline__ int make_candidate(int32_t i, uint32_t t, uint32_t st
   // surviving set of ids is the one the earliest-slot rule keeps.
   hash_clear(tab, nullptr);
   hash_insert(tab, nullptr, lane < K ? own : -1, 0);
+  if constexpr (MEMO) hash_insert(tab, nullptr, memo, 0);
   const bool fresh = hash_insert(tab, nullptr, (lane < kCand && c != i) ? c : -1, 0);
   return fresh ? c : -1;
 }
@@ -368,6 +373,33 @@ __device__ __forceinline__ float screen_dots(const uint16_t* __restrict__ X, int
 }
 
 // ---------------------------------------------------------------------------
+// New memory of rejected candidates: this refinement's rejections first (the
+// screened-out ids in lane order, then the re-ranked losers in key order),
+// then the old entries, as many as the row's width (32 or 64) holds.  The
+// new ids are never among the old ones (those were not evaluated), so the
+// row stays duplicate-free.  One point per wave; old: entry `lane` of the row
+// (lanes < width); lanes >= kCand pass -1 as rejections.
+// ---------------------------------------------------------------------------
+static_assert(kMemo == kWave && kCand <= 32, "one remembered entry per lane at the widest");
+
+__device__ __forceinline__ void remember_rejections(int32_t* __restrict__ row, int width,
+                                                    int old, int screened_out, int rejected,
+                                                    int* lst) {
+  const int lane = lane_id();
+  const uint64_t ms = __ballot(screened_out >= 0);
+  const uint64_t mr = __ballot(rejected >= 0);
+  const int ns = __popcll(ms), nr = __popcll(mr);
+  if (ns + nr == 0) return;
+  if (screened_out >= 0) lst[popc_below(ms, lane)] = screened_out;
+  if (rejected >= 0) lst[ns + popc_below(mr, lane)] = rejected;
+  wave_lds_sync();
+  const int nn = ns + nr;
+  const int shifted = __shfl(old, lane >= nn ? lane - nn : 0);
+  if (lane < width) row[lane] = lane < nn ? lst[lane] : shifted;
+  wave_lds_sync();
+}
+
+// ---------------------------------------------------------------------------
 // HD refinement of point i (runs when the coin fired): candidates from the
 // HD lists and the LD lists of iteration t, their distances, merge into the
 // sorted list, flag, and recalibration of beta_i when the list changed.
@@ -390,17 +422,22 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
   const int own = lane < Kh ? hin[(int64_t)i * Kh + lane] : -1;
   const float od2 = lane < Kh ? din[(int64_t)i * Kh + lane] : kInf;
   const int oth = lane < Kl ? lin[(int64_t)i * Kl + lane] : -1;
+  const int memo = (a.memo && lane < a.memo_w) ? a.memo[(int64_t)i * kMemo + lane] : -1;
   // candidates, compacted into lanes 0 .. n-1 so that only n rows are visited
-  int c = make_candidate(i, t, kStreamHDC, a.h, hin, Kh, own, lin, Kl, oth, a.N, S.tab);
+  int c = make_candidate<true>(i, t, kStreamHDC, a.h, hin, Kh, own, lin, Kl, oth, a.N, S.tab,
+                               memo);
   int n = compact_ids(c, S.lst);
   const int nload = n;   // candidate rows read from X
+  int screened_out = -1;
   if constexpr (SCREEN) {
     // keep the candidates whose expanded-form distance
     // |x_i|^2 + |x_c|^2 - 2 x_i.x_c is within the current K-th distance (1 + margin)
     const float dot = screen_dots(static_cast<const uint16_t*>(a.X), a.D, i, c, S.d2);
     const float r_i = readlane_f(od2, Kh - 1);
     const float approx = a.xnorm[i] + (c >= 0 ? a.xnorm[c] : 0.0f) - 2.0f * dot;
-    c = (c >= 0 && approx <= r_i * (1.0f + a.h.margin)) ? c : -1;
+    const bool keep = c >= 0 && approx <= r_i * (1.0f + a.h.margin);
+    screened_out = keep ? -1 : c;
+    c = keep ? c : -1;
     n = compact_ids(c, S.lst);
   }
   hd_dist_rows<TX, VEC, CH>(static_cast<const TX*>(a.X), a.D, i, c, n, S.d2);
@@ -457,6 +494,11 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
   const bool changed = __ballot(enter) != 0ull;
   // bit 0: list changed; bits 1..6: candidate rows loaded (for measurement)
   if (lane == 0) a.flags[i] = (uint8_t)((changed ? 1 : 0) | (nload << 1));
+  if (a.memo) {
+    const int rejected = (lane < ncand && !enter) ? key_id(ck) : -1;
+    remember_rejections(a.memo + (int64_t)i * kMemo, a.memo_w, memo, screened_out, rejected,
+                        S.lst);
+  }
   if (changed) {
     const float sorted = lane < Kh ? S.row[lane] : 0.0f;
     const float4 r = calibrate_row(sorted, Kh, a.h, a.rec[i].x);
@@ -482,6 +524,37 @@ struct WaveLds2 {
   uint64_t ck[kWave];        // sorted candidate keys, 32 per half
   uint64_t ok[kWave];        // old list keys, 32 per half
 };
+
+// remember_rejections for the two points of a wave, each half on its own row
+// of MW entries; old[r] holds entry 32 r + hl of the half's row.
+template <int MW>
+__device__ __forceinline__ void remember_rejections2(int32_t* __restrict__ memo, int32_t i,
+                                                     bool live, const int* old,
+                                                     int screened_out, int rejected, int* lst) {
+  constexpr int R = MW / 32;
+  const int lane = lane_id(), hl = lane & 31, hb = lane & 32;
+  const uint32_t ms = (uint32_t)(__ballot(screened_out >= 0) >> hb);
+  const uint32_t mr = (uint32_t)(__ballot(rejected >= 0) >> hb);
+  const int ns = __popc(ms), nn = ns + __popc(mr);
+  const uint32_t below = (1u << hl) - 1u;
+  if (screened_out >= 0) lst[hb + __popc(ms & below)] = screened_out;
+  if (rejected >= 0) lst[hb + ns + __popc(mr & below)] = rejected;
+  wave_lds_sync();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = 32 * r + hl;            // position in the new row
+    const int q = p - nn;                 // position in the old row (p >= nn)
+    const int src = hb + (q & 31);
+    int shifted = -1;
+#pragma unroll
+    for (int r2 = 0; r2 < R; ++r2) {
+      const int v = __shfl(old[r2], src);
+      if (q >= 0 && (q >> 5) == r2) shifted = v;
+    }
+    if (live && nn > 0) memo[(int64_t)i * kMemo + p] = p < nn ? lst[hb + p] : shifted;
+  }
+  wave_lds_sync();
+}
 
 // Squared distances for the candidates of both points: slots 0..n0-1 are the
 // ids in lanes 0..n0-1 (point i0), slots n0..n0+n1-1 those in lanes
@@ -586,8 +659,9 @@ __device__ void screen_dots2(const uint16_t* __restrict__ X, int D, int32_t i0, 
   wave_lds_sync();
 }
 
-template <typename TX, int VEC, bool SCREEN = false>
+template <typename TX, int VEC, bool SCREEN, int MW>
 __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
+  static_assert(MW % 32 == 0 && MW <= kMemo, "whole rows of 32 per half");
   const Scalars* sc = a.sc;
   if (!sc->fire) return;
   __shared__ WaveLds2 lds_all[kWavesPerBlock];
@@ -607,6 +681,10 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
   const int own = (live && hl < Kh) ? hin[(int64_t)i * Kh + hl] : -1;
   const float od2 = (live && hl < Kh) ? din[(int64_t)i * Kh + hl] : kInf;
   const int oth = (live && hl < Kl) ? lin[(int64_t)i * Kl + hl] : -1;
+  int memo[MW / 32];        // entries hl, hl + 32, ... of i's row
+#pragma unroll
+  for (int r = 0; r < MW / 32; ++r)
+    memo[r] = (a.memo && live) ? a.memo[(int64_t)i * kMemo + 32 * r + hl] : -1;
 
   // candidates (the one-point rule, per half)
   int c = -1;
@@ -631,6 +709,8 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
     for (int k = 0; k < kHashSlots / 32; ++k) tab[k * 32 + hl] = -1;
     wave_lds_sync();
     hash_insert(tab, nullptr, hl < Kh ? own : -1, 0);
+#pragma unroll
+    for (int r = 0; r < MW / 32; ++r) hash_insert(tab, nullptr, memo[r], 0);
     const bool fresh = hash_insert(tab, nullptr, c != i ? c : -1, 0);
     c = fresh ? c : -1;
   }
@@ -646,6 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
   }
   const int nload = n;
   int n0 = __shfl(n, 0), n1 = __shfl(n, 32);
+  int screened_out = -1;
   if constexpr (SCREEN) {
     // keep the candidates whose expanded-form distance
     // |x_i|^2 + |x_c|^2 - 2 x_i.x_c is within the current K-th distance (1 + margin)
@@ -653,7 +734,9 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
     const float r_i = __shfl(od2, hb + Kh - 1);
     const float dot = hl < n ? S.d2[(h ? n0 : 0) + hl] : 0.0f;
     const float approx = (live ? a.xnorm[i] : 0.0f) + (c >= 0 ? a.xnorm[c] : 0.0f) - 2.0f * dot;
-    c = (c >= 0 && approx <= r_i * (1.0f + a.h.margin)) ? c : -1;
+    const bool keep = c >= 0 && approx <= r_i * (1.0f + a.h.margin);
+    screened_out = keep ? -1 : c;
+    c = keep ? c : -1;
     wave_lds_sync();
     const uint32_t m = (uint32_t)(__ballot(c >= 0) >> hb);
     n = __popc(m);
@@ -716,6 +799,10 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
   wave_lds_sync();
   const bool changed = ((uint32_t)(__ballot(enter) >> hb)) != 0u;
   if (live && hl == 0) a.flags[i] = (uint8_t)((changed ? 1 : 0) | (nload << 1));
+  if (a.memo) {
+    const int rejected = (live && hl < ncand && !enter) ? key_id(ck) : -1;
+    remember_rejections2<MW>(a.memo, i, live, memo, screened_out, rejected, S.lst);
+  }
   if (__ballot(changed) != 0ull) {
     const float sorted = hl < Kh ? S.row[hb + hl] : 0.0f;
     const float4 r = calibrate_row_half(sorted, Kh, a.h, live ? a.rec[i].x : 0.0f, changed);
@@ -1507,8 +1594,11 @@ struct InitLaunch {
 template <typename TX, int VEC, int CH>
 struct RefineLaunch {
   static hipError_t run(const StepArgs& a, hipStream_t s) {
-    if (CH == 1 && a.Kh <= 32 && a.Kl <= 32)
-      hipLaunchKernelGGL((k_hd_refine2<TX, VEC>), dim3(wave_blocks((a.N + 1) / 2)),
+    if (CH == 1 && a.Kh <= 32 && a.Kl <= 32 && a.memo_w == 64)
+      hipLaunchKernelGGL((k_hd_refine2<TX, VEC, false, 64>), dim3(wave_blocks((a.N + 1) / 2)),
+                         dim3(kBlock), 0, s, a);
+    else if (CH == 1 && a.Kh <= 32 && a.Kl <= 32)
+      hipLaunchKernelGGL((k_hd_refine2<TX, VEC, false, 32>), dim3(wave_blocks((a.N + 1) / 2)),
                          dim3(kBlock), 0, s, a);
     else
       hipLaunchKernelGGL((k_hd_refine<TX, VEC, CH, false>), dim3(wave_blocks(a.N)),
@@ -1522,7 +1612,7 @@ hipError_t launch_hd_refine_bf16(const StepArgs& a, hipStream_t s) {
   if (a.xdtype != 1 || a.D % 16 != 0 || !a.xvec_ok) return hipErrorInvalidValue;
   const int chunks = (a.D / 8 + 63) / 64;
   if (chunks <= 1 && a.Kh <= 32 && a.Kl <= 32)
-    hipLaunchKernelGGL((k_hd_refine2<uint16_t, 8, true>), dim3(wave_blocks((a.N + 1) / 2)),
+    hipLaunchKernelGGL((k_hd_refine2<uint16_t, 8, true, 32>), dim3(wave_blocks((a.N + 1) / 2)),
                        dim3(kBlock), 0, s, a);
   else if (chunks <= 1)
     hipLaunchKernelGGL((k_hd_refine<uint16_t, 8, 1, true>), dim3(wave_blocks(a.N)), dim3(kBlock),
