@@ -373,6 +373,63 @@ def image_run(F, args):
     return out
 
 
+def memo_run(F, args):
+    """The memory of rejected HD candidates off and on: with every iteration
+    refining and the standard schedule, the HD kernel's time and the candidate
+    rows read per point, averaged over the 10 iterations ending at iterations
+    35, 120 and 320, for the 1M manifold (FP32, 512-byte rows), the 70k
+    image-like (FP32, 3136-byte rows, alpha 1) and the 4M Zipf (BF16, 512-byte
+    rows, K_hd = 64) workloads.  Both settings give the same lists and
+    embedding bit for bit; only the rows read and the time differ."""
+    import numpy as np
+
+    from inputs.generators import RUN_SEED, f32_to_bf16_bits, make_workload, y_init
+
+    out = {"metric": "HD kernel ms and candidate rows per point, memory of rejections off/on",
+           "workloads": {}}
+    for name in ("manifold_1m", "image_70k", "zipf_4m"):
+        X, _, cfg = make_workload(name)
+        if name == "zipf_4m":
+            X = f32_to_bf16_bits(X)
+        alpha = 1.0 if isinstance(cfg["alpha"], (list, tuple)) else cfg["alpha"]
+        N = X.shape[0]
+        Y0 = y_init(N, cfg["d"])
+        base = dict(alpha=alpha, perplexity=cfg["perplexity"],
+                    lr=N / (48.0 if cfg["d"] == 2 else 12.0), n_neg=cfg["n_neg"], hd_mode=1)
+        res = {}
+        for memo in (0, 1):
+            def hp(t):
+                return F.fsne_default_hparams(**{**schedule(F, base, t).as_dict(),
+                                                 "reject_memo": memo})
+            emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp(0))
+            t, pts = 0, []
+            for stop in (25, 110, 310):
+                if t < 250 <= stop:
+                    emb.step(250 - t)
+                    t = 250
+                    emb.set_hyperparams(hp(250))
+                emb.step(stop - t)
+                t = stop
+                emb.profile(True)
+                rows = []
+                for _ in range(10):
+                    emb.step(1)
+                    rows.append(emb.stats()["hd_cand_rows"] / N)
+                t += 10
+                kt = emb.kernel_times()
+                emb.profile(False)
+                ms, n = kt["hd_refine"]
+                pts.append({"iteration": t, "hd_refine_ms": round(ms / max(n, 1), 4),
+                            "rows_per_point": round(float(np.mean(rows)), 2)})
+            emb.close()
+            res["on" if memo else "off"] = pts
+        out["workloads"][name] = {"N": int(N), "D": int(X.shape[1]),
+                                  "dtype": "bf16" if X.dtype == np.uint16 else "f32",
+                                  "K_hd": cfg["K_hd"], **res}
+        del X
+    return out
+
+
 def scaling_run(F, args):
     """Time per iteration across dataset sizes at a fixed input dimensionality
     of 32 (the setting of the paper's timing figure, Sec. 4): manifold rows
@@ -639,6 +696,8 @@ def main():
                     default=[10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000])
     ap.add_argument("--large", action="store_true",
                     help="run the 4M-point BF16 workload instead")
+    ap.add_argument("--memo-compare", action="store_true",
+                    help="HD kernel with the memory of rejected candidates off and on instead")
     ap.add_argument("--gather-table", action="store_true",
                     help="print the random-gather ceiling for several row sizes instead")
     ap.add_argument("--fb-n", type=int, default=50000)
@@ -694,6 +753,9 @@ def main():
         return
     if args.scaling:
         print(json.dumps(scaling_run(F, args)))
+        return
+    if args.memo_compare:
+        print(json.dumps(memo_run(F, args)))
         return
     if args.image:
         print(json.dumps(image_run(F, args)))
