@@ -11,7 +11,7 @@ lists, a change of the BF16 screen), while fewer candidate rows are read.
 import numpy as np
 import pytest
 
-from inputs.generators import f32_to_bf16_bits, manifolds, y_init, zipf_mixture
+from inputs.generators import f32_to_bf16_bits, image_like, manifolds, y_init, zipf_mixture
 
 pytestmark = [pytest.mark.gpu]
 
@@ -31,6 +31,12 @@ CASES = {
     # two points per wave, BF16 rows, matrix-core screen
     "manifold_3000_bf16_screen": (lambda: f32_to_bf16_bits(
         manifolds(per_manifold=62, seed=1007)[0]), 16, 32, 32, 1),
+    # one point per wave over four row chunks, FP32 rows of 3136 bytes (64 remembered)
+    "image_3000_f32_d784": (lambda: image_like(n_per_class=310, seed=1011)[0], 2, 32, 32, 0),
+    # one point per wave over four row chunks with the matrix-core screen, K_hd = 64
+    # (BF16 rows of 2048 bytes: 32 remembered under the screen, 64 after the switch)
+    "zipf_3000_bf16_d1024_screen_k64": (lambda: f32_to_bf16_bits(
+        zipf_mixture(N=3100, D=1024, n_clusters=25, seed=1013)[0]), 16, 64, 32, 1),
 }
 
 
