@@ -211,6 +211,62 @@ def feedback_run(F, args):
     return out
 
 
+def blobs_knn_run(F, args):
+    """Quality of the HD lists on two engineered blob sets (the comparison of
+    neighbour finding in Sec. 4.1, without its NN-descent side): 'overlapping',
+    5 Gaussian blobs whose centres lie close together against their spread,
+    and 'disjointed', 1000 blobs of 30 points far apart against their spread.
+    N = 30,000, D = 50, d = 2, K_hd = K_ld = 32, 16 negatives, alpha = 1,
+    perplexity 10, the standard schedule, the HD refinement by the coin.
+    R_NX(K), K = 1 .. 32, of the HD lists against the exact neighbours of
+    3,000 query points: its mean and its spread (standard deviation) across
+    the points, at iterations 3000 and 9000."""
+    import numpy as np
+
+    from inputs.generators import RUN_SEED, blobs, y_init
+    from inputs.knn_metrics import exact_knn, rnx_auc, rnx_points
+
+    sets = {"overlapping": dict(n_clusters=5, per_cluster=6000, mean_var=0.25, seed=1021),
+            "disjointed": dict(n_clusters=1000, per_cluster=30, mean_var=100.0, seed=1023)}
+    out = {"metric": "HD-list R_NX(K), mean and spread across points, at 3000 and 9000 iterations",
+           "config": {"workload": "Gaussian blobs, N=30,000, D=50 FP32 (overlapping: 5 blobs, "
+                                  "centres N(0, 0.25 I); disjointed: 1000 blobs of 30, centres "
+                                  "N(0, 100 I); unit spread in both), d=2, K_hd=K_ld=32, "
+                                  "16 negatives, alpha=1, perplexity 10, HD refinement by the coin",
+                      "queries": 3000},
+           "sets": {}}
+    for name, kw in sets.items():
+        X, _ = blobs(D=50, **kw)
+        N = X.shape[0]
+        rng = np.random.default_rng(13)
+        q = np.sort(rng.choice(N, 3000, replace=False))
+        ex, _ = exact_knn(X, q, 32)
+        base = dict(alpha=1.0, perplexity=10.0, lr=N / 12.0, n_neg=16, hd_mode=0)
+        emb = F.Embedding(X, y_init(N, 2), 2, 32, 32, seed=RUN_SEED, hp=schedule(F, base, 0))
+        res, done, secs = {}, 0, 0.0
+        for stop in (250, 3000, 9000):
+            emb.sync()
+            t0 = time.perf_counter()
+            emb.step(stop - done)
+            emb.sync()
+            secs += time.perf_counter() - t0
+            done = stop
+            if stop == 250:
+                emb.set_hyperparams(schedule(F, base, 250))
+                continue
+            idx, _ = emb.knn(0)
+            pts = rnx_points(idx[q], ex, N)
+            mean = pts.mean(axis=0)
+            res[str(stop)] = {"seconds": round(secs, 3),
+                              "hd_refinements": int(emb.stats()["hd_refinements"]),
+                              "rnx_auc": round(rnx_auc(mean), 4),
+                              "rnx_mean": [round(float(v), 4) for v in mean],
+                              "rnx_std": [round(float(v), 4) for v in pts.std(axis=0)]}
+        emb.close()
+        out["sets"][name] = res
+    return out
+
+
 def hierarchy_run(F, args):
     """The hierarchy graph of Sec. 4.2 on a two-level Gaussian mixture (4 top
     clusters of 4 sub-clusters, 1000 points each, D = 50) embedded in d = 4:
@@ -696,6 +752,8 @@ def main():
                     default=[10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000])
     ap.add_argument("--large", action="store_true",
                     help="run the 4M-point BF16 workload instead")
+    ap.add_argument("--blobs-knn", action="store_true",
+                    help="HD-list R_NX(K) on overlapping and disjointed blobs instead")
     ap.add_argument("--memo-compare", action="store_true",
                     help="HD kernel with the memory of rejected candidates off and on instead")
     ap.add_argument("--gather-table", action="store_true",
@@ -753,6 +811,9 @@ def main():
         return
     if args.scaling:
         print(json.dumps(scaling_run(F, args)))
+        return
+    if args.blobs_knn:
+        print(json.dumps(blobs_knn_run(F, args)))
         return
     if args.memo_compare:
         print(json.dumps(memo_run(F, args)))

@@ -116,6 +116,25 @@ def rnx_curve(est, exact, N):
     return ((N - 1) * Q - K) / (N - 1 - K)
 
 
+def rnx_points(est, exact, N):
+    """Per-row R_NX(K), K = 1 .. Kmax: row r's |est_K ∩ exact_K| / K rescaled
+    as in rnx_curve (whose value is the mean of these rows).  Returns an
+    (n, Kmax) array."""
+    est = np.asarray(est, dtype=np.int64)
+    exact = np.asarray(exact, dtype=np.int64)
+    n, Kmax = exact.shape
+    hits = np.zeros((n, Kmax + 1), dtype=np.float64)
+    for r in range(n):
+        pos = {int(j): k for k, j in enumerate(exact[r])}
+        for k, j in enumerate(est[r][:Kmax]):
+            q = pos.get(int(j))
+            if q is not None:
+                hits[r, max(k, q) + 1] += 1.0
+    shared = np.cumsum(hits, axis=1)[:, 1:]
+    K = np.arange(1, Kmax + 1, dtype=np.float64)
+    return ((N - 1) * shared / K - K) / (N - 1 - K)
+
+
 def rnx_auc(curve):
     """Area under R_NX(K) on a log scale of K: sum R(K)/K over sum 1/K."""
     K = np.arange(1, len(curve) + 1, dtype=np.float64)
