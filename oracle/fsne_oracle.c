@@ -124,6 +124,36 @@ double fsneo_hd_dist2(const void *X, int32_t xdtype, int32_t D, int64_t a, int64
     return s;
 }
 
+/* HD distance of either metric (the paper names the HD metric as a setting  */
+/* that can change during optimisation, Sec. 3).  metric 0: the squared      */
+/* Euclidean distance.  metric 1 (angular): the squared Euclidean distance   */
+/* between the rows scaled to unit length, sum_k (x_k/|x| - y_k/|y|)^2,      */
+/* which is 2 (1 - cos) of the angle between them; a zero row stays zero.    */
+/* The affinities of eq. (1) take this value in place of delta^2.            */
+double fsneo_hd_dist2_metric(const void *X, int32_t xdtype, int32_t D, int32_t metric,
+                             int64_t a, int64_t b)
+{
+    if (metric == 0) return fsneo_hd_dist2(X, xdtype, D, a, b);
+    double na = 0.0, nb = 0.0;
+    for (int32_t k = 0; k < D; ++k) {
+        double u = xval(X, xdtype, a * D + k), v = xval(X, xdtype, b * D + k);
+        na += u * u;
+        nb += v * v;
+    }
+    double sa = na > 0.0 ? 1.0 / sqrt(na) : 0.0, sb = nb > 0.0 ? 1.0 / sqrt(nb) : 0.0;
+    double s = 0.0;
+    for (int32_t k = 0; k < D; ++k) {
+        double v = xval(X, xdtype, a * D + k) * sa - xval(X, xdtype, b * D + k) * sb;
+        s += v * v;
+    }
+    return s;
+}
+
+static double state_dist2(const fsneo_state *S, int64_t a, int64_t b)
+{
+    return fsneo_hd_dist2_metric(S->X, S->xdtype, S->D, S->metric, a, b);
+}
+
 /* LD squared distance used to decide LD list membership.  The decision is  */
 /* taken in single precision on the single-precision coordinates: the       */
 /* squares (y_jc - y_ic)^2, each rounded, are summed pairwise, leaves in     */
@@ -400,7 +430,7 @@ void fsneo_hd_refine_point(const fsneo_state *S, int64_t i, uint32_t t, int32_t 
         e[k].idx = S->hd_idx[i * K + k];
     }
     for (int c = 0; c < nc; ++c) {
-        e[K + c].key = fsneo_hd_dist2(S->X, S->xdtype, S->D, i, cand[c]);
+        e[K + c].key = state_dist2(S, i, cand[c]);
         e[K + c].idx = cand[c];
     }
     sort_entries(e, K + nc);
@@ -530,7 +560,7 @@ static void init_point_lists(fsneo_state *S, int64_t i, int64_t N)
     entry e[64];
     for (int32_t k = 0; k < K; ++k) {
         e[k].idx = S->hd_idx[i * K + k];
-        e[k].key = fsneo_hd_dist2(S->X, S->xdtype, S->D, i, e[k].idx);
+        e[k].key = state_dist2(S, i, e[k].idx);
     }
     sort_entries(e, K);
     for (int32_t k = 0; k < K; ++k) {
@@ -777,7 +807,7 @@ int fsneo_drift(fsneo_state *S, const fsneo_hp *hp, const int64_t *ids, int64_t 
             int64_t j = S->hd_idx[i * K + k];
             e[k].idx = j;
             if (moved[i] || moved[j]) {
-                e[k].key = fsneo_hd_dist2(S->X, S->xdtype, S->D, i, j);
+                e[k].key = state_dist2(S, i, j);
                 touched = 1;
             } else {
                 e[k].key = S->hd_d2[i * K + k];
@@ -794,6 +824,40 @@ int fsneo_drift(fsneo_state *S, const fsneo_hp *hp, const int64_t *ids, int64_t 
     }
     all_psym(S);
     free(moved);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Change of the HD metric during optimisation (Sec. 3: the scheme adapts   */
+/* to changes of HD-side settings such as the metric).  The lists keep      */
+/* their members; every stored distance is recomputed in the new metric,    */
+/* each row is re-sorted by (d2, id), flagged and recalibrated, P is        */
+/* recomputed, and E restarts at 1: the lists are not yet the new metric's  */
+/* neighbours, so the coin refines at once, as at the start.                */
+/* ------------------------------------------------------------------------ */
+int fsneo_set_metric(fsneo_state *S, const fsneo_hp *hp, int32_t metric)
+{
+    if (metric < 0 || metric > 1) return -1;
+    S->metric = metric;
+    const int64_t N = S->N;
+    const int32_t K = S->K_hd;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < N; ++i) {
+        entry e[64];
+        for (int32_t k = 0; k < K; ++k) {
+            e[k].idx = S->hd_idx[i * K + k];
+            e[k].key = state_dist2(S, i, e[k].idx);
+        }
+        sort_entries(e, K);
+        for (int32_t k = 0; k < K; ++k) {
+            S->hd_idx[i * K + k] = (int32_t)e[k].idx;
+            S->hd_d2[i * K + k] = e[k].key;
+        }
+        S->flags[i] = 1;
+        calibrate_point(S, i, hp->perplexity);
+    }
+    all_psym(S);
+    *S->E = 1.0f;
     return 0;
 }
 
@@ -843,7 +907,7 @@ void fsneo_delete_fix(fsneo_state *S, const fsneo_hp *hp, const int32_t *newid)
         random_list(i, N, Kh, FSNEO_S_DEL_HD, t, S->seed, ids, nk);
         for (int32_t k = nk; k < Kh; ++k) {
             e[k].idx = ids[k];
-            e[k].key = fsneo_hd_dist2(S->X, S->xdtype, S->D, i, ids[k]);
+            e[k].key = state_dist2(S, i, ids[k]);
         }
         sort_entries(e, Kh);
         for (int32_t k = 0; k < Kh; ++k) {

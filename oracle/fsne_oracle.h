@@ -49,6 +49,8 @@ typedef struct {
     uint8_t *flags;     /* N: 1 if the last HD refinement changed row i        */
     float *E;           /* smoothed fraction of points that gained neighbours  */
     uint32_t *t;        /* iteration counter                                   */
+    int32_t metric;     /* HD distance: 0 squared Euclidean, 1 angular (the    */
+                        /* squared Euclidean distance of the unit rows)        */
 } fsneo_state;
 
 typedef struct {
@@ -72,6 +74,9 @@ int fsneo_coin(float E, uint32_t t, uint64_t seed, int32_t hd_mode, float p_min)
 float fsneo_E_next(float E, int64_t n_new, int64_t N, float lam);
 int fsneo_calibrate(const double *d2, int32_t K, double perplexity, double out[4]);
 double fsneo_hd_dist2(const void *X, int32_t xdtype, int32_t D, int64_t a, int64_t b);
+double fsneo_hd_dist2_metric(const void *X, int32_t xdtype, int32_t D, int32_t metric,
+                             int64_t a, int64_t b);
+int fsneo_set_metric(fsneo_state *S, const fsneo_hp *hp, int32_t metric);
 int fsneo_init(fsneo_state *S, const fsneo_hp *hp);
 int fsneo_step(fsneo_state *S, const fsneo_hp *hp, fsneo_stats *st,
                double *A, double *R, double *Zh);

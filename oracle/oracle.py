@@ -40,7 +40,7 @@ class _State(C.Structure):
                 ("hd_idx", C.c_void_p), ("hd_d2", C.c_void_p), ("ld_idx", C.c_void_p),
                 ("beta", C.c_void_p), ("m", C.c_void_p), ("r", C.c_void_p),
                 ("invS", C.c_void_p), ("P", C.c_void_p), ("flags", C.c_void_p),
-                ("E", C.c_void_p), ("t", C.c_void_p)]
+                ("E", C.c_void_p), ("t", C.c_void_p), ("metric", C.c_int32)]
 
 
 class _Hp(C.Structure):
@@ -78,6 +78,11 @@ def lib():
         L.fsneo_calibrate.restype = C.c_int
         L.fsneo_hd_dist2.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64]
         L.fsneo_hd_dist2.restype = C.c_double
+        L.fsneo_hd_dist2_metric.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
+                                            C.c_int64]
+        L.fsneo_hd_dist2_metric.restype = C.c_double
+        L.fsneo_set_metric.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int32]
+        L.fsneo_set_metric.restype = C.c_int
         L.fsneo_init.argtypes = [C.POINTER(_State), C.POINTER(_Hp)]
         L.fsneo_init.restype = C.c_int
         L.fsneo_step.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.POINTER(_Stats), P, P, P]
@@ -161,7 +166,7 @@ def _xprep(X):
 class OracleState:
     """The oracle's full iteration state (double precision)."""
 
-    def __init__(self, X, d, K_hd, K_ld, seed, Y0, capacity=None):
+    def __init__(self, X, d, K_hd, K_ld, seed, Y0, capacity=None, metric=0):
         self.X, self.xdtype = _xprep(X)
         N, D = self.X.shape
         cap = N if capacity is None else capacity
@@ -185,6 +190,7 @@ class OracleState:
         self.flags = np.zeros(cap, dtype=np.uint8)
         self.E = np.ones(1, dtype=np.float32)
         self.t = np.zeros(1, dtype=np.uint32)
+        self.metric = int(metric)   # HD distance: 0 squared Euclidean, 1 angular
 
     def cstate(self) -> _State:
         return _State(self.N, self.D, self.d, self.K_hd, self.K_ld, self.xdtype, self.seed,
@@ -192,7 +198,7 @@ class OracleState:
                       self.hd_idx.ctypes.data, self.hd_d2.ctypes.data, self.ld_idx.ctypes.data,
                       self.beta.ctypes.data, self.m.ctypes.data, self.r.ctypes.data,
                       self.invS.ctypes.data, self.P.ctypes.data, self.flags.ctypes.data,
-                      self.E.ctypes.data, self.t.ctypes.data)
+                      self.E.ctypes.data, self.t.ctypes.data, self.metric)
 
     # -- the method ---------------------------------------------------------
     def init(self, hp: Hyper):
@@ -291,6 +297,14 @@ class OracleState:
         lib().fsneo_drift(C.byref(s), C.byref(hp.c()), _p(ids), ids.size,
                           None if Yn is None else _p(Yn))
 
+    def set_metric(self, hp: Hyper, metric):
+        """Switch the HD metric: every stored distance recomputed, rows
+        re-sorted, flagged and recalibrated, P recomputed, E back to 1."""
+        s = self.cstate()
+        if lib().fsneo_set_metric(C.byref(s), C.byref(hp.c()), int(metric)) != 0:
+            raise ValueError("metric must be 0 or 1")
+        self.metric = int(metric)
+
     def delete(self, hp: Hyper, ids):
         """Remove points: survivors at or beyond the new N move, in increasing
         order, into the freed ids below it, in increasing order; then the
@@ -372,9 +386,11 @@ def calibrate(d2, perplexity):
     return out, bool(noroot)
 
 
-def hd_dist2(X, a, b):
+def hd_dist2(X, a, b, metric=0):
     X, xdt = _xprep(X)
-    return lib().fsneo_hd_dist2(_p(X), xdt, X.shape[1], int(a), int(b))
+    if metric == 0:
+        return lib().fsneo_hd_dist2(_p(X), xdt, X.shape[1], int(a), int(b))
+    return lib().fsneo_hd_dist2_metric(_p(X), xdt, X.shape[1], int(metric), int(a), int(b))
 
 
 def exact_P(X, perplexity):

@@ -552,3 +552,114 @@ def test_cluster_equals_dbscan_on_exact_lists(oracle_lib):
     # clusters are numbered by the smallest index among their core points
     firsts = [np.nonzero((labels == k) & core)[0].min() for k in range(nc)]
     assert firsts == sorted(firsts)
+
+
+# --- HD metric (Sec. 3: HD-side settings such as the metric may change) ----
+def _rescaled_blobs(n_clusters, per_cluster, D, seed):
+    """Blobs with every row scaled by a power of two (exact in FP32): the
+    angular neighbours are the blobs', the Euclidean ones are not."""
+    X, lab = blobs(n_clusters=n_clusters, per_cluster=per_cluster, D=D, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    X = (X * np.exp2(rng.integers(-3, 4, size=(X.shape[0], 1)))).astype(np.float32)
+    return X, lab
+
+
+def test_angular_metric_closed_forms_and_scipy(oracle_lib):
+    """Angular delta^2 = |x/|x| - y/|y||^2 = 2 (1 - cos): right angles,
+    parallel and opposite rows, 60 degrees, the zero row, SciPy's cosine
+    distance (FP32 and BF16 rows), invariance to positive row scales."""
+    from scipy.spatial.distance import cosine
+
+    from inputs.generators import bf16_bits_to_f32, f32_to_bf16_bits
+    O = oracle_lib
+    e = np.eye(4, dtype=np.float32)
+    X = np.stack([e[0], e[1], 3 * e[0], -2 * e[0], np.zeros(4, np.float32),
+                  np.array([0.5, np.sqrt(0.75), 0, 0], np.float32)])
+
+    def dm(a, b, Z=X):
+        return O.hd_dist2(Z, a, b, metric=1)
+    assert abs(dm(0, 1) - 2.0) < 1e-15
+    assert abs(dm(0, 2)) < 1e-15
+    assert abs(dm(0, 3) - 4.0) < 1e-15
+    assert abs(dm(0, 4) - 1.0) < 1e-15 and dm(4, 4) == 0.0
+    assert abs(dm(0, 5) - 1.0) < 1e-7
+    assert O.hd_dist2(X, 0, 2) == 4.0           # metric 0 is still Euclidean
+    rng = np.random.default_rng(5)
+    R = rng.normal(size=(30, 17)).astype(np.float32)
+    B = f32_to_bf16_bits(R)
+    Rb = bf16_bits_to_f32(B).astype(np.float64)
+    for a, b in [(0, 1), (2, 9), (17, 4), (29, 28)]:
+        want = 2.0 * cosine(R[a].astype(np.float64), R[b].astype(np.float64))
+        assert abs(dm(a, b, R) - want) < 1e-12
+        assert abs(dm(a, b, B) - 2.0 * cosine(Rb[a], Rb[b])) < 1e-12
+    Rs = (R * np.exp2(rng.integers(-6, 7, size=(30, 1)))).astype(np.float32)
+    for a, b in [(0, 1), (5, 6), (11, 20)]:
+        assert abs(dm(a, b, Rs) - dm(a, b, R)) < 1e-14
+
+
+def test_angular_refinement_converges_to_exact_angular_knn(oracle_lib):
+    """With metric 1 from the start, the interleaved refinement finds the
+    exact K-NN sets of the angular distance (brute force with SciPy)."""
+    from scipy.spatial.distance import cdist
+    O = oracle_lib
+    X, _ = _rescaled_blobs(3, 40, 5, 8)
+    N, K = X.shape[0], 8
+    S = O.OracleState(X, 2, K, 6, 9, y_init(N, 2), metric=1)
+    hp = O.Hyper(alpha=1.0, perplexity=4.0, lr=N / 12, momentum=0.5, attr=4.0, n_neg=4,
+                 hd_mode=1)
+    S.init(hp)
+    for _ in range(300):
+        S.step(hp)
+    A = 2.0 * cdist(X.astype(np.float64), X.astype(np.float64), "cosine")
+    np.fill_diagonal(A, np.inf)
+    ex = np.argsort(A, axis=1, kind="stable")[:, :K]
+    np.testing.assert_array_equal(S.hd_idx[:N], ex)
+    np.testing.assert_allclose(S.hd_d2[:N], np.take_along_axis(A, ex, 1), rtol=1e-12, atol=1e-15)
+    # the Euclidean lists of the same rows differ
+    exe, _ = O.knn_exact(X, np.arange(N), K)
+    assert np.mean([len(set(a) & set(b)) for a, b in zip(ex, exe)]) < 0.8 * K
+
+
+def test_metric_switch_recomputes_every_list(oracle_lib):
+    """A switch keeps each list's members, gives every entry its distance in
+    the new metric, re-sorts by (d2, id), flags and recalibrates every row
+    (entropy ln perplexity), restarts E at 1; refinement then moves the
+    lists to the new metric's neighbours; switching back restores the
+    Euclidean distances."""
+    from scipy.spatial.distance import cdist
+    O = oracle_lib
+    X, _ = _rescaled_blobs(4, 50, 8, 12)
+    N, K, perp = X.shape[0], 12, 5.0
+    S = O.OracleState(X, 2, K, 8, 5, y_init(N, 2))
+    hp = O.Hyper(perplexity=perp, lr=N / 12, attr=4.0, n_neg=4, hd_mode=1)
+    S.init(hp)
+    for _ in range(30):
+        S.step(hp)
+    before = S.hd_idx[:N].copy()
+    S.E[0] = 0.25
+    S.flags[:N] = 0
+    S.set_metric(hp, 1)
+    X64 = X.astype(np.float64)
+    A = 2.0 * cdist(X64, X64, "cosine")
+    for i in range(N):
+        idx, d2 = S.hd_idx[i], S.hd_d2[i]
+        assert set(idx) == set(before[i])
+        np.testing.assert_allclose(d2, A[i, idx], rtol=1e-12, atol=1e-15)
+        keys = list(zip(d2, idx))
+        assert keys == sorted(keys)
+        p = np.exp(-S.beta[i] * (d2 - S.m[i]))
+        p /= p.sum()
+        H = -np.sum(p[p > 0] * np.log(p[p > 0]))
+        assert abs(H - np.log(perp)) < 1e-8
+    assert np.all(S.flags[:N] == 1) and S.E[0] == 1.0
+    assert 0.0 < S.P[:N].sum() <= 1.0 + 1e-12
+    for _ in range(150):
+        S.step(hp)
+    np.fill_diagonal(A, np.inf)
+    ex = np.argsort(A, axis=1, kind="stable")[:, :K]
+    rec = np.mean([len(set(a) & set(b)) for a, b in zip(S.hd_idx[:N], ex)]) / K
+    assert rec > 0.97, rec
+    S.set_metric(hp, 0)
+    for i in range(0, N, 5):
+        np.testing.assert_allclose(S.hd_d2[i], ((X64[S.hd_idx[i]] - X64[i]) ** 2).sum(1),
+                                   rtol=1e-12)
