@@ -32,7 +32,7 @@ C_SLOTS = 32
 
 # Sources the step's kernels and their launches are built from; the placement
 # network, clustering and jump-start files hold kernels of their own.
-STEP_SOURCES = ("fsne_api.hip", "fsne_bf16.hip", "fsne_context.h", "fsne_device.h",
+STEP_SOURCES = ("fsne_api.hip", "fsne_bf16.hip", "fsne_unit.hip", "fsne_context.h", "fsne_device.h",
                 "fsne_kernels.h", "fsne_kernels.hip")
 
 

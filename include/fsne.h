@@ -77,6 +77,14 @@ typedef struct fsne_hparams {
                            delete, a state load of the HD lists, a change of
                            dist_mode or rerank_margin); inserted points start
                            empty.                                               */
+    int32_t metric;     /* HD distance (Sec. 3 names the metric as an HD-side
+                           setting that may change during optimisation):
+                           0 squared Euclidean; 1 angular, the squared Euclidean
+                           distance between the rows scaled to unit length,
+                           2 (1 - cos); a zero row stays zero.  The affinities
+                           of eq. (1) take it in place of delta^2.  The library
+                           then keeps an FP32 copy of the unit rows (capacity x D)
+                           for the HD kernels; metric 1 needs dist_mode 0.      */
 } fsne_hparams;
 
 /* Host-side view of the iteration state for checkpoints and checks.  Every
@@ -120,7 +128,7 @@ int32_t fsne_max_dim(int32_t xdtype, int32_t D);
 
 /* Fill *hp with the defaults: alpha 1, perplexity 10, lr 100, momentum 0.5,
  * attr 1, rep 1, n_neg 16, hd_mode 0, dist_mode 0, e_smooth 0.1, p_min 0.05,
- * rerank_margin 2^-6, reject_memo 1.  Returns FSNE_EINVAL if hp is NULL. */
+ * rerank_margin 2^-6, reject_memo 1, metric 0.  Returns FSNE_EINVAL if hp is NULL. */
 fsne_status fsne_default_hparams(fsne_hparams *hp);
 
 /* Create a context and its initial state (Sec. 3: optimisation starts right
@@ -153,7 +161,12 @@ fsne_status fsne_step(fsne_ctx *ctx, int32_t n_iters);
 
 /* Replace the hyperparameters.  A perplexity change recalibrates every point
  * and recomputes the affinities before the next step (Sec. 3: HD-side
- * hyperparameters change on the fly).  Errors: FSNE_EINVAL. */
+ * hyperparameters change on the fly).  A metric change keeps every HD list's
+ * members, recomputes every stored distance in the new metric, re-sorts each
+ * list by (d2, id), flags and recalibrates every point, recomputes the
+ * affinities and sets E to 1, so that the next iterations refine the lists
+ * towards the new metric's neighbours.  Synchronises the context stream when
+ * the perplexity or the metric changes.  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_set_hyperparams(fsne_ctx *ctx, const fsne_hparams *hp);
 fsne_status fsne_get_hyperparams(const fsne_ctx *ctx, fsne_hparams *hp);
 

@@ -96,12 +96,28 @@ StepArgs make_args(const fsne_ctx* c) {
   a.cpart = c->cpart;
   a.ldc = c->ldc;
   a.memo = c->hp.reject_memo ? c->memo : nullptr;
+  // angular metric: the HD kernels take the Euclidean distances of the rows
+  // scaled to unit length
+  if (c->hp.metric == 1 && c->Xu) {
+    a.X = c->Xu;
+    a.xdtype = FSNE_F32;
+    a.xvec_ok = 1;
+  }
   // 64 remembered rejections pay where a saved row is large (direct distances
   // on rows of 512 bytes or more); elsewhere the extra 256 bytes of memory
   // traffic per point, or the screen kernel's registers, cost more than they save
-  const int64_t row_bytes = (int64_t)c->D * (c->xdtype == FSNE_F32 ? 4 : 2);
+  const int64_t row_bytes = (int64_t)c->D * (a.xdtype == FSNE_F32 ? 4 : 2);
   a.memo_w = (c->hp.dist_mode == 0 && row_bytes >= 512) ? 64 : 32;
   a.neg_scale = c->hp.n_neg > 0 ? (float)(c->N - 1) / (float)c->hp.n_neg : 0.0f;
+  return a;
+}
+
+// The same with the stored rows themselves (for the BF16 row norms).
+StepArgs raw_args(const fsne_ctx* c) {
+  StepArgs a = make_args(c);
+  a.X = c->X;
+  a.xdtype = c->xdtype;
+  a.xvec_ok = (((uintptr_t)c->X) & 15u) == 0;
   return a;
 }
 
@@ -132,6 +148,9 @@ fsne_status check_hparams(fsne_ctx* c, const fsne_hparams* hp, int32_t Kh, int32
     return fail(c, FSNE_EINVAL, "rerank_margin must be >= 0");
   if (hp->reject_memo < 0 || hp->reject_memo > 1)
     return fail(c, FSNE_EINVAL, "reject_memo must be 0 or 1");
+  if (hp->metric < 0 || hp->metric > 1) return fail(c, FSNE_EINVAL, "metric must be 0 or 1");
+  if (hp->metric == 1 && hp->dist_mode == 1)
+    return fail(c, FSNE_EINVAL, "the BF16 screen needs metric 0 (it works on the raw rows)");
   return FSNE_OK;
 }
 
@@ -215,6 +234,32 @@ fsne_status refresh_affinities(fsne_ctx* c, bool recalibrate) {
   return FSNE_OK;
 }
 
+// Under the angular metric the HD kernels read Xu, the rows of X scaled to
+// unit length: allocated on first use and recomputed for every row whenever
+// X changes while that metric is in use (and when it is switched on).
+fsne_status refresh_unit_rows(fsne_ctx* c) {
+  if (c->hp.metric != 1) return FSNE_OK;
+  if (!c->Xu) TRY(dalloc(c, &c->Xu, (size_t)c->cap * c->D));
+  HIPCHK(c, fsne::launch_unit_rows(c->X, c->xdtype, c->Xu, c->D, 0, (int32_t)c->N, c->stream));
+  return FSNE_OK;
+}
+
+// The HD metric changed (c->hp holds the new one): every list keeps its
+// members, every stored distance is recomputed in the new metric, each row is
+// re-sorted by (d2, id), flagged and recalibrated (the drift kernel with every
+// point marked), P is recomputed, and E restarts at 1 so that the coin
+// refines at once: the lists are not yet the new metric's neighbours.
+fsne_status switch_metric(fsne_ctx* c) {
+  TRY(refresh_unit_rows(c));
+  HIPCHK(c, hipMemsetAsync(c->moved, 1, (size_t)c->N, c->stream));
+  HIPCHK(c, fsne::launch_drift_rows(make_args(c), c->moved, c->stream));
+  Scalars s;
+  TRY(read_scalars(c, &s));
+  s.E = 1.0f;
+  TRY(write_scalars(c, s));
+  return refresh_affinities(c, false);
+}
+
 // Forget the rejected HD candidates of rows [r0, r0 + n).
 fsne_status clear_memo(fsne_ctx* c, int64_t r0, int64_t n) {
   if (n > 0)
@@ -278,10 +323,12 @@ fsne_status do_init(fsne_ctx* c, const void* X, int32_t x_on_device, const float
   s.E = 1.0f;
   s.hd_cur = 0;
   TRY(write_scalars(c, s));
+  TRY(refresh_unit_rows(c));
   StepArgs a = make_args(c);
   a.hd_buf_host = 0;
   a.ld_buf_host = 0;
-  if (c->xdtype == FSNE_BF16) HIPCHK(c, fsne::launch_xnorm(a, c->xnorm, 0, (int32_t)c->N, c->stream));
+  if (c->xdtype == FSNE_BF16)
+    HIPCHK(c, fsne::launch_xnorm(raw_args(c), c->xnorm, 0, (int32_t)c->N, c->stream));
   HIPCHK(c, fsne::launch_init_lists(a, 0, (int32_t)c->N, c->stream));
   TRY(refresh_affinities(c, false));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -372,6 +419,7 @@ fsne_status fsne_default_hparams(fsne_hparams* hp) {
   hp->p_min = 0.05f;
   hp->rerank_margin = 1.0f / 64.0f;
   hp->reject_memo = 1;
+  hp->metric = 0;
   return FSNE_OK;
 }
 
@@ -447,12 +495,20 @@ fsne_status fsne_set_hyperparams(fsne_ctx* c, const fsne_hparams* hp) {
   if (!c) return FSNE_EINVAL;
   TRY(check_hparams(c, hp, c->Kh, c->xdtype, c->D));
   const bool perp_changed = hp->perplexity != c->hp.perplexity;
-  // a rejection under one screen need not be one under another
+  const bool metric_changed = hp->metric != c->hp.metric;
+  // a rejection under one screen (or metric) need not be one under another
   const bool screen_changed =
       hp->dist_mode != c->hp.dist_mode || hp->rerank_margin != c->hp.rerank_margin;
+  const fsne_hparams old = c->hp;
   c->hp = *hp;
-  if (screen_changed) TRY(clear_memo(c, 0, c->cap));
-  if (perp_changed) {
+  if (screen_changed || metric_changed) TRY(clear_memo(c, 0, c->cap));
+  if (metric_changed) {
+    const fsne_status st = switch_metric(c);
+    if (st != FSNE_OK) {
+      c->hp = old;   // e.g. no memory for the unit rows: nothing was recomputed
+      return st;
+    }
+  } else if (perp_changed) {
     TRY(refresh_affinities(c, true));
   } else {
     HIPCHK(c, fsne::launch_set_fire(c->sc, make_hyper(c), c->stream));
@@ -605,11 +661,12 @@ fsne_status fsne_insert_points(fsne_ctx* c, const void* Xnew, int64_t n, const f
   HIPCHK(c, hipMemsetAsync(c->V + N0 * c->DP, 0, sizeof(float) * n * c->DP, c->stream));
   TRY(clear_memo(c, N0, n));   // rows left by deleted points
   c->N = N0 + n;
+  TRY(refresh_unit_rows(c));
   StepArgs a = make_args(c);
   a.hd_buf_host = s.hd_cur;
   a.ld_buf_host = (int32_t)(s.t & 1u);
   if (c->xdtype == FSNE_BF16)
-    HIPCHK(c, fsne::launch_xnorm(a, c->xnorm, (int32_t)N0, (int32_t)n, c->stream));
+    HIPCHK(c, fsne::launch_xnorm(raw_args(c), c->xnorm, (int32_t)N0, (int32_t)n, c->stream));
   HIPCHK(c, fsne::launch_init_lists(a, (int32_t)N0, (int32_t)n, c->stream));
   TRY(refresh_affinities(c, false));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -674,9 +731,11 @@ fsne_status fsne_drift_points(fsne_ctx* c, const int64_t* ids, const void* Xnew,
     }
     // moved rows change distances in both directions: every rejection is void
     if ((st = clear_memo(c, 0, c->cap)) != FSNE_OK) break;
+    if ((st = refresh_unit_rows(c)) != FSNE_OK) break;
     StepArgs a = make_args(c);
     if (c->xdtype == FSNE_BF16 &&
-        (e = fsne::launch_xnorm(a, c->xnorm, 0, (int32_t)c->N, c->stream)) != hipSuccess) {
+        (e = fsne::launch_xnorm(raw_args(c), c->xnorm, 0, (int32_t)c->N, c->stream)) !=
+            hipSuccess) {
       st = hip_fail(c, e, "drift norms");
       break;
     }
@@ -762,6 +821,7 @@ fsne_status fsne_delete_points(fsne_ctx* c, const int64_t* ids, int64_t n) {
     c->N = N1;
     // ids are renumbered and lists refilled at random: every rejection is void
     if ((st = clear_memo(c, 0, c->cap)) != FSNE_OK) break;
+    if ((st = refresh_unit_rows(c)) != FSNE_OK) break;
     StepArgs a = make_args(c);
     if ((e = fsne::launch_delete_fix(a, dnew, c->stream)) != hipSuccess) {
       st = hip_fail(c, e, "delete lists");

@@ -31,6 +31,7 @@ struct fsne_ctx {
   uint8_t* flags = nullptr;
   uint8_t* moved = nullptr;
   int32_t* memo = nullptr;   // cap x kMemo rejected HD candidates, -1 = empty
+  float* Xu = nullptr;       // cap x D rows scaled to unit length (angular metric)
   fsne::Scalars* sc = nullptr;
   std::string err;
   std::vector<void*> owned;

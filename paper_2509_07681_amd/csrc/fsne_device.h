@@ -150,6 +150,12 @@ __device__ __forceinline__ float group_sum_dpp(float v, int g) {
   return v;
 }
 
+// A stored element as FP32 (BF16 bit patterns widened exactly).
+__device__ __forceinline__ float to_unit_f32(float v) { return v; }
+__device__ __forceinline__ float to_unit_f32(uint16_t v) {
+  return __uint_as_float(((uint32_t)v) << 16);
+}
+
 // Wave sum, the same value in every lane (taken from lane 63 with readlane,
 // so it is wave-uniform: control flow that depends on it cannot diverge and
 // no lane drops out of a later cross-lane operation).

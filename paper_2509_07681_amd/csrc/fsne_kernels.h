@@ -57,6 +57,9 @@ hipError_t launch_delete_fix(const StepArgs& a, const int32_t* newid, hipStream_
 hipError_t launch_move_rows(void* base, const int32_t* src, const int32_t* dst, int32_t m,
                             int32_t row_bytes, hipStream_t s);
 hipError_t launch_xnorm(const StepArgs& a, float* xnorm, int32_t i0, int32_t n, hipStream_t s);
+// Xu rows [i0, i0 + n) = X rows scaled to unit length (FP32), for the angular metric.
+hipError_t launch_unit_rows(const void* X, int32_t xdtype, float* Xu, int32_t D, int32_t i0,
+                            int32_t n, hipStream_t s);
 hipError_t launch_scatter_rows(void* dst, const void* src, const int32_t* ids, int32_t n,
                                int32_t row_bytes, hipStream_t s);
 hipError_t launch_mark_moved(uint8_t* moved, float* V, int32_t DP, const int32_t* ids, int32_t n,

@@ -29,7 +29,7 @@ class fsne_hparams(C.Structure):
                 ("momentum", C.c_float), ("attr", C.c_float), ("rep", C.c_float),
                 ("n_neg", C.c_int32), ("hd_mode", C.c_int32), ("dist_mode", C.c_int32),
                 ("e_smooth", C.c_float), ("p_min", C.c_float), ("rerank_margin", C.c_float),
-                ("reject_memo", C.c_int32)]
+                ("reject_memo", C.c_int32), ("metric", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

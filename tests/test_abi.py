@@ -39,7 +39,7 @@ def test_defaults_and_argument_checks(fsne_lib):
     F = fsne_lib
     hp = F.fsne_default_hparams()
     assert hp.alpha == 1.0 and hp.p_min == np.float32(0.05) and hp.hd_mode == 0
-    assert hp.reject_memo == 1
+    assert hp.reject_memo == 1 and hp.metric == 0
     L = F.load_library()
     assert L.fsne_default_hparams(None) == F.FSNE_EINVAL
     X = np.zeros((100, 8), np.float32)
@@ -70,7 +70,7 @@ def test_defaults_and_argument_checks(fsne_lib):
     for bad in (dict(alpha=0.0), dict(alpha=-1.0), dict(perplexity=16.0), dict(perplexity=1.0),
                 dict(momentum=1.0), dict(n_neg=65), dict(hd_mode=3), dict(dist_mode=1),
                 dict(e_smooth=0.0), dict(lr=float("nan")), dict(reject_memo=2),
-                dict(reject_memo=-1)):
+                dict(reject_memo=-1), dict(metric=2), dict(metric=-1)):
         h = F.fsne_default_hparams(**bad)
         assert init(hp=C.byref(h)) == F.FSNE_EINVAL, bad
     assert not ctx.value

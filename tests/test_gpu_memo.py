@@ -6,7 +6,8 @@ the candidates), so a candidate that lost a merge would lose every later one.
 The library skips such candidates (hparams.reject_memo = 1).  With the memory
 on and off every state array must agree bit for bit, through insertion and
 through the events that void the memory (drift, delete, a state load of the
-lists, a change of the BF16 screen), while fewer candidate rows are read.
+lists, a change of the BF16 screen or of the HD metric), while fewer
+candidate rows are read.
 """
 import numpy as np
 import pytest
@@ -97,6 +98,16 @@ def test_memo_changes_no_result(fsne_lib, case):
             **{**e.hyperparams().as_dict(), "dist_mode": 1 - dist_mode})))
         both(lambda e: e.step(10))
         _same(on, off, "screen switch")
+    if on.hyperparams().dist_mode == 0:
+        # the angular metric: a switch clears the memory; drift recomputes the unit rows
+        both(lambda e: e.set_hyperparams(F.fsne_default_hparams(
+            **{**e.hyperparams().as_dict(), "metric": 1})))
+        both(lambda e: e.step(15))
+        _same(on, off, "angular metric")
+        ids2 = np.arange(1, 60, 3, dtype=np.int64)
+        both(lambda e: e.drift(ids2, X_all[ids2 + 700]))
+        both(lambda e: e.step(10))
+        _same(on, off, "angular drift")
     both(lambda e: e.set_hyperparams(F.fsne_default_hparams(
         **{**e.hyperparams().as_dict(), "hd_mode": 0, "attr": 1.0, "momentum": 0.8})))
     both(lambda e: e.step(30))
