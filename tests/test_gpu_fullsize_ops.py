@@ -1,6 +1,7 @@
 """Full-size checks of the online and hierarchy entry points at 10^6 points
 (the benchmark's workload size): jump start, deletion and clustering give
-the oracle's results on the same seeded inputs."""
+the oracle's results on the same seeded inputs; the memory of rejected HD
+candidates changes no result at this size."""
 import numpy as np
 import pytest
 
@@ -35,6 +36,32 @@ def test_fullsize_jump_start(oracle_lib, fsne_lib, manifold):
     assert rel_l2(g["Y"], S.live("Y")) < 1e-5
     assert np.all(g["V"] == 0.0)
     emb.close()
+
+
+def test_fullsize_memo_changes_no_result(fsne_lib, manifold):
+    """At the benchmark's size and launch configuration (10^6 FP32 rows, two
+    points per wave, 64 remembered rejections): 30 refining iterations with
+    the memory of rejected candidates on and off give the same state bit for
+    bit, and the memory reads fewer candidate rows."""
+    F = fsne_lib
+    X, cfg = manifold
+    N, d = X.shape[0], cfg["d"]
+    fields = ["hd_idx", "hd_d2", "ld_idx", "Y", "P", "rec"]
+    out = {}
+    for memo in (1, 0):
+        hp = F.fsne_default_hparams(alpha=1.0, perplexity=10.0, lr=N / 12.0, momentum=0.5,
+                                    attr=12.0, n_neg=cfg["n_neg"], hd_mode=1, reject_memo=memo)
+        emb = F.Embedding(X, y_init(N, d), d, cfg["K_hd"], cfg["K_ld"], seed=42, hp=hp)
+        emb.step(30)
+        st = emb.stats()
+        assert st["nonfinite"] == 0
+        g = emb.state(fields)
+        out[memo] = ({k: g[k].copy() for k in fields}, st["hd_cand_rows"], st["E"])
+        emb.close()
+    for k in fields:
+        assert np.array_equal(out[1][0][k], out[0][0][k]), k
+    assert out[1][2] == out[0][2]
+    assert out[1][1] < out[0][1], (out[1][1], out[0][1])
 
 
 def test_fullsize_delete(oracle_lib, fsne_lib, manifold):
