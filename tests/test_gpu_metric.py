@@ -190,3 +190,56 @@ def test_angular_rejects_the_screen(fsne_lib):
         emb.set_hyperparams(F.fsne_default_hparams(dist_mode=1, metric=1, perplexity=5.0))
     assert emb.hyperparams().metric == 0
     emb.close()
+
+
+def test_angular_insert_drift_delete_match_oracle(oracle_lib, fsne_lib):
+    """Online use under the angular metric: inserted rows get lists sorted by
+    the angular distance, drifted rows have their unit rows and every
+    distance involving them recomputed, deleted rows' refills get angular
+    distances; each time the GPU state matches the oracle's."""
+    O, F = oracle_lib, fsne_lib
+    X_all = _rescale(manifolds(per_manifold=44, seed=1003)[0], 7)      # 2,200 rows
+    N0, n_ins = 2000, 200
+    base = dict(alpha=1.0, perplexity=10.0, lr=N0 / 12.0, momentum=0.5, attr=12.0, rep=1.0,
+                n_neg=8, hd_mode=1, e_smooth=0.1, p_min=0.05)
+    hp_o = O.Hyper(**{k: (float(np.float32(v)) if isinstance(v, float) else v)
+                      for k, v in base.items()})
+    hp_g = F.fsne_default_hparams(**base, metric=1)
+    Y0 = y_init(N0, 2)
+    S = O.OracleState(X_all[:N0], 2, 32, 16, 42, Y0, capacity=N0 + n_ins, metric=1).init(hp_o)
+    emb = F.Embedding(X_all[:N0], Y0, 2, 32, 16, seed=42, hp=hp_g, capacity=N0 + n_ins)
+    for _ in range(3):
+        S.step(hp_o)
+    D = X_all.shape[1]
+
+    def check():
+        g = emb.state()
+        Xu = _unit(S.X[:S.N])
+        same = _check_lists(Xu, D, g["hd_idx"], g["hd_d2"], S.live("hd_idx"), S.live("hd_d2"),
+                            max(3, S.N // 200))
+        clean = _clean(S, same)
+        assert clean.mean() > 0.8
+        assert rel_l2(g["P"][clean], S.live("P")[clean]) < 1e-3
+        return g, same
+
+    emb.set_state(S.as_gpu_state())
+    Yn = np.random.default_rng(1).normal(size=(n_ins, 2)).astype(np.float32)
+    S.insert(hp_o, X_all[N0:], Yn)
+    emb.insert(X_all[N0:], Yn)
+    g, _ = check()
+    np.testing.assert_array_equal(g["ld_idx"][N0:], S.live("ld_idx")[N0:])
+    rng = np.random.default_rng(2)
+    ids = rng.choice(N0 + n_ins, 40, replace=False)
+    Xn = _rescale((X_all[ids] + rng.normal(scale=0.3, size=X_all[ids].shape)).astype(np.float32), 3)
+    emb.set_state(S.as_gpu_state())
+    S.drift(hp_o, ids, Xn)
+    emb.drift(ids, Xn)
+    g, same = check()
+    np.testing.assert_array_equal(g["flags"][same] & 1, S.live("flags")[same])
+    dead = rng.choice(N0 + n_ins, 60, replace=False)
+    emb.set_state(S.as_gpu_state())
+    S.delete(hp_o, dead)
+    emb.delete(dead)
+    assert emb.stats()["N"] == S.N
+    check()
+    emb.close()
