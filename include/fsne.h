@@ -93,7 +93,8 @@ typedef struct fsne_state_view {
     float *Y;           /* N x d embedding                                         */
     float *V;           /* N x d velocity                                          */
     int32_t *hd_idx;    /* N x K_hd HD lists, sorted by (d2, index)                */
-    float *hd_d2;       /* N x K_hd squared HD distances of the lists              */
+    float *hd_d2;       /* N x K_hd HD distances of the lists in the current
+                           metric (squared Euclidean, or angular)              */
     int32_t *ld_idx;    /* N x K_ld LD lists                                       */
     float *rec;         /* N x 4 per-point {beta, m, r, invS}: beta = 1/(2 sigma^2),
                            m and r the smallest and largest d2 of the HD list,
@@ -166,7 +167,9 @@ fsne_status fsne_step(fsne_ctx *ctx, int32_t n_iters);
  * list by (d2, id), flags and recalibrates every point, recomputes the
  * affinities and sets E to 1, so that the next iterations refine the lists
  * towards the new metric's neighbours.  Synchronises the context stream when
- * the perplexity or the metric changes.  Errors: FSNE_EINVAL, FSNE_EHIP. */
+ * the perplexity or the metric changes.  Errors: FSNE_EINVAL, FSNE_ENOMEM (no
+ * memory for the unit rows of the angular metric; the previous hyperparameters
+ * stay), FSNE_EHIP. */
 fsne_status fsne_set_hyperparams(fsne_ctx *ctx, const fsne_hparams *hp);
 fsne_status fsne_get_hyperparams(const fsne_ctx *ctx, fsne_hparams *hp);
 
@@ -175,7 +178,8 @@ fsne_status fsne_get_hyperparams(const fsne_ctx *ctx, fsne_hparams *hp);
 fsne_status fsne_get_Y(fsne_ctx *ctx, float *out, int32_t out_on_device);
 
 /* Copy the current lists: which = 0 HD (idx N x K_hd, dist2 N x K_hd may be
- * NULL), which = 1 LD (idx N x K_ld; dist2 must be NULL).  Host memory.
+ * NULL; distances in the current HD metric), which = 1 LD (idx N x K_ld;
+ * dist2 must be NULL).  Host memory.
  * Synchronises.  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_get_knn(fsne_ctx *ctx, int32_t which, int32_t *idx, float *dist2);
 
