@@ -183,6 +183,25 @@ fsne_status fsne_get_Y(fsne_ctx *ctx, float *out, int32_t out_on_device);
  * Synchronises.  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_get_knn(fsne_ctx *ctx, int32_t which, int32_t *idx, float *dist2);
 
+/* Renumber the points (not in the paper; an ordering for memory locality):
+ * point i becomes point new_of_old[i], a permutation of 0..N-1 in host
+ * memory.  Every per-point row (X, Y, V, gradient partials, records, P,
+ * flags, lists) moves to the new id and every list entry is mapped; the
+ * method then goes on exactly as it would from the renumbered state (its
+ * draws are keyed by the new ids).  The remembered rejections are cleared.
+ * Synchronises.  Errors: FSNE_EINVAL (not a permutation), FSNE_ESTATE (X
+ * borrowed), FSNE_ENOMEM, FSNE_EHIP. */
+fsne_status fsne_renumber(fsne_ctx *ctx, const int32_t *new_of_old);
+
+/* Renumber the points along the Morton (Z-order) curve of the embedding
+ * projected onto at most three axes (y itself when d <= 3; otherwise axis a
+ * sums y_a, y_{a+3}, ... with alternating signs), ties by the old id, so
+ * that points close in the embedding get nearby ids and the step's gathers
+ * hit in the caches.  new_of_old (host, N entries, may be NULL) receives the
+ * permutation applied, for the caller's own per-point arrays.  Synchronises.
+ * Errors: FSNE_ENONFINITE, FSNE_ESTATE, FSNE_ENOMEM, FSNE_EHIP. */
+fsne_status fsne_reorder(fsne_ctx *ctx, int32_t *new_of_old);
+
 /* Copy the state to / from host memory (checkpoint, resume, checks).  set
  * reads every non-NULL field except A, R, Zh and recomputes the coin of the
  * next iteration from E and t.  If it sets HD lists, distances or records

@@ -327,6 +327,23 @@ class OracleState:
         lib().fsneo_delete_fix(C.byref(s), C.byref(hp.c()), _p(newid))
         return newid
 
+    def renumber(self, new_of_old):
+        """Point i becomes point new_of_old[i]: every per-point row moves to
+        its new id and every list entry is mapped (a relabelling of the state;
+        nothing is recomputed)."""
+        p = np.asarray(new_of_old, dtype=np.int64)
+        N = self.N
+        if p.shape != (N,) or not np.array_equal(np.sort(p), np.arange(N)):
+            raise ValueError("not a permutation of 0..N-1")
+        old_of_new = np.empty(N, dtype=np.int64)
+        old_of_new[p] = np.arange(N)
+        for name in ("X", "Y", "V", "hd_idx", "hd_d2", "ld_idx", "beta", "m", "r", "invS", "P",
+                     "flags"):
+            a = getattr(self, name)
+            a[:N] = a[:N][old_of_new]
+        self.hd_idx[:N] = p[self.hd_idx[:N]]
+        self.ld_idx[:N] = p[self.ld_idx[:N]]
+
     def cluster(self, eps: float, min_pts: int):
         labels = np.empty(self.N, dtype=np.int32)
         s = self.cstate()

@@ -1,0 +1,323 @@
+// Renumbering of the points for memory locality.  Every candidate, neighbour
+// and negative row the step reads is a gather at a random position; when the
+// points that are near one another in the data also have nearby ids, the
+// rows a block gathers come from a small region and hit in the caches.
+//
+// fsne_renumber applies a caller's permutation: every per-point row moves to
+// its new id and every list entry is mapped.  fsne_reorder picks the
+// permutation itself, as the Morton (Z-order) curve over a projection of the
+// embedding onto at most three axes: points close in the embedding, which
+// the method makes close in the data, get nearby ids.
+#include <hip/hip_runtime.h>
+
+#include <hipcub/device/device_radix_sort.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "fsne_context.h"
+
+namespace {
+
+// dst row new_of_old[i] = src row i, i < n (4-byte words when the row allows).
+__global__ void k_permute_rows(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src,
+                               const int32_t* __restrict__ new_of_old, int32_t n,
+                               int32_t row_bytes) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if ((row_bytes & 3) == 0) {
+    const int32_t w = row_bytes >> 2;
+    const int64_t total = (int64_t)n * w;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
+      const int64_t i = q / w, k = q - i * w;
+      reinterpret_cast<uint32_t*>(dst)[(int64_t)new_of_old[i] * w + k] =
+          reinterpret_cast<const uint32_t*>(src)[q];
+    }
+  } else {
+    const int64_t total = (int64_t)n * row_bytes;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
+      const int64_t i = q / row_bytes, k = q - i * row_bytes;
+      dst[(int64_t)new_of_old[i] * row_bytes + k] = src[q];
+    }
+  }
+}
+
+// ids[e] = new_of_old[ids[e]], e < count (every entry is a live id).
+__global__ void k_map_ids(int32_t* __restrict__ ids, const int32_t* __restrict__ new_of_old,
+                          int64_t count) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    ids[e] = new_of_old[ids[e]];
+}
+
+constexpr int kMaxAxes = 3;
+constexpr int kRedBlocks = 1024;
+
+// Coordinate a (< axes) of the projection of y: y itself when d <= 3,
+// otherwise the coordinates c = a, a + 3, a + 6, ... summed with alternating
+// signs (a fixed +-1 projection onto three axes).
+struct Projection {
+  int d, axes;
+  __device__ float operator()(const float* y, int a) const {
+    if (d <= kMaxAxes) return y[a];
+    float s = 0.0f;
+    for (int c = a, k = 0; c < d; c += kMaxAxes, ++k) s += (k & 1) ? -y[c] : y[c];
+    return s;
+  }
+};
+
+// Per-block minimum and maximum of each projected axis.
+__global__ void k_proj_range(const float* __restrict__ Y, int32_t n, int DP, Projection pr,
+                             float* __restrict__ part) {
+  __shared__ float lo[kMaxAxes][256], hi[kMaxAxes][256];
+  float l[kMaxAxes], h[kMaxAxes];
+  for (int a = 0; a < kMaxAxes; ++a) {
+    l[a] = INFINITY;
+    h[a] = -INFINITY;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    for (int a = 0; a < pr.axes; ++a) {
+      const float v = pr(Y + i * DP, a);
+      l[a] = fminf(l[a], v);
+      h[a] = fmaxf(h[a], v);
+    }
+  }
+  for (int a = 0; a < kMaxAxes; ++a) {
+    lo[a][threadIdx.x] = l[a];
+    hi[a][threadIdx.x] = h[a];
+  }
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int a = 0; a < kMaxAxes; ++a) {
+        lo[a][threadIdx.x] = fminf(lo[a][threadIdx.x], lo[a][threadIdx.x + s]);
+        hi[a][threadIdx.x] = fmaxf(hi[a][threadIdx.x], hi[a][threadIdx.x + s]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int a = 0; a < kMaxAxes; ++a) {
+      part[blockIdx.x * 2 * kMaxAxes + 2 * a] = lo[a][0];
+      part[blockIdx.x * 2 * kMaxAxes + 2 * a + 1] = hi[a][0];
+    }
+}
+
+// Spread the low 10 (3 axes), 15 (2 axes) or 30 (1 axis) bits of v so that
+// the axes interleave.
+__device__ __forceinline__ uint32_t spread(uint32_t v, int axes) {
+  if (axes == 1) return v;
+  uint32_t r = 0;
+  const int bits = 30 / axes;
+  for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1u) << (b * axes);
+  return r;
+}
+
+// Morton key of point i from its projected coordinates scaled to the range.
+__global__ void k_morton(const float* __restrict__ Y, int32_t n, int DP, Projection pr,
+                         const float* __restrict__ range, uint32_t* __restrict__ keys,
+                         int32_t* __restrict__ ids) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int bits = 30 / pr.axes;
+  const float top = (float)((1u << bits) - 1u);
+  uint32_t key = 0;
+  for (int a = 0; a < pr.axes; ++a) {
+    const float lo = range[2 * a], hi = range[2 * a + 1];
+    const float t = hi > lo ? (pr(Y + i * DP, a) - lo) / (hi - lo) : 0.0f;
+    const uint32_t q = (uint32_t)fminf(fmaxf(t * top, 0.0f), top);
+    key |= spread(q, pr.axes) << a;
+  }
+  keys[i] = key;
+  ids[i] = (int32_t)i;
+}
+
+// new_of_old[old_of_new[k]] = k.
+__global__ void k_invert(const int32_t* __restrict__ old_of_new, int32_t n,
+                         int32_t* __restrict__ new_of_old) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) new_of_old[old_of_new[k]] = (int32_t)k;
+}
+
+unsigned grid_for(int64_t work) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 65536));
+}
+
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  hipError_t get(T** p, size_t bytes) {
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, bytes > 0 ? bytes : 1);
+    if (e == hipSuccess) ptrs.push_back(q);
+    *p = static_cast<T*>(q);
+    return e;
+  }
+};
+
+fsne_status hip_error(fsne_ctx* c, hipError_t e, const char* where) {
+  c->err = std::string(where) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? FSNE_ENOMEM : FSNE_EHIP;
+}
+
+// Move every per-point row to its new id and map the list entries; d_new is
+// a device permutation of 0..N-1.  The remembered rejections are cleared.
+fsne_status apply_permutation(fsne_ctx* c, const int32_t* d_new) {
+  hipStream_t s = c->stream;
+  fsne::Scalars sc;
+  hipError_t e = hipMemcpyAsync(&sc, c->sc, sizeof(sc), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_error(c, e, "fsne_renumber: scalars");
+  const int32_t N = (int32_t)c->N;
+  const size_t xb = c->xdtype == FSNE_F32 ? 4 : 2;
+  struct Rows {
+    void* base;
+    size_t bytes;
+  };
+  const Rows rows[] = {
+      {c->X, (size_t)c->D * xb},
+      {c->Xu, sizeof(float) * c->D},
+      {c->xnorm, sizeof(float)},
+      {c->Y, sizeof(float) * c->DP},
+      {c->V, sizeof(float) * c->DP},
+      {c->A, sizeof(float) * c->DP},
+      {c->R, sizeof(float) * c->DP},
+      {c->Zh, sizeof(float)},
+      {c->rec, sizeof(float4)},
+      {c->P, sizeof(float) * c->Kh},
+      {c->flags, 1},
+      {c->ldc, 1},
+      {c->hd_idx[sc.hd_cur], sizeof(int32_t) * c->Kh},
+      {c->hd_d2[sc.hd_cur], sizeof(float) * c->Kh},
+      {c->ld_idx[sc.t & 1u], sizeof(int32_t) * c->Kl},
+  };
+  size_t most = 0;
+  for (const Rows& r : rows)
+    if (r.base) most = std::max(most, r.bytes * (size_t)N);
+  Scratch tmp;
+  uint8_t* buf = nullptr;
+  if ((e = tmp.get(&buf, most)) != hipSuccess) return hip_error(c, e, "fsne_renumber: staging");
+  for (const Rows& r : rows) {
+    if (!r.base) continue;
+    hipLaunchKernelGGL(k_permute_rows, dim3(grid_for((int64_t)N * r.bytes / 4 + 1)), dim3(256),
+                       0, s, buf, static_cast<const uint8_t*>(r.base), d_new, N,
+                       (int32_t)r.bytes);
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpyAsync(r.base, buf, r.bytes * (size_t)N, hipMemcpyDeviceToDevice, s)) !=
+            hipSuccess)
+      return hip_error(c, e, "fsne_renumber: rows");
+  }
+  for (int32_t* ids : {c->hd_idx[sc.hd_cur], c->ld_idx[sc.t & 1u]}) {
+    const int64_t count = (int64_t)N * (ids == c->hd_idx[sc.hd_cur] ? c->Kh : c->Kl);
+    hipLaunchKernelGGL(k_map_ids, dim3(grid_for(count)), dim3(256), 0, s, ids, d_new, count);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_error(c, e, "fsne_renumber: lists");
+  }
+  if ((e = hipMemsetAsync(c->memo, 0xFF, sizeof(int32_t) * (size_t)c->cap * fsne::kMemo, s)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_error(c, e, "fsne_renumber");
+  return FSNE_OK;
+}
+
+}  // namespace
+
+extern "C" fsne_status fsne_renumber(fsne_ctx* c, const int32_t* new_of_old) {
+  if (!c) return FSNE_EINVAL;
+  if (!new_of_old) {
+    c->err = "fsne_renumber: new_of_old is NULL";
+    return FSNE_EINVAL;
+  }
+  if (!c->own_X) {
+    c->err = "fsne_renumber: X is borrowed; create the context with capacity";
+    return FSNE_ESTATE;
+  }
+  const int32_t N = (int32_t)c->N;
+  std::vector<uint8_t> seen((size_t)N, 0);
+  for (int32_t i = 0; i < N; ++i) {
+    const int32_t v = new_of_old[i];
+    if (v < 0 || v >= N || seen[(size_t)v]) {
+      c->err = "fsne_renumber: new_of_old is not a permutation of 0..N-1";
+      return FSNE_EINVAL;
+    }
+    seen[(size_t)v] = 1;
+  }
+  Scratch tmp;
+  int32_t* d_new = nullptr;
+  hipError_t e;
+  if ((e = tmp.get(&d_new, sizeof(int32_t) * (size_t)N)) != hipSuccess ||
+      (e = hipMemcpyAsync(d_new, new_of_old, sizeof(int32_t) * (size_t)N,
+                          hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return hip_error(c, e, "fsne_renumber: upload");
+  return apply_permutation(c, d_new);
+}
+
+extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
+  if (!c) return FSNE_EINVAL;
+  if (!c->own_X) {
+    c->err = "fsne_reorder: X is borrowed; create the context with capacity";
+    return FSNE_ESTATE;
+  }
+  const int32_t N = (int32_t)c->N;
+  hipStream_t s = c->stream;
+  Projection pr{c->d, std::min(c->d, kMaxAxes)};
+  Scratch tmp;
+  float* part = nullptr;
+  float* range = nullptr;
+  uint32_t *keys = nullptr, *keys2 = nullptr;
+  int32_t *ids = nullptr, *ids2 = nullptr, *d_new = nullptr;
+  void* sort_tmp = nullptr;
+  size_t sort_bytes = 0;
+  hipError_t e;
+  if ((e = tmp.get(&part, sizeof(float) * kRedBlocks * 2 * kMaxAxes)) != hipSuccess ||
+      (e = tmp.get(&range, sizeof(float) * 2 * kMaxAxes)) != hipSuccess ||
+      (e = tmp.get(&keys, sizeof(uint32_t) * (size_t)N)) != hipSuccess ||
+      (e = tmp.get(&keys2, sizeof(uint32_t) * (size_t)N)) != hipSuccess ||
+      (e = tmp.get(&ids, sizeof(int32_t) * (size_t)N)) != hipSuccess ||
+      (e = tmp.get(&ids2, sizeof(int32_t) * (size_t)N)) != hipSuccess ||
+      (e = tmp.get(&d_new, sizeof(int32_t) * (size_t)N)) != hipSuccess)
+    return hip_error(c, e, "fsne_reorder: scratch");
+  hipLaunchKernelGGL(k_proj_range, dim3(kRedBlocks), dim3(256), 0, s, c->Y, N, c->DP, pr, part);
+  std::vector<float> hp((size_t)kRedBlocks * 2 * kMaxAxes);
+  if ((e = hipGetLastError()) != hipSuccess ||
+      (e = hipMemcpyAsync(hp.data(), part, sizeof(float) * hp.size(), hipMemcpyDeviceToHost,
+                          s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_error(c, e, "fsne_reorder: range");
+  float rg[2 * kMaxAxes];
+  for (int a = 0; a < kMaxAxes; ++a) {
+    rg[2 * a] = INFINITY;
+    rg[2 * a + 1] = -INFINITY;
+    for (int b = 0; b < kRedBlocks; ++b) {
+      rg[2 * a] = std::min(rg[2 * a], hp[(size_t)b * 2 * kMaxAxes + 2 * a]);
+      rg[2 * a + 1] = std::max(rg[2 * a + 1], hp[(size_t)b * 2 * kMaxAxes + 2 * a + 1]);
+    }
+    if (!std::isfinite(rg[2 * a]) || !std::isfinite(rg[2 * a + 1])) {
+      c->err = "fsne_reorder: the embedding holds a NaN or infinity";
+      return FSNE_ENONFINITE;
+    }
+  }
+  const unsigned gn = (unsigned)((N + 255) / 256);
+  if ((e = hipMemcpyAsync(range, rg, sizeof(rg), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_error(c, e, "fsne_reorder: range upload");
+  hipLaunchKernelGGL(k_morton, dim3(gn), dim3(256), 0, s, c->Y, N, c->DP, pr, range, keys, ids);
+  if ((e = hipGetLastError()) != hipSuccess ||
+      (e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, keys, keys2, ids, ids2, N, 0,
+                                              30, s)) != hipSuccess ||
+      (e = tmp.get(&sort_tmp, sort_bytes)) != hipSuccess ||
+      (e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, keys, keys2, ids, ids2, N, 0,
+                                              30, s)) != hipSuccess)
+    return hip_error(c, e, "fsne_reorder: sort");
+  hipLaunchKernelGGL(k_invert, dim3(gn), dim3(256), 0, s, ids2, N, d_new);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_error(c, e, "fsne_reorder: invert");
+  const fsne_status st = apply_permutation(c, d_new);
+  if (st != FSNE_OK) return st;
+  if (new_of_old &&
+      ((e = hipMemcpy(new_of_old, d_new, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToHost)) !=
+       hipSuccess))
+    return hip_error(c, e, "fsne_reorder: download");
+  return FSNE_OK;
+}

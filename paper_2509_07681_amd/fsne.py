@@ -76,6 +76,8 @@ def load_library(path: str = LIB_PATH):
     L.fsne_implode.argtypes = [P, F]
     L.fsne_jump_start.argtypes = [P, I32, F]
     L.fsne_delete_points.argtypes = [P, P, I64]
+    L.fsne_renumber.argtypes = [P, P]
+    L.fsne_reorder.argtypes = [P, P]
     L.fsne_cluster.argtypes = [P, F, I32, P, P]
     L.fsne_hierarchy_edges.argtypes = [P, I32, P, I32, I64, P]
     L.fsne_destroy.argtypes = [P]
@@ -259,6 +261,17 @@ def fsne_delete_points(ctx, ids):
     _check(ctx, load_library().fsne_delete_points(ctx, _ptr(ids), ids.size))
 
 
+def fsne_renumber(ctx, new_of_old):
+    p = np.ascontiguousarray(new_of_old, dtype=np.int32)
+    _check(ctx, load_library().fsne_renumber(ctx, _ptr(p)))
+
+
+def fsne_reorder(ctx, N):
+    p = np.empty(N, dtype=np.int32)
+    _check(ctx, load_library().fsne_reorder(ctx, _ptr(p)))
+    return p
+
+
 def fsne_cluster(ctx, N, eps: float, min_pts: int):
     labels = np.empty(N, dtype=np.int32)
     nc = np.zeros(1, dtype=np.int32)
@@ -333,6 +346,14 @@ class Embedding:
     def delete(self, ids):
         fsne_delete_points(self.ctx, ids)
         self.N -= np.asarray(ids).size
+
+    def renumber(self, new_of_old):
+        """Point i becomes point new_of_old[i] (a permutation of 0..N-1)."""
+        fsne_renumber(self.ctx, new_of_old)
+
+    def reorder(self):
+        """Renumber along the Morton curve of the embedding; returns new_of_old."""
+        return fsne_reorder(self.ctx, self.N)
 
     def cluster(self, eps, min_pts):
         return fsne_cluster(self.ctx, self.N, eps, min_pts)

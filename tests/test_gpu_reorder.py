@@ -1,0 +1,118 @@
+"""Renumbering of the points (fsne_renumber, fsne_reorder).
+
+A renumbering relabels the state: every per-point row moves to its new id
+and every list entry is mapped, bit for bit; from the renumbered state the
+method goes on exactly as the oracle does from its renumbered state.  The
+Morton order of the embedding gives nearby ids to neighbours."""
+import numpy as np
+import pytest
+
+from inputs.generators import blobs, f32_to_bf16_bits, manifolds, y_init
+from tests.parity import compare_hd_rows, hd_tie_tol, rel_l2
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
+
+ROWS = ["Y", "V", "A", "R", "Zh", "rec", "P", "flags", "hd_d2"]
+
+
+def _relabelled(s0, p, s1):
+    for k in ROWS:
+        assert np.array_equal(s1[k][p], s0[k]), k
+    assert np.array_equal(s1["hd_idx"][p], p[s0["hd_idx"]])
+    assert np.array_equal(s1["ld_idx"][p], p[s0["ld_idx"]])
+    assert s1["E"] == s0["E"] and s1["t"] == s0["t"]
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_renumber_moves_every_row(fsne_lib, bf16):
+    F = fsne_lib
+    X, _ = blobs(n_clusters=8, per_cluster=250, D=32, seed=41)
+    if bf16:
+        X = f32_to_bf16_bits(X)
+    N = X.shape[0]
+    hp = F.fsne_default_hparams(perplexity=10.0, lr=N / 12.0, n_neg=8, hd_mode=1, attr=12.0)
+    emb = F.Embedding(X, y_init(N, 4), 4, 32, 16, seed=3, hp=hp)
+    emb.step(20)
+    s0 = emb.state()
+    with pytest.raises(F.FsneError) as e:
+        emb.renumber(np.zeros(N, dtype=np.int32))
+    assert e.value.status == F.FSNE_EINVAL
+    _relabelled(s0, np.arange(N), emb.state())
+    p = np.random.default_rng(5).permutation(N).astype(np.int32)
+    emb.renumber(p)
+    _relabelled(s0, p, emb.state())
+    # the rows of X moved too: the stored distances are those of the new ids
+    emb.step(3)
+    g = emb.state()
+    Xf = X.astype(np.float32) if not bf16 else None
+    if Xf is not None:
+        Xp = np.empty_like(Xf)
+        Xp[p] = Xf
+        for i in range(0, N, 97):
+            ex = ((Xp[g["hd_idx"][i]].astype(np.float64) - Xp[i]) ** 2).sum(1)
+            np.testing.assert_allclose(g["hd_d2"][i], ex, rtol=1e-5)
+    assert emb.stats()["nonfinite"] == 0
+    emb.close()
+
+
+def test_renumbered_steps_match_oracle(oracle_lib, fsne_lib):
+    O, F = oracle_lib, fsne_lib
+    X, _ = blobs(n_clusters=10, per_cluster=200, D=24, seed=43)
+    N = X.shape[0]
+    kw = dict(alpha=1.0, perplexity=10.0, lr=float(np.float32(N / 12.0)), momentum=0.5,
+              attr=12.0, rep=1.0, n_neg=8, hd_mode=1, e_smooth=0.1, p_min=0.05)
+    hp_o, hp_g = O.Hyper(**kw), F.fsne_default_hparams(**kw)
+    Y0 = y_init(N, 2)
+    S = O.OracleState(X, 2, 32, 16, 42, Y0).init(hp_o)
+    emb = F.Embedding(X, Y0, 2, 32, 16, seed=42, hp=hp_g)
+    for _ in range(3):
+        S.step(hp_o)
+    emb.set_state(S.as_gpu_state())
+    p = np.random.default_rng(6).permutation(N).astype(np.int32)
+    S.renumber(p)
+    emb.renumber(p)
+    tol = hd_tie_tol(X.shape[1])
+    for _ in range(3):
+        out = S.step(hp_o, want_partials=True)
+        emb.step(1)
+        g = emb.state()
+        differ, nbad, bad = compare_hd_rows(S.live("X"), g["hd_idx"], S.live("hd_idx"),
+                                            S.live("hd_d2"), tol)
+        assert nbad == 0 and differ <= max(3, N // 500), (differ, bad[:5])
+        same = np.all(g["hd_idx"] == S.live("hd_idx"), axis=1)
+        clean = same & np.all(same[S.live("hd_idx")], axis=1)
+        ok = clean & np.all(g["ld_idx"] == S.live("ld_idx"), axis=1)
+        assert ok.mean() > 0.9
+        assert rel_l2(g["P"][clean], S.live("P")[clean]) < 1e-4
+        assert rel_l2(g["A"][ok], out["A"][ok]) < 1e-4
+        assert rel_l2(g["R"][ok], out["R"][ok]) < 1e-4
+        emb.set_state(S.as_gpu_state())
+    emb.close()
+
+
+def _locality(hd):
+    N = hd.shape[0]
+    return float(np.mean(np.abs(hd - np.arange(N)[:, None]))) / N
+
+
+def test_reorder_gives_neighbours_nearby_ids(fsne_lib):
+    F = fsne_lib
+    X = manifolds(n_manifolds=20, per_manifold=400, seed=1003)[0]
+    N = X.shape[0]
+    hp = F.fsne_default_hparams(perplexity=10.0, lr=N / 12.0, n_neg=16, hd_mode=1, attr=12.0)
+    emb = F.Embedding(X, y_init(N, 16), 16, 32, 32, seed=3, hp=hp)
+    emb.step(150)
+    s0 = emb.state()
+    before = _locality(s0["hd_idx"])
+    p = emb.reorder()
+    assert np.array_equal(np.sort(p), np.arange(N))
+    _relabelled(s0, p, emb.state())
+    after = _locality(emb.state()["hd_idx"])
+    assert after < 0.3 * before, (before, after)
+    # the run goes on from the renumbered state and the ids stay local
+    emb.step(50)
+    g = emb.state()
+    assert emb.stats()["nonfinite"] == 0
+    assert np.all(np.diff(g["hd_d2"], axis=1) >= 0)
+    assert _locality(g["hd_idx"]) < 0.5 * before
+    emb.close()

@@ -663,3 +663,39 @@ def test_metric_switch_recomputes_every_list(oracle_lib):
     for i in range(0, N, 5):
         np.testing.assert_allclose(S.hd_d2[i], ((X64[S.hd_idx[i]] - X64[i]) ** 2).sum(1),
                                    rtol=1e-12)
+
+
+# --- renumbering (a relabelling of the state, for memory locality) ----------
+def test_renumber_relabels_the_state(oracle_lib):
+    """The identity changes nothing; a permutation and its inverse restore the
+    state exactly; every stored distance is the distance between the
+    renumbered rows and every list holds the mapped set of points."""
+    O = oracle_lib
+    X, _ = blobs(n_clusters=4, per_cluster=50, D=8, seed=31)
+    N, K = X.shape[0], 12
+    S = O.OracleState(X, 2, K, 8, 5, y_init(N, 2))
+    hp = O.Hyper(perplexity=5.0, lr=N / 12, attr=4.0, n_neg=4, hd_mode=1)
+    S.init(hp)
+    for _ in range(10):
+        S.step(hp)
+    ref = S.copy()
+    names = ("X", "Y", "V", "hd_idx", "hd_d2", "ld_idx", "beta", "m", "r", "invS", "P", "flags")
+    S.renumber(np.arange(N))
+    for k in names:
+        assert np.array_equal(S.live(k), ref.live(k)), k
+    p = np.random.default_rng(4).permutation(N)
+    S.renumber(p)
+    Xd = S.live("X").astype(np.float64)
+    for i_old in range(0, N, 9):
+        i = p[i_old]
+        assert set(S.hd_idx[i].tolist()) == set(p[ref.hd_idx[i_old]].tolist())
+        np.testing.assert_allclose(S.hd_d2[i], ((Xd[S.hd_idx[i]] - Xd[i]) ** 2).sum(1),
+                                   rtol=1e-12)
+        assert np.array_equal(S.Y[i], ref.Y[i_old]) and np.array_equal(S.P[i], ref.P[i_old])
+    inv = np.empty(N, dtype=np.int64)
+    inv[p] = np.arange(N)
+    S.renumber(inv)
+    for k in names:
+        assert np.array_equal(S.live(k), ref.live(k)), k
+    with pytest.raises(ValueError):
+        S.renumber(np.zeros(N, dtype=np.int64))
