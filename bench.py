@@ -32,7 +32,8 @@ C_SLOTS = 32
 
 # Sources the step's kernels and their launches are built from; the placement
 # network, clustering and jump-start files hold kernels of their own.
-STEP_SOURCES = ("fsne_api.hip", "fsne_bf16.hip", "fsne_unit.hip", "fsne_context.h", "fsne_device.h",
+STEP_SOURCES = ("fsne_api.hip", "fsne_bf16.hip", "fsne_unit.hip", "fsne_reorder.hip",
+                "fsne_context.h", "fsne_device.h",
                 "fsne_kernels.h", "fsne_kernels.hip")
 
 
@@ -78,6 +79,38 @@ def all_slot_bytes_per_point(cfg, xbytes):
     return dict(hd_refine=hd, ld_grad=ld, update=6 * sy)
 
 
+def run_steps(emb, n, every):
+    """n iterations; with every > 0 the points are renumbered along the Morton
+    order of the embedding (fsne_reorder) before each chunk of `every`
+    iterations, the renumbering's time included."""
+    done = 0
+    while done < n:
+        k = n - done if every <= 0 else min(every, n - done)
+        if every > 0:
+            emb.reorder()
+        emb.step(k)
+        done += k
+
+
+def profiled_steps(emb, n, every, N):
+    """n single iterations with kernel timing on (renumbering as run_steps);
+    returns the kernel times and the mean HD / LD candidate rows per point."""
+    import numpy as np
+
+    emb.profile(True)
+    hd_c, ld_c = [], []
+    for it in range(n):
+        if every > 0 and it % every == 0:
+            emb.reorder()
+        emb.step(1)
+        s1 = emb.stats()
+        hd_c.append(s1["hd_cand_rows"] / N)
+        ld_c.append(s1["ld_cand_rows"] / N)
+    kt = emb.kernel_times()
+    emb.profile(False)
+    return kt, float(np.mean(hd_c)), float(np.mean(ld_c))
+
+
 def schedule(F, base, t):
     """Early exaggeration 12 with momentum 0.5 for 250 iterations, then 1 and 0.8."""
     early = t < 250
@@ -86,10 +119,14 @@ def schedule(F, base, t):
 
 
 def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=50,
-                labels=None, lr_div=12.0):
+                labels=None, lr_div=12.0, reorder_every=0):
     """n_iter iterations under the coin with the standard schedule; HD recall@K
     on the query sample every ``every`` iterations (the clock is stopped while
-    the recall is measured)."""
+    the recall is measured).  With reorder_every > 0 the points are renumbered
+    along the embedding's Morton order at every multiple of it (timed); the
+    lists are mapped back to the original ids to be measured."""
+    import numpy as np
+
     from inputs.knn_metrics import recall_at_k
 
     N = X.shape[0]
@@ -99,6 +136,13 @@ def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=
                       hp=schedule(F, base, 0))
     emb.sync()
     r0 = emb.stats()["hd_refinements"]
+    orig = np.arange(N)              # original id of each current id
+
+    def in_original_ids(lists):
+        out = np.empty_like(lists)
+        out[orig] = orig[lists]
+        return out
+
     done, secs, curve = 0, 0.0, []
     while done < n_iter:
         stop = min(n_iter, (done // every + 1) * every)
@@ -106,17 +150,23 @@ def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=
             stop = 250
         emb.set_hyperparams(schedule(F, base, done))
         t0 = time.perf_counter()
+        if reorder_every > 0 and done > 0 and done % reorder_every == 0:
+            p = emb.reorder()
+            nxt = np.empty_like(orig)
+            nxt[p] = orig
+            orig = nxt
         emb.step(stop - done)
         emb.sync()
         secs += time.perf_counter() - t0
         done = stop
         if done % every == 0 or done == n_iter:
             idx, _ = emb.knn(0)
-            curve.append([done, round(secs, 4), round(recall_at_k(idx, X, queries, ex_d2), 4)])
+            curve.append([done, round(secs, 4),
+                          round(recall_at_k(in_original_ids(idx), X, queries, ex_d2), 4)])
     st = emb.stats()
     extra = {}
     if labels is not None:
-        ld, _ = emb.knn(1)
+        ld = in_original_ids(emb.knn(1)[0])
         extra["ld_same_class"] = round(float((labels[ld] == labels[:, None]).mean()), 4)
     emb.close()
     return dict(**extra, iters=n_iter, seconds=round(secs, 3), iters_per_s=round(n_iter / secs, 2),
@@ -752,6 +802,9 @@ def main():
                     default=[10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000])
     ap.add_argument("--large", action="store_true",
                     help="run the 4M-point BF16 workload instead")
+    ap.add_argument("--reorder-every", type=int, default=25,
+                    help="renumber the points along the embedding's Morton order every this "
+                         "many steps in the timed runs (0: never)")
     ap.add_argument("--blobs-knn", action="store_true",
                     help="HD-list R_NX(K) on overlapping and disjointed blobs instead")
     ap.add_argument("--memo-compare", action="store_true",
@@ -834,12 +887,25 @@ def main():
     Y0 = y_init(N, cfg["d"])
     hp = F.fsne_default_hparams(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=N / 12.0,
                                 momentum=0.5, attr=12.0, n_neg=cfg["n_neg"], hd_mode=1)
+    every = args.reorder_every
+    n_prof = min(args.steps, 50)
+    # the same run without renumbering, for comparison
+    emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp)
+    emb.step(args.warmup)
+    emb.sync()
+    t0 = time.perf_counter()
+    emb.step(args.steps)
+    emb.sync()
+    ms_plain = (time.perf_counter() - t0) * 1e3 / args.steps
+    kt0, _, _ = profiled_steps(emb, n_prof, 0, N)
+    emb.close()
+
     emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp)
     emb.step(args.warmup)
     emb.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    emb.step(args.steps)
+    run_steps(emb, args.steps, every)
     emb.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -849,19 +915,9 @@ def main():
 
     # per-kernel durations from HIP events recorded on the library's stream,
     # and the candidate rows each iteration actually loaded
-    n_prof = min(args.steps, 50)
-    emb.profile(True)
-    hd_c, ld_c = [], []
-    for _ in range(n_prof):
-        emb.step(1)
-        s1 = emb.stats()
-        hd_c.append(s1["hd_cand_rows"] / N)
-        ld_c.append(s1["ld_cand_rows"] / N)
-    kt = emb.kernel_times()
-    emb.profile(False)
+    kt, hd_cand, ld_cand = profiled_steps(emb, n_prof, every, N)
     emb.close()
 
-    hd_cand, ld_cand = float(np.mean(hd_c)), float(np.mean(ld_c))
     bpp = bytes_per_point(cfg, 4, hd_cand, ld_cand)
     sbpp = all_slot_bytes_per_point(cfg, 4)
     kernels = {}
@@ -893,7 +949,8 @@ def main():
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tf):
         rec = json.load(open(tf))
-        if rec.get("source_hash") == kernel_source_hash() and "hd_refine" in rec.get("per_launch_GB", {}):
+        if (rec.get("source_hash") == kernel_source_hash() and rec.get("reorder_every") == every
+                and "hd_refine" in rec.get("per_launch_GB", {})):
             traffic = rec["per_launch_GB"]["hd_refine"]
     out = {
         "metric": METRIC,
@@ -910,9 +967,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "manifold_1m: N=1,000,000 points on 50 seeded 8-dim linear "
                                "manifolds in R^128 (FP32 rows), d=16, K_hd=K_ld=32, 16 negatives, "
-                               "alpha=1, perplexity 10; every timed step refines the HD lists",
+                               "alpha=1, perplexity 10; every timed step refines the HD lists"
+                               + (f"; the points are renumbered along the embedding's Morton "
+                                  f"order every {every} steps, inside the timed region"
+                                  if every > 0 else ""),
                    "N": N, "D": cfg["D"], "d": cfg["d"], "K_hd": cfg["K_hd"],
-                   "K_ld": cfg["K_ld"], "n_neg": cfg["n_neg"], "hd_mode": "always"},
+                   "K_ld": cfg["K_ld"], "n_neg": cfg["n_neg"], "hd_mode": "always",
+                   "reorder_every": every},
         "roofline": {"bound": "hbm", "kernel": "hd_refine", "achieved": dom["GBps"],
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": dom["frac"],
                      "traffic": traffic, "traffic_unit": "GB per launch (FETCH_SIZE x2.0 "
@@ -921,6 +982,10 @@ def main():
         "gather_ceiling": probe,
         "ld_only_ms_per_step": round(ld_only_ms, 4),
         "ld_only_iters_per_s": round(1000.0 / ld_only_ms, 2),
+        "no_reorder": {"ms_per_step": round(ms_plain, 4),
+                       "iters_per_s": round(1000.0 / ms_plain, 3),
+                       "kernels_ms": {k: round(v[0] / max(v[1], 1), 4)
+                                      for k, v in kt0.items() if v[1]}},
     }
 
     # the BF16 forms: step time with the HD refinement on
@@ -930,13 +995,11 @@ def main():
         hpf = F.fsne_default_hparams(**{**hp.as_dict(), "dist_mode": dm})
         e2 = F.Embedding(Xb, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hpf)
         e2.step(args.warmup)
-        e2.profile(True)
         nf = min(args.steps, 50)
-        e2.step(nf)
-        kt2 = e2.kernel_times()
+        kt2, _, _ = profiled_steps(e2, nf, every, N)
         e2.sync()
         t2 = time.perf_counter()
-        e2.step(nf)
+        run_steps(e2, nf, every)
         e2.sync()
         ms2 = (time.perf_counter() - t2) * 1e3 / nf
         e2.close()
@@ -950,12 +1013,14 @@ def main():
         rng = np.random.default_rng(7)
         queries = rng.choice(N, args.queries, replace=False)
         _, ex_d2 = exact_knn(X, queries, cfg["K_hd"])
-        runs = {"f32": quality_run(F, X, cfg, Y0, args.quality_iters, RUN_SEED, queries, ex_d2)}
+        qre = 100 if every > 0 else 0     # renumbering cadence under the coin
+        runs = {"f32": quality_run(F, X, cfg, Y0, args.quality_iters, RUN_SEED, queries, ex_d2,
+                                   reorder_every=qre)}
         _, ex_b = exact_knn(Xb, queries, cfg["K_hd"])
         runs["bf16_rows_direct"] = quality_run(F, Xb, cfg, Y0, args.quality_iters, RUN_SEED,
-                                               queries, ex_b)
+                                               queries, ex_b, reorder_every=qre)
         runs["bf16_mfma_screen"] = quality_run(F, Xb, cfg, Y0, args.quality_iters, RUN_SEED,
-                                               queries, ex_b, dist_mode=1)
+                                               queries, ex_b, dist_mode=1, reorder_every=qre)
         # seconds for each form to reach 0.95 of the FP32 form's final recall
         target = round(0.95 * runs["f32"]["recall_at_32"], 4)
         for r in runs.values():
