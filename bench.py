@@ -384,7 +384,8 @@ def large_run(F, args):
     mixture in R^256 (BF16 rows), d = 32, K_hd = 64, K_ld = 32, 32 negatives,
     alpha = 0.5, perplexity 20.  Reports the step time with the HD refinement
     on and off (and with the BF16 MFMA screen), the per-kernel times, and
-    500-iteration runs, under the coin and with every iteration refining, with
+    500-iteration runs, under the coin and with every iteration refining, each
+    also with the points renumbered for locality every 100 iterations, with
     HD recall@64 of 500 query points against exact neighbours."""
     import numpy as np
     import torch
@@ -428,22 +429,40 @@ def large_run(F, args):
     _, ex = exact_knn_device(Xd, Xb, q, K)
     del Xd
     torch.cuda.empty_cache()
-    # 500 iterations under the coin, then the same with every iteration refining
-    for hd_mode, name in ((0, "run_500"), (1, "run_500_hd_always")):
+    # 500 iterations under the coin, then the same with every iteration
+    # refining; each also with the points renumbered along the embedding's
+    # Morton order every 100 iterations (timed; the lists are mapped back to
+    # the original ids to be measured)
+    runs = [(0, "run_500", 0), (1, "run_500_hd_always", 0)]
+    if args.reorder_every > 0:
+        runs += [(0, "run_500_renumbered", 100), (1, "run_500_hd_always_renumbered", 100)]
+    for hd_mode, name, every in runs:
         emb = F.Embedding(Xb, Y0, cfg["d"], K, cfg["K_ld"], seed=RUN_SEED,
                           hp=schedule(F, {**base, "hd_mode": hd_mode}, 0))
         emb.sync()
+        orig = np.arange(N)
         t0 = time.perf_counter()
-        emb.step(250)
-        emb.set_hyperparams(schedule(F, {**base, "hd_mode": hd_mode}, 250))
-        emb.step(250)
+        for done in range(0, 500, 100):
+            if every and done > 0:
+                p = emb.reorder()
+                nxt = np.empty_like(orig)
+                nxt[p] = orig
+                orig = nxt
+            if done < 250 < done + 100:
+                emb.step(250 - done)
+                emb.set_hyperparams(schedule(F, {**base, "hd_mode": hd_mode}, 250))
+                emb.step(done + 100 - 250)
+            else:
+                emb.step(100)
         emb.sync()
         secs = time.perf_counter() - t0
-        idx, _ = emb.knn(0)
+        idx = emb.knn(0)[0]
+        lists = np.empty_like(idx)
+        lists[orig] = orig[idx]
         st = emb.stats()
         emb.close()
         out[name] = {"seconds": round(secs, 3), "iters_per_s": round(500 / secs, 2),
-                     "recall_at_64": round(recall_at_k(idx, Xb, q, ex), 4),
+                     "recall_at_64": round(recall_at_k(lists, Xb, q, ex), 4),
                      "final_E": round(float(st["E"]), 4), "nonfinite": int(st["nonfinite"])}
     return out
 
