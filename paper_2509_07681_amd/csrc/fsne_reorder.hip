@@ -287,8 +287,8 @@ extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
                           s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess)
     return hip_error(c, e, "fsne_reorder: range");
-  float rg[2 * kMaxAxes];
-  for (int a = 0; a < kMaxAxes; ++a) {
+  float rg[2 * kMaxAxes] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int a = 0; a < pr.axes; ++a) {
     rg[2 * a] = INFINITY;
     rg[2 * a + 1] = -INFINITY;
     for (int b = 0; b < kRedBlocks; ++b) {

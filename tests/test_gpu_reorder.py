@@ -116,3 +116,52 @@ def test_reorder_gives_neighbours_nearby_ids(fsne_lib):
     assert np.all(np.diff(g["hd_d2"], axis=1) >= 0)
     assert _locality(g["hd_idx"]) < 0.5 * before
     emb.close()
+
+
+@pytest.mark.parametrize("N,d", [(7, 2), (1001, 2), (999, 3), (1234, 1)])
+def test_reorder_low_dimensions_and_small_sizes(fsne_lib, N, d):
+    """d <= 3 keys the Morton curve on the coordinates themselves; tiny and
+    ragged sizes give valid permutations and relabelled states."""
+    F = fsne_lib
+    X = np.random.default_rng(N).normal(size=(N, 12)).astype(np.float32)
+    Kh, Kl = min(5, N - 1), min(4, N - 1)
+    hp = F.fsne_default_hparams(perplexity=min(3.0, Kh - 0.5), lr=max(N / 12.0, 1.0), n_neg=4,
+                                hd_mode=1)
+    emb = F.Embedding(X, y_init(N, d), d, Kh, Kl, seed=9, hp=hp)
+    emb.step(30)
+    s0 = emb.state()
+    p = emb.reorder()
+    assert np.array_equal(np.sort(p), np.arange(N))
+    _relabelled(s0, p, emb.state())
+    # the new order follows the Morton keys: ids grow along the first axis
+    # within runs, so consecutive ids are close in the embedding
+    Y = emb.Y()
+    step = np.sqrt(((Y[1:] - Y[:-1]) ** 2).sum(1)).mean()
+    rnd = np.sqrt(((Y[np.random.default_rng(1).permutation(N)][1:] - Y[:-1]) ** 2).sum(1)).mean()
+    assert N < 100 or step < 0.5 * rnd, (step, rnd)
+    emb.step(5)
+    assert emb.stats()["nonfinite"] == 0
+    emb.close()
+
+
+def test_renumber_under_the_angular_metric(fsne_lib):
+    """The unit rows move with X: after a renumbering every stored distance
+    is the angular distance between the new ids' rows."""
+    F = fsne_lib
+    X, _ = blobs(n_clusters=6, per_cluster=200, D=20, seed=47)
+    X = (X * np.exp2(np.random.default_rng(3).integers(-3, 4, size=(X.shape[0], 1)))).astype(
+        np.float32)
+    N = X.shape[0]
+    hp = F.fsne_default_hparams(perplexity=8.0, lr=N / 12.0, n_neg=8, hd_mode=1, metric=1)
+    emb = F.Embedding(X, y_init(N, 2), 2, 16, 8, seed=3, hp=hp)
+    emb.step(10)
+    p = emb.reorder()
+    emb.step(3)
+    g = emb.state()
+    Xp = np.empty_like(X)
+    Xp[p] = X
+    U = Xp.astype(np.float64) / np.linalg.norm(Xp.astype(np.float64), axis=1, keepdims=True)
+    for i in range(0, N, 37):
+        ex = ((U[g["hd_idx"][i]] - U[i]) ** 2).sum(1)
+        assert np.all(np.abs(g["hd_d2"][i] - ex) <= 1e-4 * np.sqrt(ex) + 1e-6 * ex + 1e-7), i
+    emb.close()
