@@ -21,16 +21,19 @@ from tests.parity import exact_d2, hd_tie_tol, rel_l2
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
-# name: (workload, BF16 rows, dist_mode, alpha override, HD metric)
+# name: (workload, BF16 rows, dist_mode, alpha override, HD metric, renumbered)
 CASES = {
-    "image_70k_f32": ("image_70k", False, 0, 1.0, 0),
-    "image_70k_f32_a05": ("image_70k", False, 0, 0.5, 0),
-    "image_70k_f32_a4": ("image_70k", False, 0, 4.0, 0),
-    "manifold_1m_f32": ("manifold_1m", False, 0, None, 0),
-    "manifold_1m_f32_angular": ("manifold_1m", False, 0, None, 1),
-    "manifold_1m_bf16_screen": ("manifold_1m", True, 1, None, 0),
-    "zipf_4m_bf16": ("zipf_4m", True, 0, None, 0),
-    "zipf_4m_bf16_screen": ("zipf_4m", True, 1, None, 0),
+    "image_70k_f32": ("image_70k", False, 0, 1.0, 0, False),
+    "image_70k_f32_a05": ("image_70k", False, 0, 0.5, 0, False),
+    "image_70k_f32_a4": ("image_70k", False, 0, 4.0, 0, False),
+    "manifold_1m_f32": ("manifold_1m", False, 0, None, 0, False),
+    # the benchmark's configuration: the state renumbered (fsne_reorder) on the
+    # GPU and the same permutation applied to the oracle's state
+    "manifold_1m_f32_renumbered": ("manifold_1m", False, 0, None, 0, True),
+    "manifold_1m_f32_angular": ("manifold_1m", False, 0, None, 1, False),
+    "manifold_1m_bf16_screen": ("manifold_1m", True, 1, None, 0, False),
+    "zipf_4m_bf16": ("zipf_4m", True, 0, None, 0, False),
+    "zipf_4m_bf16_screen": ("zipf_4m", True, 1, None, 0, False),
 }
 
 U = 2.0 ** -24
@@ -59,7 +62,7 @@ def _d2_bound(D, bf16, metric, d2):
 @pytest.mark.parametrize("case", list(CASES))
 def test_fullsize_sampled_step(oracle_lib, fsne_lib, case):
     O, F = oracle_lib, fsne_lib
-    name, bf16, dist_mode, alpha_override, metric = CASES[case]
+    name, bf16, dist_mode, alpha_override, metric, renumbered = CASES[case]
     X, _, cfg = make_workload(name)
     if bf16:
         X = f32_to_bf16_bits(X)
@@ -74,6 +77,11 @@ def test_fullsize_sampled_step(oracle_lib, fsne_lib, case):
     S = O.OracleState(X, cfg["d"], cfg["K_hd"], cfg["K_ld"], 42, Y0, metric=metric).init(hp_o)
     emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=42, hp=hp_g)
     emb.set_state(S.as_gpu_state())
+    if renumbered:
+        p = emb.reorder()
+        assert np.array_equal(np.sort(p), np.arange(N))
+        S.renumber(p)
+        X = S.live("X")
     emb.step(1)
     g = emb.state(["hd_idx", "hd_d2", "ld_idx", "rec", "P", "flags", "A", "R", "Zh"])
     st = emb.stats()
