@@ -996,7 +996,14 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "hd_refine", "achieved": dom["GBps"],
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": dom["frac"],
                      "traffic": traffic, "traffic_unit": "GB per launch (FETCH_SIZE x2.0 "
-                     "+ WRITE_SIZE x1.0, copy-calibrated)"},
+                     "+ WRITE_SIZE x1.0, copy-calibrated)",
+                     # the bytes the kernel actually moves to and from the memory
+                     # side, over the same duration (with renumbering the caches
+                     # serve part of the algorithmic bytes, so frac can exceed 1)
+                     "traffic_GBps": (round(traffic / (dom["avg_ms"] * 1e-3), 1)
+                                      if traffic is not None else None),
+                     "traffic_frac": (round(traffic / (dom["avg_ms"] * 1e-3) / PEAK_HBM_GBS, 4)
+                                      if traffic is not None else None)},
         "kernels": kernels,
         "gather_ceiling": probe,
         "ld_only_ms_per_step": round(ld_only_ms, 4),
