@@ -561,7 +561,8 @@ def scaling_run(F, args):
     (50 linear 8-dim manifolds in R^32, FP32), d = 2, K_hd = K_ld = 32, 16
     negatives, alpha = 1, perplexity 10.  For each N: ms per iteration with
     the HD refinement on every step and with it off, and the mean over a
-    500-iteration run under the coin with the standard schedule."""
+    500-iteration run under the coin with the standard schedule, also with
+    the points renumbered every 100 iterations."""
     from inputs.generators import RUN_SEED, manifolds, y_init
 
     out = {"metric": "ms per iteration vs N at D = 32",
@@ -593,6 +594,24 @@ def scaling_run(F, args):
         emb.sync()
         row["run_500_mean_ms"] = round((time.perf_counter() - t0) * 1e3 / 500, 4)
         emb.close()
+        if args.reorder_every > 0:
+            # the same run with the points renumbered every 100 iterations (timed)
+            emb = F.Embedding(X, Y0, 2, 32, 32, seed=RUN_SEED,
+                              hp=schedule(F, {**base, "hd_mode": 0}, 0))
+            emb.sync()
+            t0 = time.perf_counter()
+            for done in range(0, 500, 100):
+                if done:
+                    emb.reorder()
+                if done < 250 < done + 100:
+                    emb.step(250 - done)
+                    emb.set_hyperparams(schedule(F, {**base, "hd_mode": 0}, 250))
+                    emb.step(done + 100 - 250)
+                else:
+                    emb.step(100)
+            emb.sync()
+            row["run_500_renumbered_mean_ms"] = round((time.perf_counter() - t0) * 1e3 / 500, 4)
+            emb.close()
         out["sizes"].append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
     return out
