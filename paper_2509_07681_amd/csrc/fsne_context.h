@@ -32,6 +32,8 @@ struct fsne_ctx {
   uint8_t* moved = nullptr;
   int32_t* memo = nullptr;   // cap x kMemo rejected HD candidates, -1 = empty
   float* Xu = nullptr;       // cap x D rows scaled to unit length (angular metric)
+  uint8_t* rwork = nullptr;  // renumbering workspace (kept between calls)
+  size_t rwork_bytes = 0;
   fsne::Scalars* sc = nullptr;
   std::string err;
   std::vector<void*> owned;

@@ -144,41 +144,41 @@ unsigned grid_for(int64_t work) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 65536));
 }
 
-struct Scratch {
-  std::vector<void*> ptrs;
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
-  template <typename T>
-  hipError_t get(T** p, size_t bytes) {
+// The renumbering's device workspace, kept by the context between calls (a
+// call that needs more replaces it) and freed with the context, so that a
+// renumbering allocates nothing once the first one has run.
+hipError_t workspace(fsne_ctx* c, size_t bytes, uint8_t** out) {
+  if (c->rwork_bytes < bytes) {
+    if (c->rwork) {
+      const auto it = std::find(c->owned.begin(), c->owned.end(), (void*)c->rwork);
+      if (it != c->owned.end()) c->owned.erase(it);
+      (void)hipFree(c->rwork);
+      c->rwork = nullptr;
+      c->rwork_bytes = 0;
+    }
     void* q = nullptr;
-    const hipError_t e = hipMalloc(&q, bytes > 0 ? bytes : 1);
-    if (e == hipSuccess) ptrs.push_back(q);
-    *p = static_cast<T*>(q);
-    return e;
+    const hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return e;
+    c->owned.push_back(q);
+    c->rwork = static_cast<uint8_t*>(q);
+    c->rwork_bytes = bytes;
   }
-};
-
-fsne_status hip_error(fsne_ctx* c, hipError_t e, const char* where) {
-  c->err = std::string(where) + ": " + hipGetErrorString(e);
-  return e == hipErrorOutOfMemory ? FSNE_ENOMEM : FSNE_EHIP;
+  *out = c->rwork;
+  return hipSuccess;
 }
 
-// Move every per-point row to its new id and map the list entries; d_new is
-// a device permutation of 0..N-1.  The remembered rejections are cleared.
-fsne_status apply_permutation(fsne_ctx* c, const int32_t* d_new) {
-  hipStream_t s = c->stream;
-  fsne::Scalars sc;
-  hipError_t e = hipMemcpyAsync(&sc, c->sc, sizeof(sc), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_error(c, e, "fsne_renumber: scalars");
-  const int32_t N = (int32_t)c->N;
+constexpr size_t align_up(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct RowArray {
+  void* base;
+  size_t bytes;
+};
+
+// Per-point arrays a renumbering moves (null ones are skipped), and the
+// largest of them in bytes for N points.
+std::vector<RowArray> row_arrays(fsne_ctx* c, const fsne::Scalars& sc, size_t* most) {
   const size_t xb = c->xdtype == FSNE_F32 ? 4 : 2;
-  struct Rows {
-    void* base;
-    size_t bytes;
-  };
-  const Rows rows[] = {
+  std::vector<RowArray> rows = {
       {c->X, (size_t)c->D * xb},
       {c->Xu, sizeof(float) * c->D},
       {c->xnorm, sizeof(float)},
@@ -195,13 +195,38 @@ fsne_status apply_permutation(fsne_ctx* c, const int32_t* d_new) {
       {c->hd_d2[sc.hd_cur], sizeof(float) * c->Kh},
       {c->ld_idx[sc.t & 1u], sizeof(int32_t) * c->Kl},
   };
+  *most = 0;
+  for (const RowArray& r : rows)
+    if (r.base) *most = std::max(*most, r.bytes * (size_t)c->N);
+  return rows;
+}
+
+fsne_status read_scalars(fsne_ctx* c, fsne::Scalars* sc) {
+  hipError_t e = hipMemcpyAsync(sc, c->sc, sizeof(*sc), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->err = std::string("fsne_renumber: scalars: ") + hipGetErrorString(e);
+    return FSNE_EHIP;
+  }
+  return FSNE_OK;
+}
+
+fsne_status hip_error(fsne_ctx* c, hipError_t e, const char* where) {
+  c->err = std::string(where) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? FSNE_ENOMEM : FSNE_EHIP;
+}
+
+// Move every per-point row to its new id and map the list entries; d_new is
+// a device permutation of 0..N-1 and buf a staging area of the size
+// row_arrays reports.  The remembered rejections are cleared.
+fsne_status apply_permutation(fsne_ctx* c, const fsne::Scalars& sc, const int32_t* d_new,
+                              uint8_t* buf) {
+  hipStream_t s = c->stream;
+  const int32_t N = (int32_t)c->N;
   size_t most = 0;
-  for (const Rows& r : rows)
-    if (r.base) most = std::max(most, r.bytes * (size_t)N);
-  Scratch tmp;
-  uint8_t* buf = nullptr;
-  if ((e = tmp.get(&buf, most)) != hipSuccess) return hip_error(c, e, "fsne_renumber: staging");
-  for (const Rows& r : rows) {
+  const std::vector<RowArray> rows = row_arrays(c, sc, &most);
+  hipError_t e;
+  for (const RowArray& r : rows) {
     if (!r.base) continue;
     hipLaunchKernelGGL(k_permute_rows, dim3(grid_for((int64_t)N * r.bytes / 4 + 1)), dim3(256),
                        0, s, buf, static_cast<const uint8_t*>(r.base), d_new, N,
@@ -245,14 +270,21 @@ extern "C" fsne_status fsne_renumber(fsne_ctx* c, const int32_t* new_of_old) {
     }
     seen[(size_t)v] = 1;
   }
-  Scratch tmp;
-  int32_t* d_new = nullptr;
+  fsne::Scalars sc;
+  fsne_status st = read_scalars(c, &sc);
+  if (st != FSNE_OK) return st;
+  size_t most = 0;
+  (void)row_arrays(c, sc, &most);
+  const size_t o_new = 0, o_buf = align_up(sizeof(int32_t) * (size_t)N);
+  uint8_t* w = nullptr;
   hipError_t e;
-  if ((e = tmp.get(&d_new, sizeof(int32_t) * (size_t)N)) != hipSuccess ||
-      (e = hipMemcpyAsync(d_new, new_of_old, sizeof(int32_t) * (size_t)N,
+  if ((e = workspace(c, o_buf + most, &w)) != hipSuccess)
+    return hip_error(c, e, "fsne_renumber: workspace");
+  int32_t* d_new = reinterpret_cast<int32_t*>(w + o_new);
+  if ((e = hipMemcpyAsync(d_new, new_of_old, sizeof(int32_t) * (size_t)N,
                           hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return hip_error(c, e, "fsne_renumber: upload");
-  return apply_permutation(c, d_new);
+  return apply_permutation(c, sc, d_new, w + o_buf);
 }
 
 extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
@@ -264,22 +296,36 @@ extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
   const int32_t N = (int32_t)c->N;
   hipStream_t s = c->stream;
   Projection pr{c->d, std::min(c->d, kMaxAxes)};
-  Scratch tmp;
-  float* part = nullptr;
-  float* range = nullptr;
-  uint32_t *keys = nullptr, *keys2 = nullptr;
-  int32_t *ids = nullptr, *ids2 = nullptr, *d_new = nullptr;
-  void* sort_tmp = nullptr;
-  size_t sort_bytes = 0;
+  fsne::Scalars sc;
+  fsne_status st = read_scalars(c, &sc);
+  if (st != FSNE_OK) return st;
+  size_t most = 0;
+  (void)row_arrays(c, sc, &most);
+  // workspace: range partials, range, keys (2), ids (2), permutation, the
+  // radix sort's own space, staging for the rows
   hipError_t e;
-  if ((e = tmp.get(&part, sizeof(float) * kRedBlocks * 2 * kMaxAxes)) != hipSuccess ||
-      (e = tmp.get(&range, sizeof(float) * 2 * kMaxAxes)) != hipSuccess ||
-      (e = tmp.get(&keys, sizeof(uint32_t) * (size_t)N)) != hipSuccess ||
-      (e = tmp.get(&keys2, sizeof(uint32_t) * (size_t)N)) != hipSuccess ||
-      (e = tmp.get(&ids, sizeof(int32_t) * (size_t)N)) != hipSuccess ||
-      (e = tmp.get(&ids2, sizeof(int32_t) * (size_t)N)) != hipSuccess ||
-      (e = tmp.get(&d_new, sizeof(int32_t) * (size_t)N)) != hipSuccess)
-    return hip_error(c, e, "fsne_reorder: scratch");
+  size_t sort_bytes = 0;
+  if ((e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t*)nullptr,
+                                              (uint32_t*)nullptr, (const int32_t*)nullptr,
+                                              (int32_t*)nullptr, N, 0, 30, s)) != hipSuccess)
+    return hip_error(c, e, "fsne_reorder: sort size");
+  const size_t n4 = align_up(sizeof(int32_t) * (size_t)N);
+  const size_t o_part = 0, o_range = align_up(sizeof(float) * kRedBlocks * 2 * kMaxAxes);
+  const size_t o_keys = o_range + align_up(sizeof(float) * 2 * kMaxAxes);
+  const size_t o_keys2 = o_keys + n4, o_ids = o_keys2 + n4, o_ids2 = o_ids + n4;
+  const size_t o_new = o_ids2 + n4, o_sort = o_new + n4;
+  const size_t o_buf = o_sort + align_up(sort_bytes);
+  uint8_t* w = nullptr;
+  if ((e = workspace(c, o_buf + most, &w)) != hipSuccess)
+    return hip_error(c, e, "fsne_reorder: workspace");
+  float* part = reinterpret_cast<float*>(w + o_part);
+  float* range = reinterpret_cast<float*>(w + o_range);
+  uint32_t* keys = reinterpret_cast<uint32_t*>(w + o_keys);
+  uint32_t* keys2 = reinterpret_cast<uint32_t*>(w + o_keys2);
+  int32_t* ids = reinterpret_cast<int32_t*>(w + o_ids);
+  int32_t* ids2 = reinterpret_cast<int32_t*>(w + o_ids2);
+  int32_t* d_new = reinterpret_cast<int32_t*>(w + o_new);
+  void* sort_tmp = w + o_sort;
   hipLaunchKernelGGL(k_proj_range, dim3(kRedBlocks), dim3(256), 0, s, c->Y, N, c->DP, pr, part);
   std::vector<float> hp((size_t)kRedBlocks * 2 * kMaxAxes);
   if ((e = hipGetLastError()) != hipSuccess ||
@@ -305,15 +351,12 @@ extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
     return hip_error(c, e, "fsne_reorder: range upload");
   hipLaunchKernelGGL(k_morton, dim3(gn), dim3(256), 0, s, c->Y, N, c->DP, pr, range, keys, ids);
   if ((e = hipGetLastError()) != hipSuccess ||
-      (e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, keys, keys2, ids, ids2, N, 0,
-                                              30, s)) != hipSuccess ||
-      (e = tmp.get(&sort_tmp, sort_bytes)) != hipSuccess ||
       (e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, keys, keys2, ids, ids2, N, 0,
                                               30, s)) != hipSuccess)
     return hip_error(c, e, "fsne_reorder: sort");
   hipLaunchKernelGGL(k_invert, dim3(gn), dim3(256), 0, s, ids2, N, d_new);
   if ((e = hipGetLastError()) != hipSuccess) return hip_error(c, e, "fsne_reorder: invert");
-  const fsne_status st = apply_permutation(c, d_new);
+  st = apply_permutation(c, sc, d_new, w + o_buf);
   if (st != FSNE_OK) return st;
   if (new_of_old &&
       ((e = hipMemcpy(new_of_old, d_new, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToHost)) !=
