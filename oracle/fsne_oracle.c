@@ -7,8 +7,8 @@
  * order on one thread.
  *
  * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off -shared -fPIC
- * (contraction stays off so the single-precision decisions below are exactly
- * the stated operation sequence).
+ * (contraction stays off so that the one single-precision decision, the
+ * clustering's eps test, is exactly the stated operation sequence).
  */
 #include "fsne_oracle.h"
 
@@ -72,33 +72,40 @@ static int64_t uniform_other(uint32_t u, int64_t i, int64_t N)
 
 /* ------------------------------------------------------------------------ */
 /* Refinement probability (Sec. 3, paragraph on skipping the HD refinement): */
-/* p = p_min + (1 - p_min) E with the paper's p_min = 0.05.  The comparison  */
-/* of a 32-bit draw with floor(p 2^32) is taken in single precision, which   */
-/* is how the GPU takes it.                                                  */
+/* p = p_min + (1 - p_min) E with the paper's p_min = 0.05.  The iteration   */
+/* refines when its 32-bit draw u satisfies u < p 2^32, compared in double   */
+/* (u is an integer below 2^32 and scaling p by 2^32 is exact).              */
 /* ------------------------------------------------------------------------ */
-int fsneo_coin(float E, uint32_t t, uint64_t seed, int32_t hd_mode, float p_min)
+static uint32_t coin_draw(uint32_t t, uint64_t seed)
+{
+    uint32_t u[4];
+    draw(seed, 0xFFFFFFFFu, t, FSNEO_S_COIN, 0, u);
+    return u[0];
+}
+
+int fsneo_coin(double E, uint32_t t, uint64_t seed, int32_t hd_mode, double p_min)
 {
     if (hd_mode == 1) return 1;
     if (hd_mode == 2) return 0;
-    volatile float one_minus = 1.0f - p_min;
-    volatile float prod = one_minus * E;
-    volatile float p = p_min + prod;
-    if (!(p < 1.0f)) return 1;
-    if (!(p > 0.0f)) return 0;
-    uint32_t thr = (uint32_t)(p * 4294967296.0f);
-    uint32_t u[4];
-    draw(seed, 0xFFFFFFFFu, t, FSNEO_S_COIN, 0, u);
-    return u[0] < thr;
+    double p = p_min + (1.0 - p_min) * E;
+    if (p >= 1.0) return 1;
+    if (p <= 0.0) return 0;
+    return (double)coin_draw(t, seed) < p * 4294967296.0;
 }
 
-/* E <- (1 - lambda) E + lambda N_new / N, in single precision. */
-float fsneo_E_next(float E, int64_t n_new, int64_t N, float lam)
+/* u - p 2^32 for iteration t: how far the draw lies from the threshold (a  */
+/* single-precision implementation of the same rule can only decide          */
+/* otherwise when this is within its rounding of p 2^32).                    */
+double fsneo_coin_margin(double E, uint32_t t, uint64_t seed, double p_min)
 {
-    volatile float frac = (float)n_new / (float)N;
-    volatile float a = (1.0f - lam) * E;
-    volatile float b = lam * frac;
-    volatile float e = a + b;
-    return e;
+    double p = p_min + (1.0 - p_min) * E;
+    return (double)coin_draw(t, seed) - p * 4294967296.0;
+}
+
+/* E <- (1 - lambda) E + lambda N_new / N. */
+double fsneo_E_next(double E, int64_t n_new, int64_t N, double lam)
+{
+    return (1.0 - lam) * E + lam * (double)n_new / (double)N;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -154,23 +161,6 @@ static double state_dist2(const fsneo_state *S, int64_t a, int64_t b)
     return fsneo_hd_dist2_metric(S->X, S->xdtype, S->D, S->metric, a, b);
 }
 
-/* LD squared distance used to decide LD list membership.  The decision is  */
-/* taken in single precision on the single-precision coordinates: the       */
-/* squares (y_jc - y_ic)^2, each rounded, are summed pairwise, leaves in     */
-/* index order, as a balanced binary tree over 64 leaves (components beyond */
-/* d are zero): adjacent pairs are added level by level, each sum rounded.  */
-static float ld_dist2_decision(const double *Y, int32_t d, int64_t i, int64_t j)
-{
-    volatile float t[64];
-    for (int32_t c = 0; c < 64; ++c) {
-        volatile float diff = c < d ? (float)Y[j * d + c] - (float)Y[i * d + c] : 0.0f;
-        t[c] = diff * diff;
-    }
-    for (int w = 64; w > 1; w /= 2)
-        for (int k = 0; k < w / 2; ++k) t[k] = t[2 * k] + t[2 * k + 1];
-    return t[0];
-}
-
 /* Squared distance of the clustering's eps test: single precision on the  */
 /* single-precision coordinates, summed over c in index order, each         */
 /* operation rounded, no fused multiply-add.                                */
@@ -185,6 +175,8 @@ static float cluster_dist2(const double *Y, int32_t d, int64_t i, int64_t j)
     return acc;
 }
 
+/* Squared LD distance |y_i - y_j|^2 (the distance of eq. (4)), in double.  */
+/* It both decides LD list membership and enters the kernel.                */
 static double ld_dist2(const double *Y, int32_t d, int64_t i, int64_t j)
 {
     double s = 0.0;
@@ -467,11 +459,11 @@ static void ld_point(const fsneo_state *S, const fsneo_hp *hp, int64_t i, uint32
     entry e[64 + FSNEO_C];
     for (int32_t k = 0; k < K; ++k) {
         e[k].idx = S->ld_idx[i * K + k];
-        e[k].key = (double)ld_dist2_decision(S->Y, d, i, e[k].idx);
+        e[k].key = ld_dist2(S->Y, d, i, e[k].idx);
     }
     for (int c = 0; c < nc; ++c) {
         e[K + c].idx = cand[c];
-        e[K + c].key = (double)ld_dist2_decision(S->Y, d, i, cand[c]);
+        e[K + c].key = ld_dist2(S->Y, d, i, cand[c]);
     }
     sort_entries(e, K + nc);
     for (int32_t k = 0; k < K; ++k) ld_out[k] = (int32_t)e[k].idx;
@@ -590,9 +582,36 @@ int fsneo_init(fsneo_state *S, const fsneo_hp *hp)
     }
     all_psym(S);
     for (int64_t k = 0; k < N * S->d; ++k) S->V[k] = 0.0;
-    *S->E = 1.0f;
+    *S->E = 1.0;
     *S->t = 0;
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The end of the HD phase (Sec. 3, flags paragraph; eq. (1)): the points   */
+/* whose list changed (flag set) are recalibrated, then P is recomputed for */
+/* every point from the new lists and records.                              */
+/* ------------------------------------------------------------------------ */
+void fsneo_hd_finish(fsneo_state *S, const fsneo_hp *hp)
+{
+    const int64_t N = S->N;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < N; ++i)
+        if (S->flags[i]) calibrate_point(S, i, hp->perplexity);
+    all_psym(S);
+}
+
+/* The LD phase of every point (LD refinement at the current Y and gradient */
+/* partials) against given HD lists and affinities of this iteration.       */
+void fsneo_ld_phase(const fsneo_state *S, const fsneo_hp *hp, uint32_t t, const int32_t *hd_next,
+                    const double *P_next, int32_t *ld_out, double *A, double *R, double *Zh)
+{
+    const int64_t N = S->N;
+    const int32_t Kl = S->K_ld, d = S->d;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < N; ++i)
+        fsneo_ld_refine_grad_point(S, hp, i, t, hd_next, P_next, ld_out + i * Kl, A + i * d,
+                                   R + i * d, Zh + i);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -627,11 +646,8 @@ int fsneo_step(fsneo_state *S, const fsneo_hp *hp, fsneo_stats *st, double *A_ou
         memcpy(S->hd_d2, nd, sizeof(double) * N * Kh);
         free(ni);
         free(nd);
-#pragma omp parallel for schedule(dynamic, 256)
-        for (int64_t i = 0; i < N; ++i)
-            if (S->flags[i]) calibrate_point(S, i, hp->perplexity);
         for (int64_t i = 0; i < N; ++i) n_new += S->flags[i];
-        all_psym(S);
+        fsneo_hd_finish(S, hp);
     }
     int32_t *nl = malloc(sizeof(int32_t) * N * Kl);
     double *A = malloc(sizeof(double) * N * d);
@@ -644,10 +660,7 @@ int fsneo_step(fsneo_state *S, const fsneo_hp *hp, fsneo_stats *st, double *A_ou
         free(Zh);
         return -2;
     }
-#pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t i = 0; i < N; ++i)
-        fsneo_ld_refine_grad_point(S, hp, i, t, S->hd_idx, S->P, nl + i * Kl, A + i * d,
-                                   R + i * d, Zh + i);
+    fsneo_ld_phase(S, hp, t, S->hd_idx, S->P, nl, A, R, Zh);
     double Z = 0.0;
     for (int64_t i = 0; i < N; ++i) Z += Zh[i];
     for (int64_t k = 0; k < N * d; ++k) {
@@ -688,6 +701,15 @@ typedef struct {
     double rec[4];
 } point_next;
 
+/* Planted mistakes, compiled in only by the test which shows that comparing */
+/* fsneo_point_step with fsneo_step catches them (0: none).  1: a changed    */
+/* neighbour keeps its old record; 2: the LD phase reads the neighbours'     */
+/* HD rows from before the refinement; 3: the affinities test membership in  */
+/* the neighbours' old rows; 4: i's affinities use its own old record.     */
+#ifndef FSNEO_PLANT
+#define FSNEO_PLANT 0
+#endif
+
 /* HD row and record of point j after the HD phase; returns j's flag. */
 static uint8_t next_of(const fsneo_state *S, const fsneo_hp *hp, int64_t j, int32_t fired,
                        point_next *pn)
@@ -700,7 +722,7 @@ static uint8_t next_of(const fsneo_state *S, const fsneo_hp *hp, int64_t j, int3
         memcpy(pn->idx, S->hd_idx + j * K, sizeof(int32_t) * K);
         memcpy(pn->d2, S->hd_d2 + j * K, sizeof(double) * K);
     }
-    if (ch) {
+    if (ch && FSNEO_PLANT != 1) {
         fsneo_calibrate(pn->d2, K, hp->perplexity, pn->rec);
     } else {
         pn->rec[0] = S->beta[j];
@@ -731,17 +753,21 @@ int fsneo_point_step(const fsneo_state *S, const fsneo_hp *hp, int64_t i, int32_
         const int32_t *rows_j[64] = {0};
         const double *rec_j[64] = {0};
         for (int32_t k = 0; k < K; ++k) {
-            rows_j[k] = pn[1 + k].idx;
+            rows_j[k] = FSNEO_PLANT == 3 ? S->hd_idx + (int64_t)pn[0].idx[k] * K : pn[1 + k].idx;
             rec_j[k] = pn[1 + k].rec;
         }
-        psym_row_from(i, pn[0].idx, pn[0].d2, K, N, pn[0].rec, rows_j, rec_j, P_out);
+        double rec_old[4] = {S->beta[i], S->m[i], S->r[i], S->invS[i]};
+        psym_row_from(i, pn[0].idx, pn[0].d2, K, N, FSNEO_PLANT == 4 ? rec_old : pn[0].rec,
+                      rows_j, rec_j, P_out);
     }
     /* the LD phase of i reads the next HD rows of i and of its members only */
     ids[0] = i;
     memcpy(rows, pn[0].idx, sizeof(int32_t) * K);
     for (int32_t k = 0; k < K; ++k) {
         ids[1 + k] = pn[0].idx[k];
-        memcpy(rows + (int64_t)(1 + k) * K, pn[1 + k].idx, sizeof(int32_t) * K);
+        memcpy(rows + (int64_t)(1 + k) * K,
+               FSNEO_PLANT == 2 ? S->hd_idx + (int64_t)pn[0].idx[k] * K : pn[1 + k].idx,
+               sizeof(int32_t) * K);
     }
     rows_t H = {NULL, K, K + 1, ids, rows};
     ld_point(S, hp, i, *S->t, &H, P_out, ld_out, A, R, Zh);
@@ -857,7 +883,7 @@ int fsneo_set_metric(fsneo_state *S, const fsneo_hp *hp, int32_t metric)
         calibrate_point(S, i, hp->perplexity);
     }
     all_psym(S);
-    *S->E = 1.0f;
+    *S->E = 1.0;
     return 0;
 }
 

@@ -47,7 +47,7 @@ typedef struct {
     double *invS;       /* N: 1 / sum_k exp(-beta_i (d2_ik - m_i))             */
     double *P;          /* N x K_hd symmetrised affinities aligned with hd_idx */
     uint8_t *flags;     /* N: 1 if the last HD refinement changed row i        */
-    float *E;           /* smoothed fraction of points that gained neighbours  */
+    double *E;          /* smoothed fraction of points that gained neighbours  */
     uint32_t *t;        /* iteration counter                                   */
     int32_t metric;     /* HD distance: 0 squared Euclidean, 1 angular (the    */
                         /* squared Euclidean distance of the unit rows)        */
@@ -57,21 +57,22 @@ typedef struct {
     double alpha, perplexity, lr, momentum, attr, rep;
     int32_t n_neg;
     int32_t hd_mode;    /* 0 auto (coin), 1 always, 2 never                    */
-    float e_smooth;     /* smoothing weight lambda of E                        */
-    float p_min;        /* floor of the refinement probability                 */
+    double e_smooth;    /* smoothing weight lambda of E                        */
+    double p_min;       /* floor of the refinement probability                 */
 } fsneo_hp;
 
 typedef struct {
     int32_t fired;
     int64_t n_new;
     double Z;
-    float E;            /* E after the step                                    */
+    double E;           /* E after the step                                    */
     uint32_t t;         /* t after the step                                    */
 } fsneo_stats;
 
 void fsneo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
-int fsneo_coin(float E, uint32_t t, uint64_t seed, int32_t hd_mode, float p_min);
-float fsneo_E_next(float E, int64_t n_new, int64_t N, float lam);
+int fsneo_coin(double E, uint32_t t, uint64_t seed, int32_t hd_mode, double p_min);
+double fsneo_coin_margin(double E, uint32_t t, uint64_t seed, double p_min);
+double fsneo_E_next(double E, int64_t n_new, int64_t N, double lam);
 int fsneo_calibrate(const double *d2, int32_t K, double perplexity, double out[4]);
 double fsneo_hd_dist2(const void *X, int32_t xdtype, int32_t D, int64_t a, int64_t b);
 double fsneo_hd_dist2_metric(const void *X, int32_t xdtype, int32_t D, int32_t metric,
@@ -86,6 +87,9 @@ void fsneo_psym_row(const fsneo_state *S, int64_t i, double *out);
 void fsneo_ld_refine_grad_point(const fsneo_state *S, const fsneo_hp *hp, int64_t i,
                                 uint32_t t, const int32_t *hd_next, const double *P_next,
                                 int32_t *ld_out, double *A, double *R, double *Zh);
+void fsneo_hd_finish(fsneo_state *S, const fsneo_hp *hp);
+void fsneo_ld_phase(const fsneo_state *S, const fsneo_hp *hp, uint32_t t, const int32_t *hd_next,
+                    const double *P_next, int32_t *ld_out, double *A, double *R, double *Zh);
 int fsneo_point_step(const fsneo_state *S, const fsneo_hp *hp, int64_t i, int32_t fired,
                      int32_t *hd_idx_out, double *hd_d2_out, uint8_t *flag_out,
                      double rec_out[4], double *P_out, int32_t *ld_out,

@@ -6,6 +6,7 @@ in the library's single-precision layout, for injection into the HIP path.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -20,17 +21,18 @@ __all__ = ["build_oracle", "lib", "Hyper", "OracleState", "philox4x32_10", "coin
            "num_threads"]
 
 
-def build_oracle(force: bool = True) -> str:
-    """Compile the C oracle with gcc into oracle/liboracle_fsne.so."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
+def build_oracle(force: bool = True, path: str = _LIB_PATH, defines=()) -> str:
+    """Compile the C oracle with gcc into oracle/liboracle_fsne.so (or into
+    path, with extra -D definitions: the planted-mistake builds of the tests)."""
+    if not force and os.path.exists(path):
+        return path
     srcs = [os.path.join(_HERE, f) for f in ("fsne_oracle.c", "fsne_mlp_oracle.c")]
-    tmp = _LIB_PATH + ".tmp"
+    tmp = path + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-Wall", "-shared",
-           "-fPIC", "-o", tmp, *srcs, "-lm"]
+           "-fPIC", *[f"-D{d}" for d in defines], "-o", tmp, *srcs, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, path)
+    return path
 
 
 class _State(C.Structure):
@@ -46,8 +48,8 @@ class _State(C.Structure):
 class _Hp(C.Structure):
     _fields_ = [("alpha", C.c_double), ("perplexity", C.c_double), ("lr", C.c_double),
                 ("momentum", C.c_double), ("attr", C.c_double), ("rep", C.c_double),
-                ("n_neg", C.c_int32), ("hd_mode", C.c_int32), ("e_smooth", C.c_float),
-                ("p_min", C.c_float)]
+                ("n_neg", C.c_int32), ("hd_mode", C.c_int32), ("e_smooth", C.c_double),
+                ("p_min", C.c_double)]
 
 
 class _MlpDims(C.Structure):
@@ -56,7 +58,7 @@ class _MlpDims(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("fired", C.c_int32), ("n_new", C.c_int64), ("Z", C.c_double),
-                ("E", C.c_float), ("t", C.c_uint32)]
+                ("E", C.c_double), ("t", C.c_uint32)]
 
 
 _lib = None
@@ -67,62 +69,86 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build_oracle()
-        L = C.CDLL(_LIB_PATH)
-        P = C.c_void_p
-        L.fsneo_philox4x32_10.argtypes = [P, P, P]
-        L.fsneo_coin.argtypes = [C.c_float, C.c_uint32, C.c_uint64, C.c_int32, C.c_float]
-        L.fsneo_coin.restype = C.c_int
-        L.fsneo_E_next.argtypes = [C.c_float, C.c_int64, C.c_int64, C.c_float]
-        L.fsneo_E_next.restype = C.c_float
-        L.fsneo_calibrate.argtypes = [P, C.c_int32, C.c_double, P]
-        L.fsneo_calibrate.restype = C.c_int
-        L.fsneo_hd_dist2.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64]
-        L.fsneo_hd_dist2.restype = C.c_double
-        L.fsneo_hd_dist2_metric.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
-                                            C.c_int64]
-        L.fsneo_hd_dist2_metric.restype = C.c_double
-        L.fsneo_set_metric.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int32]
-        L.fsneo_set_metric.restype = C.c_int
-        L.fsneo_init.argtypes = [C.POINTER(_State), C.POINTER(_Hp)]
-        L.fsneo_init.restype = C.c_int
-        L.fsneo_step.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.POINTER(_Stats), P, P, P]
-        L.fsneo_step.restype = C.c_int
-        L.fsneo_hd_refine_point.argtypes = [C.POINTER(_State), C.c_int64, C.c_uint32, P, P, P]
-        L.fsneo_psym_row.argtypes = [C.POINTER(_State), C.c_int64, P]
-        L.fsneo_ld_refine_grad_point.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int64,
-                                                 C.c_uint32, P, P, P, P, P, P]
-        L.fsneo_point_step.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int64, C.c_int32,
-                                       P, P, P, P, P, P, P, P, P]
-        L.fsneo_point_step.restype = C.c_int
-        L.fsneo_exact_P.argtypes = [P, C.c_int32, C.c_int64, C.c_int32, C.c_double, P, P]
-        L.fsneo_exact_cost.argtypes = [P, P, C.c_int64, C.c_int32, C.c_double]
-        L.fsneo_exact_cost.restype = C.c_double
-        L.fsneo_exact_grad.argtypes = [P, P, C.c_int64, C.c_int32, C.c_double, P]
-        L.fsneo_knn_exact.argtypes = [P, C.c_int32, C.c_int64, C.c_int32, P, C.c_int64,
-                                      C.c_int32, P, P]
-        L.fsneo_insert.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int64, P]
-        L.fsneo_insert.restype = C.c_int
-        L.fsneo_drift.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P, C.c_int64, P]
-        L.fsneo_drift.restype = C.c_int
-        L.fsneo_num_threads.restype = C.c_int
-        L.fsneo_jump_start.argtypes = [C.POINTER(_State), C.c_int32, C.c_double]
-        L.fsneo_jump_start.restype = C.c_int
-        L.fsneo_delete_fix.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P]
-        L.fsneo_delete_fix.restype = None
-        L.fsneo_cluster.argtypes = [C.POINTER(_State), C.c_float, C.c_int32, P]
-        L.fsneo_cluster.restype = C.c_int32
-        L.fsneo_mlp_nparams.argtypes = [C.POINTER(_MlpDims)]
-        L.fsneo_mlp_nparams.restype = C.c_int64
-        L.fsneo_mlp_init.argtypes = [C.POINTER(_MlpDims), C.c_uint64, P]
-        L.fsneo_mlp_forward.argtypes = [C.POINTER(_MlpDims), P, P, C.c_int32, C.c_int64,
-                                        C.c_int32, P]
-        L.fsneo_mlp_loss_grad.argtypes = [C.POINTER(_MlpDims), P, P, C.c_int32, P, C.c_int64,
-                                          C.c_int32, P]
-        L.fsneo_mlp_loss_grad.restype = C.c_double
-        L.fsneo_mlp_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int64, C.c_double, C.c_double,
-                                     C.c_double, C.c_double]
-        _lib = L
+        _lib = _declare(C.CDLL(_LIB_PATH))
     return _lib
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Route every oracle call through another build of the oracle (a
+    planted-mistake build in the tests) for the duration of the block."""
+    global _lib
+    saved = lib()
+    _lib = _declare(C.CDLL(path))
+    try:
+        yield _lib
+    finally:
+        _lib = saved
+
+
+def _declare(L):
+    """Argument and result types of the oracle's C functions."""
+    P = C.c_void_p
+    L.fsneo_philox4x32_10.argtypes = [P, P, P]
+    L.fsneo_coin.argtypes = [C.c_double, C.c_uint32, C.c_uint64, C.c_int32, C.c_double]
+    L.fsneo_coin.restype = C.c_int
+    L.fsneo_coin_margin.argtypes = [C.c_double, C.c_uint32, C.c_uint64, C.c_double]
+    L.fsneo_coin_margin.restype = C.c_double
+    L.fsneo_E_next.argtypes = [C.c_double, C.c_int64, C.c_int64, C.c_double]
+    L.fsneo_E_next.restype = C.c_double
+    L.fsneo_calibrate.argtypes = [P, C.c_int32, C.c_double, P]
+    L.fsneo_calibrate.restype = C.c_int
+    L.fsneo_hd_dist2.argtypes = [P, C.c_int32, C.c_int32, C.c_int64, C.c_int64]
+    L.fsneo_hd_dist2.restype = C.c_double
+    L.fsneo_hd_dist2_metric.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
+                                        C.c_int64]
+    L.fsneo_hd_dist2_metric.restype = C.c_double
+    L.fsneo_set_metric.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int32]
+    L.fsneo_set_metric.restype = C.c_int
+    L.fsneo_init.argtypes = [C.POINTER(_State), C.POINTER(_Hp)]
+    L.fsneo_init.restype = C.c_int
+    L.fsneo_step.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.POINTER(_Stats), P, P, P]
+    L.fsneo_step.restype = C.c_int
+    L.fsneo_hd_refine_point.argtypes = [C.POINTER(_State), C.c_int64, C.c_uint32, P, P, P]
+    L.fsneo_psym_row.argtypes = [C.POINTER(_State), C.c_int64, P]
+    L.fsneo_ld_refine_grad_point.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int64,
+                                             C.c_uint32, P, P, P, P, P, P]
+    L.fsneo_hd_finish.argtypes = [C.POINTER(_State), C.POINTER(_Hp)]
+    L.fsneo_hd_finish.restype = None
+    L.fsneo_ld_phase.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_uint32, P, P, P, P,
+                                 P, P]
+    L.fsneo_ld_phase.restype = None
+    L.fsneo_point_step.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int64, C.c_int32,
+                                   P, P, P, P, P, P, P, P, P]
+    L.fsneo_point_step.restype = C.c_int
+    L.fsneo_exact_P.argtypes = [P, C.c_int32, C.c_int64, C.c_int32, C.c_double, P, P]
+    L.fsneo_exact_cost.argtypes = [P, P, C.c_int64, C.c_int32, C.c_double]
+    L.fsneo_exact_cost.restype = C.c_double
+    L.fsneo_exact_grad.argtypes = [P, P, C.c_int64, C.c_int32, C.c_double, P]
+    L.fsneo_knn_exact.argtypes = [P, C.c_int32, C.c_int64, C.c_int32, P, C.c_int64,
+                                  C.c_int32, P, P]
+    L.fsneo_insert.argtypes = [C.POINTER(_State), C.POINTER(_Hp), C.c_int64, P]
+    L.fsneo_insert.restype = C.c_int
+    L.fsneo_drift.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P, C.c_int64, P]
+    L.fsneo_drift.restype = C.c_int
+    L.fsneo_num_threads.restype = C.c_int
+    L.fsneo_jump_start.argtypes = [C.POINTER(_State), C.c_int32, C.c_double]
+    L.fsneo_jump_start.restype = C.c_int
+    L.fsneo_delete_fix.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P]
+    L.fsneo_delete_fix.restype = None
+    L.fsneo_cluster.argtypes = [C.POINTER(_State), C.c_float, C.c_int32, P]
+    L.fsneo_cluster.restype = C.c_int32
+    L.fsneo_mlp_nparams.argtypes = [C.POINTER(_MlpDims)]
+    L.fsneo_mlp_nparams.restype = C.c_int64
+    L.fsneo_mlp_init.argtypes = [C.POINTER(_MlpDims), C.c_uint64, P]
+    L.fsneo_mlp_forward.argtypes = [C.POINTER(_MlpDims), P, P, C.c_int32, C.c_int64,
+                                    C.c_int32, P]
+    L.fsneo_mlp_loss_grad.argtypes = [C.POINTER(_MlpDims), P, P, C.c_int32, P, C.c_int64,
+                                      C.c_int32, P]
+    L.fsneo_mlp_loss_grad.restype = C.c_double
+    L.fsneo_mlp_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int64, C.c_double, C.c_double,
+                                 C.c_double, C.c_double]
+    return L
 
 
 def _p(a: np.ndarray):
@@ -188,7 +214,7 @@ class OracleState:
         self.invS = np.zeros(cap)
         self.P = np.zeros((cap, K_hd))
         self.flags = np.zeros(cap, dtype=np.uint8)
-        self.E = np.ones(1, dtype=np.float32)
+        self.E = np.ones(1, dtype=np.float64)
         self.t = np.zeros(1, dtype=np.uint32)
         self.metric = int(metric)   # HD distance: 0 squared Euclidean, 1 angular
 
@@ -227,6 +253,55 @@ class OracleState:
             out.update(A=A, R=R, Zh=Zh)
         return out
 
+    def hd_finish(self, hp: Hyper):
+        """End of the HD phase on the current lists: recalibrate the flagged
+        points, then recompute P for every point."""
+        s = self.cstate()
+        lib().fsneo_hd_finish(C.byref(s), C.byref(hp.c()))
+
+    def ld_phase(self, hp: Hyper, hd_next, P_next, t=None):
+        """LD phase of every point (LD lists, A, R, Zh) at the current Y and LD
+        lists, against the given HD lists and affinities of the iteration."""
+        N, Kh, Kl, d = self.N, self.K_hd, self.K_ld, self.d
+        hd_next = np.ascontiguousarray(hd_next, dtype=np.int32)
+        P_next = np.ascontiguousarray(P_next, dtype=np.float64)
+        assert hd_next.shape == (N, Kh) and P_next.shape == (N, Kh)
+        ld = np.zeros((N, Kl), np.int32)
+        A = np.zeros((N, d))
+        R = np.zeros((N, d))
+        Zh = np.zeros(N)
+        s = self.cstate()
+        lib().fsneo_ld_phase(C.byref(s), C.byref(hp.c()), int(self.t[0] if t is None else t),
+                             _p(hd_next), _p(P_next), _p(ld), _p(A), _p(R), _p(Zh))
+        return ld, A, R, Zh
+
+    def round_to_f32(self):
+        """Round the embedding and its velocity to single precision, so that
+        the oracle and a single-precision implementation start an iteration
+        from the same numbers."""
+        N = self.N
+        self.Y[:N] = self.Y[:N].astype(np.float32)
+        self.V[:N] = self.V[:N].astype(np.float32)
+        return self
+
+    @classmethod
+    def from_gpu_state(cls, X, g, d, K_hd, K_ld, seed, metric=0):
+        """An oracle state holding a state read from the library (single
+        precision values widened to double)."""
+        N = g["Y"].shape[0]
+        S = cls(X[:N], d, K_hd, K_ld, seed, g["Y"].astype(np.float64), metric=metric)
+        S.V[:N] = g["V"]
+        S.hd_idx[:N] = g["hd_idx"]
+        S.hd_d2[:N] = g["hd_d2"]
+        S.ld_idx[:N] = g["ld_idx"]
+        rec = g["rec"].astype(np.float64)
+        S.beta[:N], S.m[:N], S.r[:N], S.invS[:N] = rec[:, 0], rec[:, 1], rec[:, 2], rec[:, 3]
+        S.P[:N] = g["P"]
+        S.flags[:N] = g["flags"] & 1
+        S.E[0] = g["E"]
+        S.t[0] = g["t"]
+        return S
+
     def point_step(self, hp: Hyper, i: int, fired: int):
         """Next-iteration outputs of point i alone (sampled checks at large N)."""
         K, Kl, d = self.K_hd, self.K_ld, self.d
@@ -257,9 +332,13 @@ class OracleState:
                                     _p(hi), _p(hd), _p(ch))
         return hi, hd, int(ch[0])
 
-    def ld_refine_grad_point(self, hp: Hyper, i, t=None):
-        """LD phase of point i against the current HD lists and P (no HD phase)."""
+    def ld_refine_grad_point(self, hp: Hyper, i, t=None, hd_next=None, P_next=None):
+        """LD phase of point i against the current HD lists and P (no HD
+        phase), or against the given full HD lists and affinities."""
         Kl, d = self.K_ld, self.d
+        hd_next = self.hd_idx if hd_next is None else np.ascontiguousarray(hd_next, np.int32)
+        P_next = self.P if P_next is None else np.ascontiguousarray(P_next, np.float64)
+        assert hd_next.shape[0] >= self.N and P_next.shape[0] >= self.N
         ld = np.zeros(Kl, np.int32)
         A = np.zeros(d)
         R = np.zeros(d)
@@ -267,7 +346,7 @@ class OracleState:
         s = self.cstate()
         lib().fsneo_ld_refine_grad_point(C.byref(s), C.byref(hp.c()), int(i),
                                          int(self.t[0] if t is None else t),
-                                         _p(self.hd_idx), _p(self.P), _p(ld), _p(A), _p(R),
+                                         _p(hd_next), _p(P_next), _p(ld), _p(A), _p(R),
                                          _p(Zh))
         return ld, A, R, float(Zh[0])
 
@@ -390,6 +469,11 @@ def philox4x32_10(ctr, key):
 
 def coin(E, t, seed, hd_mode=0, p_min=0.05):
     return lib().fsneo_coin(float(E), int(t), int(seed), int(hd_mode), float(p_min))
+
+
+def coin_margin(E, t, seed, p_min=0.05):
+    """u - p 2^32 of iteration t's draw (negative: the coin fires)."""
+    return lib().fsneo_coin_margin(float(E), int(t), int(seed), float(p_min))
 
 
 def E_next(E, n_new, N, lam=0.1):

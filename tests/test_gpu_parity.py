@@ -9,7 +9,7 @@ import pytest
 
 from inputs.generators import (blobs, f32_to_bf16_bits, image_like, manifolds, y_init,
                                zipf_mixture)
-from tests.parity import compare_hd_rows, hd_tie_tol, rel_l2
+from tests.parity import check_injected_step, compare_hd_rows, hd_tie_tol, rel_l2
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
 
@@ -57,16 +57,15 @@ WORKLOADS = {
     # well separated at this D)
     # At D = 4096 the tie tolerance is 4e-6 relative, so a few rows differ at
     # ties, and with K_hd = N / 5 each such row sits in ~64 other points'
-    # lists: the share of points whose neighbourhood matches exactly (compared
-    # element by element) is lower; every other point is checked for validity.
+    # lists; the phase-wise checks still cover every point.
     "max_f32_320": lambda: (manifolds(n_manifolds=5, per_manifold=64, D=4096, k=4,
                                       noise=0.005, seed=1009)[0],
                             dict(d=64, K_hd=64, K_ld=64, n_neg=64, alpha=1.0, perplexity=20.0,
-                                 tie_rows=8, min_clean=0.3, min_clean_p=0.6)),
+                                 tie_rows=8)),
     "max_bf16_300": lambda: (f32_to_bf16_bits(manifolds(n_manifolds=5, per_manifold=60, D=2048,
                                                         k=4, noise=0.005, seed=1010)[0]),
                              dict(d=64, K_hd=64, K_ld=64, n_neg=64, alpha=0.7,
-                                  perplexity=15.0, tie_rows=8, min_clean=0.3, min_clean_p=0.6)),
+                                  perplexity=15.0, tie_rows=8)),
     # D with no vector width: one element per lane, several chunks per lane
     "odd_d1023_260": lambda: (manifolds(n_manifolds=4, per_manifold=65, D=1023, k=3,
                                         noise=0.005, seed=1011)[0],
@@ -140,49 +139,25 @@ def test_init_matches_oracle(oracle_lib, fsne_lib, name):
 @pytest.mark.parametrize("name", list(WORKLOADS))
 @pytest.mark.parametrize("hd_mode", [1, 0])
 def test_step_matches_oracle_with_injection(oracle_lib, fsne_lib, name, hd_mode):
+    """Six iterations, each from the oracle's state injected into the GPU and
+    compared phase by phase over every point (tests/parity.py)."""
     O, F = oracle_lib, fsne_lib
     X, c, S, emb, hp_o, hp_g = _setup(O, F, name, hd_mode=hd_mode)
     bf16 = X.dtype == np.uint16
-    d = c["d"]
     fired_seen = set()
     n_fired, r0 = 0, emb.stats()["hd_refinements"]
     for it in range(6):
-        emb.set_state(S.as_gpu_state())
-        Y0 = S.live("Y").copy()
-        Y0f = Y0.astype(np.float32).astype(np.float64)
-        out = S.step(hp_o, want_partials=True)
-        emb.step(1)
+        g, out = check_injected_step(O, S, emb, hp_o, lambda g, S: _check_hd(X, c, g, S, bf16),
+                                     tie_rows=c.get("tie_rows"))
         st = emb.stats()
-        assert st["last_fired"] == out["fired"]
-        fired_seen.add(out["fired"])
-        n_fired += int(out["fired"])
+        fired_seen.add(st["last_fired"])
+        n_fired += int(st["last_fired"])
         assert st["hd_refinements"] - r0 == n_fired
-        g = emb.state()
-        assert g["t"] == out["t"] and g["E"] == np.float32(out["E"])
-        same = _check_hd(X, c, g, S, bf16)
-        if out["fired"]:
-            assert np.array_equal(g["flags"][same], S.live("flags")[same])
-            assert abs(st["n_new"] - out["n_new"]) <= (~same).sum()
-        cleanP = _clean_affinity(S, g["hd_idx"], same)
-        assert cleanP.mean() > c.get("min_clean_p", 0.97)
-        assert rel_l2(g["P"][cleanP], S.live("P")[cleanP]) < 1e-4
-        clean = _clean_points(S, same)
-        assert clean.mean() > c.get("min_clean", 0.8)
-        ld_same = np.all(g["ld_idx"] == S.live("ld_idx"), axis=1)
-        assert np.all(ld_same[clean]), np.where(clean & ~ld_same)[0][:10]
-        # every LD list, compared or not, is a valid list of distinct other points
+        # every LD list is a valid list of distinct other points
         ld = g["ld_idx"]
         assert np.all((ld >= 0) & (ld < S.N)) and not np.any(ld == np.arange(S.N)[:, None])
         assert all(len(set(r.tolist())) == ld.shape[1] for r in ld)
-        ok = clean & ld_same
-        assert rel_l2(g["A"][ok], out["A"][ok]) < 1e-4
-        assert rel_l2(g["R"][ok], out["R"][ok]) < 1e-4
-        assert np.all(np.abs(g["Zh"][ok] - out["Zh"][ok]) <= 1e-5 * out["Zh"][ok])
-        assert abs(st["Z"] - out["Z"]) <= 1e-4 * out["Z"]
-        dY_g = g["Y"].astype(np.float64) - Y0f
-        dY_o = S.live("Y") - Y0
-        assert rel_l2(dY_g[ok], dY_o[ok]) < 1e-4
-        assert g["Y"].shape == (S.N, d)
+        assert g["Y"].shape == (S.N, c["d"])
     if hd_mode == 1:
         assert fired_seen == {1}
     emb.close()

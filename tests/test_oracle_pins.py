@@ -349,13 +349,26 @@ def test_coin_probability(oracle_lib):
     assert O.coin(0.0, 3, 42, hd_mode=1) == 1 and O.coin(1.0, 3, 42, hd_mode=2) == 0
 
 
+def test_coin_margin_decides_the_coin(oracle_lib):
+    """The coin fires exactly when the draw lies below p 2^32, p = 0.05 + 0.95 E."""
+    O = oracle_lib
+    for E in (0.0, 0.013, 0.5, 0.97):
+        for t in range(300):
+            m = O.coin_margin(E, t, 42)
+            assert O.coin(E, t, 42) == (m < 0)
+            # the margin is the draw minus the threshold: recover the draw
+            u = m + (0.05 + 0.95 * E) * 2.0 ** 32
+            assert abs(u - round(u)) < 1e-6 and 0 <= round(u) < 2 ** 32
+
+
 def test_E_smoothing(oracle_lib):
     O = oracle_lib
-    assert O.E_next(1.0, 0, 100, 0.1) == np.float32(0.9)
-    e = np.float32(1.0)
-    for _ in range(200):
+    assert O.E_next(1.0, 0, 100, 0.1) == 0.9
+    assert O.E_next(0.5, 100, 100, 0.25) == 0.625
+    e = 1.0
+    for _ in range(400):
         e = O.E_next(e, 30, 100, 0.1)
-    assert abs(e - 0.3) < 1e-5                                   # fixed point N_new / N
+    assert abs(e - 0.3) < 1e-15                                  # fixed point N_new / N
 
 
 # --- determinism ----------------------------------------------------------------
