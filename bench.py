@@ -80,29 +80,47 @@ def all_slot_bytes_per_point(cfg, xbytes):
     return dict(hd_refine=hd, ld_grad=ld, update=6 * sy)
 
 
-def run_steps(emb, n, every):
-    """n iterations; with every > 0 the points are renumbered along the Morton
-    order of the embedding (fsne_reorder) before each chunk of `every`
-    iterations, the renumbering's time included."""
-    done = 0
-    while done < n:
-        k = n - done if every <= 0 else min(every, n - done)
-        if every > 0:
-            emb.reorder()
-        emb.step(k)
-        done += k
+def reorder_due(t, every, start):
+    """Whether the points are renumbered before iteration t: every `every`
+    iterations from iteration `start` on (before it the embedding has no
+    structure that a renumbering could follow)."""
+    return every > 0 and t >= start and (t - start) % every == 0
 
 
-def profiled_steps(emb, n, every, N):
-    """n single iterations with kernel timing on (renumbering as run_steps);
-    returns the kernel times and the mean HD / LD candidate rows per point."""
+def track_renumbering(orig, p):
+    """orig[k] = original id of current point k; point k becomes p[k]."""
+    if orig is not None:
+        nxt = orig.copy()
+        nxt[p] = orig
+        orig[:] = nxt
+
+
+def run_steps(emb, t0, n, every, start, orig=None):
+    """Iterations t0 .. t0+n-1, the points renumbered along the Morton order of
+    the embedding (fsne_reorder) where reorder_due says so (orig, if given,
+    follows the original id of each point)."""
+    t = t0
+    while t < t0 + n:
+        if reorder_due(t, every, start):
+            track_renumbering(orig, emb.reorder())
+        nxt = t + 1
+        while nxt < t0 + n and not reorder_due(nxt, every, start):
+            nxt += 1
+        emb.step(nxt - t)
+        t = nxt
+
+
+def profiled_steps(emb, t0, n, every, start, N, orig=None):
+    """Iterations t0 .. t0+n-1 one at a time with kernel timing on (HIP events
+    on the library's stream), renumbering as run_steps; returns the kernel
+    times and the mean HD / LD candidate rows per point."""
     import numpy as np
 
     emb.profile(True)
     hd_c, ld_c = [], []
-    for it in range(n):
-        if every > 0 and it % every == 0:
-            emb.reorder()
+    for t in range(t0, t0 + n):
+        if reorder_due(t, every, start):
+            track_renumbering(orig, emb.reorder())
         emb.step(1)
         s1 = emb.stats()
         hd_c.append(s1["hd_cand_rows"] / N)
@@ -189,7 +207,10 @@ def seconds_to(curve, target):
     return None
 
 
-def cpu_baseline(X, cfg, Y0, seed):
+def cpu_baseline(X, cfg, Y0, seed, n_one=200_000):
+    """The FP64 oracle on the host: one HD-refining iteration over all N points
+    on every thread, and the same on one thread over the first n_one rows (a
+    uniform sample: the rows are shuffled), scaled to N by the point count."""
     from oracle import oracle as O
 
     N = X.shape[0]
@@ -199,11 +220,29 @@ def cpu_baseline(X, cfg, Y0, seed):
     t0 = time.perf_counter()
     S.step(hp)
     dt = time.perf_counter() - t0
-    return {"value": round(1.0 / dt, 4), "unit": "iters/s", "cores": O.num_threads(),
+    del S
+    threads = O.num_threads()
+    O.set_num_threads(1)
+    try:
+        S1 = O.OracleState(X[:n_one], cfg["d"], cfg["K_hd"], cfg["K_ld"], seed, Y0[:n_one])
+        S1.init(hp.copy(lr=float(n_one / 12.0)))
+        t1 = time.perf_counter()
+        S1.step(hp.copy(lr=float(n_one / 12.0)))
+        dt1 = time.perf_counter() - t1
+        del S1
+    finally:
+        O.set_num_threads(threads)
+    return {"value": round(1.0 / dt, 4), "unit": "iters/s", "cores": threads,
             "kind": "oracle",
             "sample": f"1 iteration with the HD refinement on, over all N={N} points of the "
                       "same workload (FP64 C oracle, OpenMP over points), after an untimed "
-                      f"oracle init; {dt:.2f} s"}
+                      f"oracle init; {dt:.2f} s",
+            "single_thread": {"value": round(n_one / (N * dt1), 5), "unit": "iters/s",
+                              "cores": 1, "kind": "oracle",
+                              "sample": f"1 HD-refining iteration over the first {n_one} rows "
+                                        f"(a uniform sample of the shuffled workload) on one "
+                                        f"thread, {dt1:.2f} s, scaled to N={N} by the point "
+                                        "count"}}
 
 
 def feedback_run(F, args):
@@ -618,24 +657,184 @@ def scaling_run(F, args):
     return out
 
 
-def gather_probe(row_bytes, rows_per_wave, table_bytes, nwaves=1_000_000, reps=5):
-    """Random-row gather ceiling: rows/s and bytes/s at which the GPU gathers
-    rows of row_bytes from random positions of a table, one wave per point as
-    the step kernels do (the probe library, not the method)."""
-    import ctypes as C
+STEP_KERNELS = (("hd_refine", "k_hd_refine"), ("affinity", "k_psym"), ("ld_grad", "k_ld_grad"),
+                ("reduce", "k_reduce"), ("update", "k_update"))
 
-    lib = C.CDLL(os.path.join(ROOT, "paper_2509_07681_amd", "libfsne_probe.so"))
-    lib.fsne_probe_gather.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                      C.POINTER(C.c_float)]
-    lib.fsne_probe_gather.restype = C.c_int
-    ms = C.c_float(0.0)
-    rc = lib.fsne_probe_gather(table_bytes, row_bytes, rows_per_wave, nwaves, reps, C.byref(ms))
-    if rc != 0:
-        raise RuntimeError(f"gather probe failed ({rc})")
-    rows = float(rows_per_wave) * nwaves / (ms.value * 1e-3)
-    return {"row_bytes": row_bytes, "rows_per_wave": rows_per_wave,
-            "table_MB": round(table_bytes / 2 ** 20, 1), "ms": round(ms.value, 4),
-            "G_rows_per_s": round(rows / 1e9, 2), "TBps": round(rows * row_bytes / 1e12, 3)}
+
+def counted_traffic(kernel, W, K, every, start):
+    """HBM bytes per launch of `kernel` in the timed iterations, from
+    profiles/traffic.json, if it was taken with the current step sources over
+    the same iterations and renumbering (else None)."""
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tf):
+        return None
+    rec = json.load(open(tf))
+    if (rec.get("source_hash") != kernel_source_hash() or rec.get("window") != [W, K]
+            or rec.get("reorder") != [every, start]):
+        return None
+    return rec.get("per_launch_GB", {}).get(kernel)
+
+
+def roofline(kernels, name, W, K, every, start):
+    """The roofline object of the dominant kernel.  achieved = its algorithmic
+    bytes per launch over its average launch duration.  Where that exceeds the
+    HBM peak (renumbered points: the caches serve part of the bytes) the
+    fraction of HBM is taken from the counted HBM traffic of the same
+    iterations instead, and the share the caches served is stated."""
+    k = kernels[name]
+    avg_s = k["avg_ms"] * 1e-3
+    traffic = counted_traffic(name, W, K, every, start)
+    r = {"bound": "hbm", "kernel": name, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+         "algorithmic_GB_per_launch": k["algorithmic_GB"], "avg_launch_ms": k["avg_ms"],
+         "traffic": traffic,
+         "traffic_unit": "GB per launch (FETCH_SIZE x2 + WRITE_SIZE x1, calibrated on a copy)"}
+    if k["GBps"] <= PEAK_HBM_GBS:
+        r.update(achieved=k["GBps"], frac=round(k["GBps"] / PEAK_HBM_GBS, 4),
+                 basis="algorithmic bytes per launch / average launch duration")
+    elif traffic is not None:
+        ach = traffic / avg_s
+        r.update(achieved=round(ach, 1), frac=round(ach / PEAK_HBM_GBS, 4),
+                 algorithmic_GBps=k["GBps"],
+                 cache_served=round(1.0 - traffic / k["algorithmic_GB"], 4),
+                 basis="counted HBM bytes per launch / average launch duration: the "
+                       "algorithmic bytes exceed what HBM moves in that time, the caches "
+                       "serve the rest")
+    else:
+        r.update(achieved=None, frac=None, algorithmic_GBps=k["GBps"],
+                 basis="the algorithmic bytes exceed what HBM moves in the launch time (the "
+                       "caches serve part) and no counted traffic matches these sources")
+    if traffic is not None:
+        r["traffic_GBps"] = round(traffic / avg_s, 1)
+        r["traffic_frac"] = round(traffic / avg_s / PEAK_HBM_GBS, 4)
+    return r
+
+
+def bf16_error_statement(F, X, Xb, emb, cfg, n_points=2000, seed=11):
+    """Per-result error of the BF16 form: the stored HD distances (FP32 re-rank
+    of BF16 rows) against exact FP64 distances of the same BF16 rows and of
+    the original FP32 rows, on a sample of points; and the neighbours the MFMA
+    screen loses in one refinement against direct distances from the same
+    state."""
+    import numpy as np
+
+    from inputs.generators import RUN_SEED, bf16_bits_to_f32
+
+    g = emb.state()
+    N = Xb.shape[0]
+    pts = np.sort(np.random.default_rng(seed).choice(N, n_points, replace=False))
+    Xbf = bf16_bits_to_f32(Xb)
+    idx, d2 = g["hd_idx"][pts], g["hd_d2"][pts].astype(np.float64)
+    e_b = ((Xbf[idx].astype(np.float64) - Xbf[pts][:, None, :].astype(np.float64)) ** 2).sum(-1)
+    e_f = ((X[idx].astype(np.float64) - X[pts][:, None, :].astype(np.float64)) ** 2).sum(-1)
+    rb = np.abs(d2 - e_b) / np.maximum(e_b, 1e-30)
+    rf = np.abs(d2 - e_f) / np.maximum(e_f, 1e-30)
+    q = lambda a: {"median": float(f"{np.median(a):.3g}"), "p99": float(f"{np.quantile(a, 0.99):.3g}"),
+                   "max": float(f"{a.max():.3g}")}
+    # one refinement from the same state, screened and direct
+    lists = {}
+    for dm in (0, 1):
+        hpf = F.fsne_default_hparams(**{**emb.hyperparams().as_dict(), "dist_mode": dm,
+                                        "hd_mode": 1})
+        e = F.Embedding(Xb, g["Y"], cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hpf)
+        e.set_state({k: v for k, v in g.items() if k not in ("A", "R", "Zh")})
+        e.step(1)
+        lists[dm] = e.knn(0)[0]
+        e.close()
+    diff = lists[0] != lists[1]
+    rows = np.nonzero(diff.any(1))[0]
+    lost = sum(len(set(lists[0][i].tolist()) - set(lists[1][i].tolist())) for i in rows)
+    return {"points": int(n_points),
+            "rel_err_vs_fp64_of_bf16_rows": q(rb),
+            "rel_err_vs_fp64_of_fp32_rows": q(rf),
+            "screen_lost_neighbours_one_refinement": int(lost),
+            "screen_rows_differing": int(rows.size),
+            "screen_lost_per_point": float(f"{lost / N:.3g}")}
+
+
+def summarize_profile(args):
+    """Figures of the timed iterations from rocprofv3 CSV output: the step
+    kernels' dispatches are assigned to iterations (one k_update ends each,
+    the last dispatch of a kernel before it is the step's), and those of
+    iterations warmup .. warmup+steps-1 of the first embedding are averaged.
+    Directories given as name=dir: 'trace' (kernel trace: microseconds),
+    others (counter collection: KiB per dispatch, instances summed); 'cfetch'
+    and 'cwrite' are the copy-probe runs that calibrate FETCH_SIZE and
+    WRITE_SIZE."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    W, K = args.warmup, args.steps
+    out = {"window": [W, K], "reorder": [args.reorder_every, args.reorder_from]}
+    dirs = dict(x.split("=", 1) for x in args.summarize_profile)
+
+    def rows_of(d, pattern):
+        files = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+        assert files, f"no {pattern} under {d}"
+        rows = []
+        for fn in files:
+            with open(fn) as fh:
+                rows += list(csv.DictReader(fh))
+        return rows
+
+    def per_iteration(disp):
+        """disp: [(dispatch id, kernel name, value)] -> {kernel: [value per iteration]}."""
+        it, cur, per = 0, {}, defaultdict(list)
+        for _, kname, v in sorted(disp):
+            for key, pat in STEP_KERNELS:
+                if pat in kname:
+                    cur[key] = v
+                    if key == "update":
+                        for kk, vv in cur.items():
+                            per[kk].append((it, vv))
+                        it, cur = it + 1, {}
+        return {k: [v for i, v in lst if W <= i < W + K] for k, lst in per.items()}
+
+    for name, d in dirs.items():
+        if name == "trace":
+            rows = rows_of(d, "*kernel_trace.csv")
+            disp = [(int(r["Dispatch_Id"]), r["Kernel_Name"],
+                     (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3) for r in rows]
+            per = per_iteration(disp)
+            out["trace_us"] = {k: {"launches": len(v), "avg_us": round(sum(v) / len(v), 1),
+                                   "min_us": round(min(v), 1), "max_us": round(max(v), 1)}
+                               for k, v in per.items() if v}
+        else:
+            rows = rows_of(d, "*counter_collection.csv")
+            acc = defaultdict(float)
+            names = {}
+            for r in rows:
+                key = (int(r["Dispatch_Id"]), r["Counter_Name"])
+                acc[key] += float(r["Counter_Value"])
+                names[key[0]] = r["Kernel_Name"]
+            counters = sorted({c for _, c in acc})
+            for c in counters:
+                disp = [(di, names[di], v) for (di, cc), v in acc.items() if cc == c]
+                if name in ("cfetch", "cwrite"):
+                    biggest = max(v for _, _, v in disp)
+                    out[f"{name}_{c}_KiB"] = biggest
+                    continue
+                per = per_iteration(disp)
+                out.setdefault("counters_KiB", {})[c] = {
+                    k: round(sum(v) / len(v), 1) for k, v in per.items() if v}
+    if "cfetch" in dirs and "cwrite" in dirs and "counters_KiB" in out:
+        copy_kib = args.copy_bytes / 1024.0
+        f_fetch = round(copy_kib / out["cfetch_FETCH_SIZE_KiB"], 2)
+        f_write = round(copy_kib / out["cwrite_WRITE_SIZE_KiB"], 2)
+        c = out["counters_KiB"]
+        per_launch = {k: round((c["FETCH_SIZE"][k] * f_fetch + c["WRITE_SIZE"][k] * f_write)
+                               * 1024 / 1e9, 3)
+                      for k in c["FETCH_SIZE"] if k in c.get("WRITE_SIZE", {})}
+        out["factors"] = {"FETCH_SIZE": f_fetch, "WRITE_SIZE": f_write}
+        out["per_launch_GB"] = per_launch
+        if args.write_traffic:
+            rec = {"source_hash": kernel_source_hash(), "workload": "manifold_1m",
+                   "window": [W, K], "reorder": [args.reorder_every, args.reorder_from],
+                   "unit": "GB per launch", "factors": out["factors"],
+                   "per_launch_GB": per_launch, "sources": list(STEP_SOURCES)}
+            with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+                json.dump(rec, fh, indent=1)
+    print(json.dumps(out, indent=1))
 
 
 def mlp_flops(D, H1, H2, d, n):
@@ -844,12 +1043,19 @@ def main():
     ap.add_argument("--reorder-every", type=int, default=25,
                     help="renumber the points along the embedding's Morton order every this "
                          "many steps in the timed runs (0: never)")
+    ap.add_argument("--reorder-from", type=int, default=50,
+                    help="first iteration before which the timed runs renumber")
     ap.add_argument("--blobs-knn", action="store_true",
                     help="HD-list R_NX(K) on overlapping and disjointed blobs instead")
     ap.add_argument("--memo-compare", action="store_true",
                     help="HD kernel with the memory of rejected candidates off and on instead")
-    ap.add_argument("--gather-table", action="store_true",
-                    help="print the random-gather ceiling for several row sizes instead")
+    ap.add_argument("--summarize-profile", nargs="+", metavar="NAME=DIR",
+                    help="summarize rocprofv3 CSV output of this command's timed iterations "
+                         "instead (trace=, fetch=, write=, cfetch=, cwrite= directories)")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30,
+                    help="bytes of the copy-probe runs given to --summarize-profile")
+    ap.add_argument("--write-traffic", action="store_true",
+                    help="with --summarize-profile: write profiles/traffic.json")
     ap.add_argument("--fb-n", type=int, default=50000)
     ap.add_argument("--fb-iters", type=int, default=2000)
     ap.add_argument("--fb-every", type=int, default=100)
@@ -863,6 +1069,9 @@ def main():
                     help="styles: classes with a 3-dim style manifold; image: independent "
                          "pixel drops and jitter within a class")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args)
+        return
     if args.copy_probe:
         import torch
 
@@ -913,48 +1122,40 @@ def main():
     if args.image:
         print(json.dumps(image_run(F, args)))
         return
-    if args.gather_table:
-        # random-gather ceilings for the row sizes the step kernels gather
-        for rb, rows, table in ((16, 128, 2 ** 24), (64, 112, 2 ** 26), (128, 64, 2 ** 27),
-                                (128, 64, 2 ** 29), (256, 32, 2 ** 28), (256, 32, 2 ** 31),
-                                (512, 32, 2 ** 29), (512, 32, 2 ** 32)):
-            print(json.dumps(gather_probe(rb, rows, table)), flush=True)
-        return
-
     X, _, cfg = make_workload("manifold_1m")
     N = X.shape[0]
     Y0 = y_init(N, cfg["d"])
     hp = F.fsne_default_hparams(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=N / 12.0,
                                 momentum=0.5, attr=12.0, n_neg=cfg["n_neg"], hd_mode=1)
-    every = args.reorder_every
-    n_prof = min(args.steps, 50)
-    # the same run without renumbering, for comparison
-    emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp)
-    emb.step(args.warmup)
-    emb.sync()
-    t0 = time.perf_counter()
-    emb.step(args.steps)
-    emb.sync()
-    ms_plain = (time.perf_counter() - t0) * 1e3 / args.steps
-    kt0, _, _ = profiled_steps(emb, n_prof, 0, N)
-    emb.close()
+    every, start = args.reorder_every, args.reorder_from
+    W, K = args.warmup, args.steps
+    renumbers = [t for t in range(W + K) if reorder_due(t, every, start)]
 
+    # The timed region: iterations W .. W+K-1 of a fresh embedding, every
+    # kernel launch bracketed by HIP events on the library's stream (read
+    # after the region) for the per-kernel durations.
     emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp)
-    emb.step(args.warmup)
+    run_steps(emb, 0, W, every, start)
     emb.sync()
+    emb.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run_steps(emb, args.steps, every)
+    run_steps(emb, W, K, every, start)
     emb.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_step = dt * 1e3 / args.steps
+    ms_step = dt * 1e3 / K
+    kt = emb.kernel_times()
+    emb.profile(False)
     st = emb.stats()
     assert st["nonfinite"] == 0, "embedding diverged"
+    emb.close()
 
-    # per-kernel durations from HIP events recorded on the library's stream,
-    # and the candidate rows each iteration actually loaded
-    kt, hd_cand, ld_cand = profiled_steps(emb, n_prof, every, N)
+    # The same iterations again (the run is deterministic), one at a time, for
+    # the candidate rows each of them loaded.
+    emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp)
+    run_steps(emb, 0, W, every, start)
+    _, hd_cand, ld_cand = profiled_steps(emb, W, K, every, start, N)
     emb.close()
 
     bpp = bytes_per_point(cfg, 4, hd_cand, ld_cand)
@@ -971,38 +1172,18 @@ def main():
         kernels[k] = e
     kernels["hd_refine"]["candidate_rows_per_point"] = round(hd_cand, 3)
     kernels["ld_grad"]["candidate_rows_per_point"] = round(ld_cand, 3)
-    # the LD pass gathers one 4*DP-byte row per neighbour, candidate and
-    # negative: compare its row rate with the random-gather ceiling
-    dp = 2
-    while dp < cfg["d"]:
-        dp *= 2
-    ld_rows = 1 + cfg["K_ld"] + ld_cand + cfg["K_hd"] + cfg["n_neg"]
-    probe = gather_probe(4 * dp, 112, N * 4 * dp)
-    ld_rate = ld_rows * N / (kernels["ld_grad"]["avg_ms"] * 1e-3) / 1e9
-    kernels["ld_grad"]["rows_per_point"] = round(ld_rows, 2)
-    kernels["ld_grad"]["G_rows_per_s"] = round(ld_rate, 2)
-    kernels["ld_grad"]["frac_of_gather_ceiling"] = round(ld_rate / probe["G_rows_per_s"], 4)
     ld_only_ms = sum(kernels[k]["avg_ms"] for k in ("ld_grad", "reduce", "update"))
-    # the dominant kernel: the one with algorithmic bytes that takes longest
-    # per step (the HD refinement on ids without locality; the LD pass once
-    # the points are renumbered and the HD gathers come mostly from the caches)
+    # the dominant kernel: of those with algorithmic bytes, the one that takes
+    # longest per step in the timed iterations
     dom_name = max((k for k in kernels if "algorithmic_GB" in kernels[k]),
                    key=lambda k: kernels[k]["avg_ms"])
-    dom = kernels[dom_name]
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tf):
-        rec = json.load(open(tf))
-        if (rec.get("source_hash") == kernel_source_hash() and rec.get("reorder_every") == every
-                and dom_name in rec.get("per_launch_GB", {})):
-            traffic = rec["per_launch_GB"][dom_name]
     out = {
         "metric": METRIC,
         "value": round(1000.0 / ms_step, 3),
         "unit": "iters/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": K,
+        "warmup": W,
         "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
@@ -1013,50 +1194,51 @@ def main():
                                "manifolds in R^128 (FP32 rows), d=16, K_hd=K_ld=32, 16 negatives, "
                                "alpha=1, perplexity 10; every timed step refines the HD lists"
                                + (f"; the points are renumbered along the embedding's Morton "
-                                  f"order every {every} steps, inside the timed region"
-                                  if every > 0 else ""),
+                                  f"order every {every} iterations from iteration {start} on, "
+                                  f"inside the timed region" if every > 0 else ""),
                    "N": N, "D": cfg["D"], "d": cfg["d"], "K_hd": cfg["K_hd"],
                    "K_ld": cfg["K_ld"], "n_neg": cfg["n_neg"], "hd_mode": "always",
-                   "reorder_every": every},
-        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": dom["GBps"],
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": dom["frac"],
-                     "traffic": traffic, "traffic_unit": "GB per launch (FETCH_SIZE x2.0 "
-                     "+ WRITE_SIZE x1.0, copy-calibrated)",
-                     # the bytes the kernel actually moves to and from the memory
-                     # side, over the same duration (with renumbering the caches
-                     # serve part of the algorithmic bytes, so an HD refinement's
-                     # frac can exceed 1)
-                     "traffic_GBps": (round(traffic / (dom["avg_ms"] * 1e-3), 1)
-                                      if traffic is not None else None),
-                     "traffic_frac": (round(traffic / (dom["avg_ms"] * 1e-3) / PEAK_HBM_GBS, 4)
-                                      if traffic is not None else None)},
+                   "timed_iterations": [W, W + K - 1],
+                   "renumbered_before_iterations": renumbers},
+        "roofline": roofline(kernels, dom_name, W, K, every, start),
         "kernels": kernels,
-        "gather_ceiling": probe,
         "ld_only_ms_per_step": round(ld_only_ms, 4),
         "ld_only_iters_per_s": round(1000.0 / ld_only_ms, 2),
-        "no_reorder": {"ms_per_step": round(ms_plain, 4),
-                       "iters_per_s": round(1000.0 / ms_plain, 3),
-                       "kernels_ms": {k: round(v[0] / max(v[1], 1), 4)
-                                      for k, v in kt0.items() if v[1]}},
     }
+    if renumbers:
+        # the same iterations without renumbering, for comparison
+        emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp)
+        emb.step(W)
+        emb.sync()
+        t0 = time.perf_counter()
+        emb.step(K)
+        emb.sync()
+        ms_plain = (time.perf_counter() - t0) * 1e3 / K
+        emb.close()
+        out["no_reorder"] = {"ms_per_step": round(ms_plain, 4),
+                             "iters_per_s": round(1000.0 / ms_plain, 3)}
 
-    # the BF16 forms: step time with the HD refinement on
+    # the BF16 forms over the same iterations (at most 50 of them)
     Xb = f32_to_bf16_bits(X)
     forms = {}
+    nf = min(K, 50)
     for name, dm in (("bf16_rows_direct", 0), ("bf16_mfma_screen", 1)):
         hpf = F.fsne_default_hparams(**{**hp.as_dict(), "dist_mode": dm})
         e2 = F.Embedding(Xb, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hpf)
-        e2.step(args.warmup)
-        nf = min(args.steps, 50)
-        kt2, _, _ = profiled_steps(e2, nf, every, N)
+        orig = np.arange(N)
+        run_steps(e2, 0, W, every, start, orig)
         e2.sync()
         t2 = time.perf_counter()
-        run_steps(e2, nf, every)
+        run_steps(e2, W, nf, every, start, orig)
         e2.sync()
         ms2 = (time.perf_counter() - t2) * 1e3 / nf
-        e2.close()
+        kt2, _, _ = profiled_steps(e2, W + nf, min(nf, 10), every, start, N, orig)
         forms[name] = {"ms_per_step": round(ms2, 4), "iters_per_s": round(1000.0 / ms2, 2),
-                       "hd_refine_ms": round(kt2["hd_refine"][0] / max(kt2["hd_refine"][1], 1), 4)}
+                       "hd_refine_ms": round(kt2["hd_refine"][0] / max(kt2["hd_refine"][1], 1),
+                                             4)}
+        if dm == 1:
+            forms["bf16_error"] = bf16_error_statement(F, X[orig], Xb[orig], e2, cfg)
+        e2.close()
     out["forms"] = forms
 
     if not args.no_quality:

@@ -140,8 +140,11 @@ fsne_status fsne_default_hparams(fsne_hparams *hp);
  *   Y0        N x d initial embedding, host memory (NULL: all zeros).
  *   d, K_hd, K_ld  embedding dimension and list lengths:
  *             1 <= d <= 64, 2 <= K_hd <= 64, 1 <= K_ld <= 64, K_hd, K_ld < N.
+ *   alpha     tail of the LD kernel (eq. (4)), > 0; replaces hp->alpha.
+ *   perplexity  of the HD affinities (eq. (1)), 1 < perplexity < K_hd;
+ *             replaces hp->perplexity.
  *   seed      key of the Philox4x32-10 draws (candidates, negatives, coin).
- *   hp        hyperparameters, or NULL for the defaults.
+ *   hp        the other hyperparameters, or NULL for the defaults.
  *   stream    hipStream_t to run on, or NULL for a stream the context owns.
  *   capacity  rows reserved for fsne_insert_points (>= N).
  * Initial lists: for point i, the first K distinct other points from draws
@@ -149,9 +152,9 @@ fsne_status fsne_default_hparams(fsne_hparams *hp);
  * the perplexity; V = 0; E = 1; t = 0.
  * Errors: FSNE_EINVAL (bad sizes or hyperparameters), FSNE_ENOMEM, FSNE_EHIP. */
 fsne_status fsne_init(fsne_ctx **out, const void *X, int64_t N, int32_t D, int32_t xdtype,
-                      const float *Y0, int32_t d, int32_t K_hd, int32_t K_ld, uint64_t seed,
-                      const fsne_hparams *hp, int32_t x_on_device, void *stream,
-                      int64_t capacity);
+                      const float *Y0, int32_t d, int32_t K_hd, int32_t K_ld, float alpha,
+                      float perplexity, uint64_t seed, const fsne_hparams *hp,
+                      int32_t x_on_device, void *stream, int64_t capacity);
 
 /* Run n_iters iterations (Sec. 3), asynchronously on the context stream.
  * Per iteration: [if the coin fires] HD refinement + recalibration of changed

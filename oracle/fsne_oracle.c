@@ -1206,3 +1206,14 @@ int fsneo_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads used by the loops over points from now on (results do not depend */
+/* on it).                                                                    */
+void fsneo_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

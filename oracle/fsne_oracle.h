@@ -108,6 +108,7 @@ int fsneo_jump_start(fsneo_state *S, int32_t projection, double sigma);
 void fsneo_delete_fix(fsneo_state *S, const fsneo_hp *hp, const int32_t *newid);
 int32_t fsneo_cluster(const fsneo_state *S, float eps, int32_t min_pts, int32_t *labels);
 int fsneo_num_threads(void);
+void fsneo_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

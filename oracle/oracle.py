@@ -132,6 +132,8 @@ def _declare(L):
     L.fsneo_drift.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P, C.c_int64, P]
     L.fsneo_drift.restype = C.c_int
     L.fsneo_num_threads.restype = C.c_int
+    L.fsneo_set_num_threads.argtypes = [C.c_int]
+    L.fsneo_set_num_threads.restype = None
     L.fsneo_jump_start.argtypes = [C.POINTER(_State), C.c_int32, C.c_double]
     L.fsneo_jump_start.restype = C.c_int
     L.fsneo_delete_fix.argtypes = [C.POINTER(_State), C.POINTER(_Hp), P]
@@ -157,6 +159,10 @@ def _p(a: np.ndarray):
 
 def num_threads() -> int:
     return lib().fsneo_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().fsneo_set_num_threads(int(n))
 
 
 class Hyper:

@@ -1,9 +1,7 @@
 """Build libfsne.so (HIP, gfx950) in-tree with hipcc.
 
 Every .hip file under csrc/ is compiled to an object in _build/ (in
-parallel), then linked into paper_2509_07681_amd/libfsne.so.  The gather
-probe under probe/ (a measurement aid for the benchmark) becomes
-libfsne_probe.so.
+parallel), then linked into paper_2509_07681_amd/libfsne.so.
 """
 from __future__ import annotations
 
@@ -18,8 +16,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfsne.so")
-PROBE_SRC = os.path.join(HERE, "probe", "gather_probe.hip")
-PROBE_LIB = os.path.join(HERE, "libfsne_probe.so")
 ARCH = os.environ.get("FSNE_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [
@@ -59,15 +55,8 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
-    # the measurement probe is a library of its own, loaded only by the benchmark
-    tmp = PROBE_LIB + ".tmp"
-    r = subprocess.run([_hipcc(), *CFLAGS, "-shared", "-o", tmp, PROBE_SRC], capture_output=True,
-                       text=True)
-    if r.returncode != 0:
-        raise RuntimeError("probe build failed:\n" + r.stdout + r.stderr)
-    os.replace(tmp, PROBE_LIB)
     if verbose:
-        print(f"built {LIB} and {PROBE_LIB}")
+        print(f"built {LIB}")
     return LIB
 
 

@@ -424,9 +424,9 @@ fsne_status fsne_default_hparams(fsne_hparams* hp) {
 }
 
 fsne_status fsne_init(fsne_ctx** out, const void* X, int64_t N, int32_t D, int32_t xdtype,
-                      const float* Y0, int32_t d, int32_t K_hd, int32_t K_ld, uint64_t seed,
-                      const fsne_hparams* hp, int32_t x_on_device, void* stream,
-                      int64_t capacity) {
+                      const float* Y0, int32_t d, int32_t K_hd, int32_t K_ld, float alpha,
+                      float perplexity, uint64_t seed, const fsne_hparams* hp,
+                      int32_t x_on_device, void* stream, int64_t capacity) {
   if (!out) return FSNE_EINVAL;
   *out = nullptr;
   if (!X || N < 3 || N > 2147483647LL || D < 1 || d < 1 || d > 64 || K_hd < 2 || K_hd > 64 ||
@@ -441,6 +441,8 @@ fsne_status fsne_init(fsne_ctx** out, const void* X, int64_t N, int32_t D, int32
     h = *hp;
   else
     fsne_default_hparams(&h);
+  h.alpha = alpha;
+  h.perplexity = perplexity;
   fsne_status st = check_hparams(c, &h, K_hd, xdtype, D);
   if (st != FSNE_OK) {
     delete c;
@@ -840,6 +842,12 @@ fsne_status fsne_profile(fsne_ctx* c, int32_t enable) {
   if (!c) return FSNE_EINVAL;
   TRY(drain_timings(c));
   c->prof = enable != 0;
+  // events for the first 1024 launches up front: none is created between launches
+  while (c->prof && c->spare.size() < 2048) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    c->spare.push_back(e);
+  }
   for (int k = 0; k < FSNE_NKERNELS; ++k) {
     c->ms[k] = 0.0;
     c->launches[k] = 0;

@@ -7,10 +7,9 @@
 // its new id and every list entry is mapped.  fsne_reorder picks the
 // permutation itself, as the Morton (Z-order) curve over a projection of the
 // embedding onto at most three axes: points close in the embedding, which
-// the method makes close in the data, get nearby ids.
+// the method makes close in the data, get nearby ids (a stable sort of the
+// Morton keys: equal keys keep the order of the current ids).
 #include <hip/hip_runtime.h>
-
-#include <hipcub/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -131,6 +130,134 @@ __global__ void k_morton(const float* __restrict__ Y, int32_t n, int DP, Project
   }
   keys[i] = key;
   ids[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Stable least-significant-digit radix sort of (key, id) pairs by 8-bit
+// digits (four passes cover the 30-bit keys).  A block owns a tile of
+// kSortItems rounds of 256 consecutive elements.  Per pass: every block counts
+// its digits; one block turns the digit-major count table into exclusive
+// offsets (digit d of block b starts after every smaller digit and after
+// digit d of the blocks before b); every block scatters its tile in element
+// order, each element at its digit's offset plus the number of equal digits
+// before it in the tile (found with ballots within a wave, per-wave counts
+// across the waves of a round, running counts across rounds).  Equal keys
+// keep their order, so the result is deterministic.
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 256;   // = number of digit values
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kSortWaves = kSortThreads / 64;
+
+__global__ __launch_bounds__(kSortThreads) void k_digit_count(const uint32_t* __restrict__ keys,
+                                                              int32_t n, int shift,
+                                                              uint32_t* __restrict__ count) {
+  __shared__ uint32_t c[kSortThreads];
+  c[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&c[(keys[i] >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  count[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = c[threadIdx.x];
+}
+
+// In-place exclusive prefix sum of a[0..len) by one block of 1024 threads:
+// each thread sums a contiguous chunk, the chunk sums are scanned in LDS,
+// then each thread rewrites its chunk.
+__global__ __launch_bounds__(1024) void k_exclusive_scan(uint32_t* __restrict__ a, int64_t len) {
+  __shared__ uint32_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (len + 1023) / 1024;
+  const int64_t lo = std::min<int64_t>(len, tid * chunk), hi = std::min<int64_t>(len, lo + chunk);
+  uint32_t s = 0u;
+  for (int64_t k = lo; k < hi; ++k) s += a[k];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[tid] - s;
+  for (int64_t k = lo; k < hi; ++k) {
+    const uint32_t v = a[k];
+    a[k] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
+    const uint32_t* __restrict__ keys, const int32_t* __restrict__ ids, int32_t n, int shift,
+    const uint32_t* __restrict__ offset, uint32_t* __restrict__ keys_out,
+    int32_t* __restrict__ ids_out) {
+  __shared__ uint32_t run[kSortThreads];             // next position of each digit
+  __shared__ uint32_t wcount[kSortWaves][kSortThreads];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  run[tid] = offset[(int64_t)tid * gridDim.x + blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + (int64_t)r * kSortThreads + tid;
+    const bool ok = i < n;
+    const uint32_t k = ok ? keys[i] : 0u;
+    const int32_t v = ok ? ids[i] : 0;
+    const uint32_t dg = (k >> shift) & 0xFFu;
+    // lanes of this wave whose element has the same digit
+    uint64_t same = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = ((dg >> b) & 1u) != 0u;
+      const uint64_t m = __ballot(ok && bit);
+      same &= bit ? m : ~m;
+    }
+    const uint32_t below = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    for (int q = 0; q < kSortWaves; ++q) wcount[q][tid] = 0u;
+    __syncthreads();
+    if (ok && below == 0u) wcount[w][dg] = (uint32_t)__popcll(same);
+    __syncthreads();
+    uint32_t pos = 0u;
+    if (ok) {
+      pos = run[dg] + below;
+      for (int q = 0; q < w; ++q) pos += wcount[q][dg];
+    }
+    __syncthreads();
+    uint32_t add = 0u;
+    for (int q = 0; q < kSortWaves; ++q) add += wcount[q][tid];
+    run[tid] += add;
+    if (ok) {
+      keys_out[pos] = k;
+      ids_out[pos] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Sorts (keys, ids) by the low `bits` bits of the keys (bits <= 32, even
+// number of passes: the result ends in keys / ids; tmp_* are the other
+// buffers of the ping-pong, count holds 256 x ceil(n / kSortTile) words).
+hipError_t radix_sort_pairs(uint32_t* keys, int32_t* ids, uint32_t* tmp_keys, int32_t* tmp_ids,
+                            uint32_t* count, int32_t n, int bits, hipStream_t s) {
+  const unsigned nb = (unsigned)((n + kSortTile - 1) / kSortTile);
+  int passes = (bits + 7) / 8;
+  passes += passes & 1;
+  uint32_t *ka = keys, *kb = tmp_keys;
+  int32_t *ia = ids, *ib = tmp_ids;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(k_digit_count, dim3(nb), dim3(kSortThreads), 0, s, ka, n, shift, count);
+    hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(1024), 0, s, count,
+                       (int64_t)kSortThreads * nb);
+    hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortThreads), 0, s, ka, ia, n, shift,
+                       count, kb, ib);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    std::swap(ka, kb);
+    std::swap(ia, ib);
+  }
+  return hipSuccess;
 }
 
 // new_of_old[old_of_new[k]] = k.
@@ -302,13 +429,10 @@ extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
   size_t most = 0;
   (void)row_arrays(c, sc, &most);
   // workspace: range partials, range, keys (2), ids (2), permutation, the
-  // radix sort's own space, staging for the rows
+  // sort's digit counts, staging for the rows
   hipError_t e;
-  size_t sort_bytes = 0;
-  if ((e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t*)nullptr,
-                                              (uint32_t*)nullptr, (const int32_t*)nullptr,
-                                              (int32_t*)nullptr, N, 0, 30, s)) != hipSuccess)
-    return hip_error(c, e, "fsne_reorder: sort size");
+  const size_t sort_bytes =
+      sizeof(uint32_t) * kSortThreads * (size_t)((N + kSortTile - 1) / kSortTile);
   const size_t n4 = align_up(sizeof(int32_t) * (size_t)N);
   const size_t o_part = 0, o_range = align_up(sizeof(float) * kRedBlocks * 2 * kMaxAxes);
   const size_t o_keys = o_range + align_up(sizeof(float) * 2 * kMaxAxes);
@@ -325,7 +449,7 @@ extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
   int32_t* ids = reinterpret_cast<int32_t*>(w + o_ids);
   int32_t* ids2 = reinterpret_cast<int32_t*>(w + o_ids2);
   int32_t* d_new = reinterpret_cast<int32_t*>(w + o_new);
-  void* sort_tmp = w + o_sort;
+  uint32_t* sort_count = reinterpret_cast<uint32_t*>(w + o_sort);
   hipLaunchKernelGGL(k_proj_range, dim3(kRedBlocks), dim3(256), 0, s, c->Y, N, c->DP, pr, part);
   std::vector<float> hp((size_t)kRedBlocks * 2 * kMaxAxes);
   if ((e = hipGetLastError()) != hipSuccess ||
@@ -351,10 +475,9 @@ extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
     return hip_error(c, e, "fsne_reorder: range upload");
   hipLaunchKernelGGL(k_morton, dim3(gn), dim3(256), 0, s, c->Y, N, c->DP, pr, range, keys, ids);
   if ((e = hipGetLastError()) != hipSuccess ||
-      (e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, keys, keys2, ids, ids2, N, 0,
-                                              30, s)) != hipSuccess)
+      (e = radix_sort_pairs(keys, ids, keys2, ids2, sort_count, N, 30, s)) != hipSuccess)
     return hip_error(c, e, "fsne_reorder: sort");
-  hipLaunchKernelGGL(k_invert, dim3(gn), dim3(256), 0, s, ids2, N, d_new);
+  hipLaunchKernelGGL(k_invert, dim3(gn), dim3(256), 0, s, ids, N, d_new);
   if ((e = hipGetLastError()) != hipSuccess) return hip_error(c, e, "fsne_reorder: invert");
   st = apply_permutation(c, sc, d_new, w + o_buf);
   if (st != FSNE_OK) return st;

@@ -60,8 +60,8 @@ def load_library(path: str = LIB_PATH):
     L = C.CDLL(path)
     P, I32, I64, F = C.c_void_p, C.c_int32, C.c_int64, C.c_float
     L.fsne_default_hparams.argtypes = [C.POINTER(fsne_hparams)]
-    L.fsne_init.argtypes = [C.POINTER(P), P, I64, I32, I32, P, I32, I32, I32, C.c_uint64,
-                            C.POINTER(fsne_hparams), I32, P, I64]
+    L.fsne_init.argtypes = [C.POINTER(P), P, I64, I32, I32, P, I32, I32, I32, F, F,
+                            C.c_uint64, C.POINTER(fsne_hparams), I32, P, I64]
     L.fsne_step.argtypes = [P, I32]
     L.fsne_set_hyperparams.argtypes = [P, C.POINTER(fsne_hparams)]
     L.fsne_get_hyperparams.argtypes = [P, C.POINTER(fsne_hparams)]
@@ -118,9 +118,14 @@ def fsne_default_hparams(**overrides) -> fsne_hparams:
     return hp
 
 
-def fsne_init(X, Y0, d, K_hd, K_ld, seed, hp=None, stream=None, capacity=None):
-    """X: float32 array (host numpy or device torch tensor) or uint16 BF16 bits."""
+def fsne_init(X, Y0, d, K_hd, K_ld, seed, hp=None, stream=None, capacity=None, alpha=None,
+              perplexity=None):
+    """X: float32 array (host numpy or device torch tensor) or uint16 BF16 bits.
+    alpha, perplexity: None takes them from hp (or the defaults)."""
     L = load_library()
+    base = hp if hp is not None else fsne_default_hparams()
+    alpha = base.alpha if alpha is None else alpha
+    perplexity = base.perplexity if perplexity is None else perplexity
     on_dev = hasattr(X, "is_cuda") and X.is_cuda
     if on_dev:
         import torch
@@ -147,8 +152,9 @@ def fsne_init(X, Y0, d, K_hd, K_ld, seed, hp=None, stream=None, capacity=None):
     if Y0a is not None and Y0a.shape != (N, d):
         raise ValueError("Y0 must be N x d")
     ctx = C.c_void_p()
-    st = L.fsne_init(C.byref(ctx), _ptr(X), N, D, xdt, _ptr(Y0a), d, K_hd, K_ld, seed,
-                     C.byref(hp) if hp is not None else None, 1 if on_dev else 0,
+    st = L.fsne_init(C.byref(ctx), _ptr(X), N, D, xdt, _ptr(Y0a), d, K_hd, K_ld, float(alpha),
+                     float(perplexity), seed, C.byref(hp) if hp is not None else None,
+                     1 if on_dev else 0,
                      None if stream is None else C.c_void_p(stream),
                      N if capacity is None else capacity)
     if st != FSNE_OK:

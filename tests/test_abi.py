@@ -46,11 +46,12 @@ def test_defaults_and_argument_checks(fsne_lib):
     ctx = C.c_void_p()
 
     def init(**kw):
-        a = dict(X=X.ctypes.data, N=100, D=8, xdt=0, Y0=None, d=2, Kh=16, Kl=8, seed=1,
-                 hp=None, dev=0, stream=None, cap=100)
+        a = dict(X=X.ctypes.data, N=100, D=8, xdt=0, Y0=None, d=2, Kh=16, Kl=8, alpha=1.0,
+                 perp=10.0, seed=1, hp=None, dev=0, stream=None, cap=100)
         a.update(kw)
         return L.fsne_init(C.byref(ctx), a["X"], a["N"], a["D"], a["xdt"], a["Y0"], a["d"],
-                           a["Kh"], a["Kl"], a["seed"], a["hp"], a["dev"], a["stream"], a["cap"])
+                           a["Kh"], a["Kl"], a["alpha"], a["perp"], a["seed"], a["hp"], a["dev"],
+                           a["stream"], a["cap"])
 
     assert init(Kh=100) == F.FSNE_EINVAL          # K_hd >= N
     assert init(Kh=65) == F.FSNE_EINVAL           # list longer than a wave
@@ -67,8 +68,12 @@ def test_defaults_and_argument_checks(fsne_lib):
     assert init(D=4100) == F.FSNE_EINVAL
     assert init(D=1025) == F.FSNE_EINVAL
     assert init(D=2056, xdt=1) == F.FSNE_EINVAL
-    for bad in (dict(alpha=0.0), dict(alpha=-1.0), dict(perplexity=16.0), dict(perplexity=1.0),
-                dict(momentum=1.0), dict(n_neg=65), dict(hd_mode=3), dict(dist_mode=1),
+    # alpha and perplexity are positional and replace the hyperparameters' values
+    assert init(alpha=0.0) == F.FSNE_EINVAL
+    assert init(alpha=-1.0) == F.FSNE_EINVAL
+    assert init(perp=16.0) == F.FSNE_EINVAL        # >= K_hd: no finite calibration
+    assert init(perp=1.0) == F.FSNE_EINVAL
+    for bad in (dict(momentum=1.0), dict(n_neg=65), dict(hd_mode=3), dict(dist_mode=1),
                 dict(e_smooth=0.0), dict(lr=float("nan")), dict(reject_memo=2),
                 dict(reject_memo=-1), dict(metric=2), dict(metric=-1)):
         h = F.fsne_default_hparams(**bad)

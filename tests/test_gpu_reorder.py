@@ -160,3 +160,58 @@ def test_renumber_under_the_angular_metric(fsne_lib):
         ex = ((U[g["hd_idx"][i]] - U[i]) ** 2).sum(1)
         assert np.all(np.abs(g["hd_d2"][i] - ex) <= 1e-4 * np.sqrt(ex) + 1e-6 * ex + 1e-7), i
     emb.close()
+
+
+def _spread(v, axes):
+    if axes == 1:
+        return v
+    r = np.zeros_like(v)
+    for b in range(30 // axes):
+        r |= ((v >> b) & 1) << (b * axes)
+    return r
+
+
+def _morton_keys(Y):
+    """The Morton keys of the renumbering, on the host in single precision:
+    projection onto min(d, 3) axes (coordinates c = a, a+3, ... summed with
+    alternating signs when d > 3), each axis scaled to its range and cut to
+    30 / axes bits, bits interleaved."""
+    N, d = Y.shape
+    axes = min(d, 3)
+    bits = 30 // axes
+    top = np.float32((1 << bits) - 1)
+    key = np.zeros(N, np.uint64)
+    for a in range(axes):
+        if d <= 3:
+            v = Y[:, a].astype(np.float32)
+        else:
+            v = np.zeros(N, np.float32)
+            for k, c in enumerate(range(a, d, 3)):
+                v = (v - Y[:, c]) if k & 1 else (v + Y[:, c])
+        lo, hi = v.min(), v.max()
+        t = (v - lo) / (hi - lo) if hi > lo else np.zeros(N, np.float32)
+        q = np.minimum(np.maximum(t * top, np.float32(0)), top).astype(np.uint64)
+        key |= _spread(q, axes) << np.uint64(a)
+    return key
+
+
+@pytest.mark.parametrize("N,d", [(5000, 2), (70001, 3), (4097, 1), (12345, 16), (300, 5)])
+def test_reorder_is_a_stable_sort_of_the_morton_keys(fsne_lib, N, d):
+    """The new ids list the points by Morton key, equal keys in the order of
+    the current ids (the library's own radix sort, several tiles and a
+    ragged last one)."""
+    F = fsne_lib
+    X = manifolds(n_manifolds=10, per_manifold=-(-N // 10), D=24, k=3, seed=N)[0][:N]
+    hp = F.fsne_default_hparams(perplexity=5.0, lr=max(N / 12.0, 1.0), n_neg=4, hd_mode=1)
+    emb = F.Embedding(X, y_init(N, d), d, 8, 6, seed=9, hp=hp)
+    emb.step(20)
+    Y = emb.Y()
+    p = emb.reorder()
+    assert np.array_equal(np.sort(p), np.arange(N))
+    old_of_new = np.argsort(p)
+    k = _morton_keys(Y)[old_of_new].astype(np.int64)
+    assert np.all(np.diff(k) >= 0)
+    ties = np.diff(k) == 0
+    assert np.all(np.diff(old_of_new)[ties] > 0)
+    assert len(np.unique(k)) > N // 4       # keys spread, not all tied
+    emb.close()
