@@ -236,6 +236,22 @@ fsne_status fsne_insert_points(fsne_ctx *ctx, const void *Xnew, int64_t n, const
 fsne_status fsne_drift_points(fsne_ctx *ctx, const int64_t *ids, const void *Xnew, int64_t n,
                               const float *Yinit);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid device allocation): fsne_drift_points
+ * without any hipMalloc / hipFree.  The ids, X rows and Y rows of the call
+ * are staged in a fixed device array of 16 MiB that the library holds on
+ * each GPU until the process ends; a call needs
+ *   align256(8n) + align256(4n) + align256(n D xbytes) + align256(4 n d)
+ *   + align256(4 n DP)  bytes  (DP: d rounded up to a power of two >= 2)
+ * and a larger batch is rejected with FSNE_EINVAL (split it).  ids must be
+ * strictly increasing (no duplicates).  Same results as fsne_drift_points.
+ * Synchronises the context stream before returning.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (from several
+ * threads or contexts) race and must be serialised by the caller.
+ * Errors: FSNE_EINVAL, FSNE_ESTATE (borrowed X), FSNE_EHIP. */
+fsne_status fsne_drift_points_noalloc(fsne_ctx *ctx, const int64_t *ids, const void *Xnew,
+                                      int64_t n, const float *Yinit);
+
 /* Remove n points (host ids, distinct, 0 <= id < N; at least
  * max(K_hd, K_ld) + 1 points must remain) -- online use, Sec. 3.  Ids stay
  * dense: with N' = N - n, the surviving points at or beyond N' move, in

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,7 +18,18 @@ using fsne::StepArgs;
 
 #include "fsne_context.h"
 
+// Device staging of fsne_drift_points_noalloc (the ids, X rows and Y rows of
+// one call): a fixed 16 MiB per device, held until the process ends.  Host
+// code never passes `scratch` itself to a kernel or a copy; it uses the
+// device address bind_scratch looks up.
+static constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxScratchDevices] = {};
 
 const char* kNoCtx = "null context";
 
@@ -393,6 +405,52 @@ void release(fsne_ctx* c) {
   c->stream = nullptr;
 }
 
+// Apply a drift whose staging is on the device: n ids (int32), their new X
+// rows and, if dy is not null, their new Y rows (padded, n x DP).
+fsne_status drift_apply(fsne_ctx* c, const int32_t* dids, const uint8_t* dx, const float* dy,
+                        int64_t n) {
+  const size_t xrow = (size_t)c->D * xbytes(c);
+  HIPCHK(c, fsne::launch_scatter_rows(c->X, dx, dids, (int32_t)n, (int32_t)xrow, c->stream));
+  if (dy)
+    HIPCHK(c, fsne::launch_scatter_rows(c->Y, dy, dids, (int32_t)n,
+                                        (int32_t)(sizeof(float) * c->DP), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->moved, 0, (size_t)c->N, c->stream));
+  HIPCHK(c, fsne::launch_mark_moved(c->moved, c->V, c->DP, dids, (int32_t)n, c->stream));
+  // moved rows change distances in both directions: every rejection is void
+  TRY(clear_memo(c, 0, c->cap));
+  TRY(refresh_unit_rows(c));
+  StepArgs a = make_args(c);
+  if (c->xdtype == FSNE_BF16)
+    HIPCHK(c, fsne::launch_xnorm(raw_args(c), c->xnorm, 0, (int32_t)c->N, c->stream));
+  HIPCHK(c, fsne::launch_drift_rows(a, c->moved, c->stream));
+  return refresh_affinities(c, false);
+}
+
+__global__ void k_narrow_ids(const int64_t* __restrict__ in, int32_t* __restrict__ out,
+                             int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = (int32_t)in[k];
+}
+
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The address of `scratch` on the current device, looked up once per device
+// (each GPU holds its own copy of the array).
+fsne_status bind_scratch(fsne_ctx* c) {
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(c, FSNE_EHIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(c, e, "scratch address");
+    g_scratch[dev] = p;
+  }
+  c->scratch = g_scratch[dev];
+  return FSNE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -468,7 +526,8 @@ fsne_status fsne_init(fsne_ctx** out, const void* X, int64_t N, int32_t D, int32
     }
     c->own_stream = true;
   }
-  st = do_init(c, X, x_on_device, Y0);
+  st = bind_scratch(c);
+  if (st == FSNE_OK) st = do_init(c, X, x_on_device, Y0);
   if (st != FSNE_OK) {
     release(c);
     delete c;
@@ -710,44 +769,58 @@ fsne_status fsne_drift_points(fsne_ctx* c, const int64_t* ids, const void* Xnew,
     hipError_t e;
     if ((e = hipMemcpyAsync(dids, ids32.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice,
                             c->stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(dx, Xnew, xrow * n, hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
-        (e = fsne::launch_scatter_rows(c->X, dx, dids, (int32_t)n, (int32_t)xrow, c->stream)) !=
-            hipSuccess) {
+        (e = hipMemcpyAsync(dx, Xnew, xrow * n, hipMemcpyHostToDevice, c->stream)) != hipSuccess) {
       st = hip_fail(c, e, "drift upload");
       break;
     }
-    if (Yinit) {
-      if ((st = put_Y(c, dy, Yinit, 0, n)) != FSNE_OK) break;
-      if ((e = fsne::launch_scatter_rows(c->Y, dy, dids, (int32_t)n,
-                                         (int32_t)(sizeof(float) * c->DP), c->stream)) !=
-          hipSuccess) {
-        st = hip_fail(c, e, "drift Y");
-        break;
-      }
-    }
-    if ((e = hipMemsetAsync(c->moved, 0, (size_t)c->N, c->stream)) != hipSuccess ||
-        (e = fsne::launch_mark_moved(c->moved, c->V, c->DP, dids, (int32_t)n, c->stream)) !=
-            hipSuccess) {
-      st = hip_fail(c, e, "drift marks");
-      break;
-    }
-    // moved rows change distances in both directions: every rejection is void
-    if ((st = clear_memo(c, 0, c->cap)) != FSNE_OK) break;
-    if ((st = refresh_unit_rows(c)) != FSNE_OK) break;
-    StepArgs a = make_args(c);
-    if (c->xdtype == FSNE_BF16 &&
-        (e = fsne::launch_xnorm(raw_args(c), c->xnorm, 0, (int32_t)c->N, c->stream)) !=
-            hipSuccess) {
-      st = hip_fail(c, e, "drift norms");
-      break;
-    }
-    if ((e = fsne::launch_drift_rows(a, c->moved, c->stream)) != hipSuccess) {
-      st = hip_fail(c, e, "drift rows");
-      break;
-    }
-    st = refresh_affinities(c, false);
+    if (Yinit && (st = put_Y(c, dy, Yinit, 0, n)) != FSNE_OK) break;
+    st = drift_apply(c, dids, dx, dy, n);
   } while (false);
   cleanup();
+  return st;
+}
+
+fsne_status fsne_drift_points_noalloc(fsne_ctx* c, const int64_t* ids, const void* Xnew,
+                                      int64_t n, const float* Yinit) {
+  if (!c) return FSNE_EINVAL;
+  if (!ids || !Xnew || n < 0)
+    return fail(c, FSNE_EINVAL, "bad arguments to fsne_drift_points_noalloc");
+  if (n == 0) return FSNE_OK;
+  if (!c->own_X) return fail(c, FSNE_ESTATE, "X is borrowed; create the context with capacity");
+  if (!c->scratch) return fail(c, FSNE_ESTATE, "no device scratch for this context's device");
+  for (int64_t k = 0; k < n; ++k) {
+    if (ids[k] < 0 || ids[k] >= c->N) return fail(c, FSNE_EINVAL, "drift id out of range");
+    if (k > 0 && ids[k] <= ids[k - 1])
+      return fail(c, FSNE_EINVAL, "drift ids must be strictly increasing");
+  }
+  const size_t xrow = (size_t)c->D * xbytes(c);
+  const size_t o_ids = 0, o_ids32 = align256(sizeof(int64_t) * n);
+  const size_t o_x = o_ids32 + align256(sizeof(int32_t) * n);
+  const size_t o_yh = o_x + align256(xrow * n);
+  const size_t o_y = o_yh + align256(sizeof(float) * n * c->d);
+  const size_t need = o_y + align256(sizeof(float) * n * c->DP);
+  if (need > kScratchBytes)
+    return fail(c, FSNE_EINVAL,
+                "drift batch too large for the fixed scratch: " + std::to_string(need) +
+                    " bytes needed, " + std::to_string(kScratchBytes) + " available");
+  uint8_t* w = static_cast<uint8_t*>(c->scratch);
+  int64_t* d64 = reinterpret_cast<int64_t*>(w + o_ids);
+  int32_t* dids = reinterpret_cast<int32_t*>(w + o_ids32);
+  uint8_t* dx = w + o_x;
+  float* dyh = reinterpret_cast<float*>(w + o_yh);
+  float* dy = Yinit ? reinterpret_cast<float*>(w + o_y) : nullptr;
+  HIPCHK(c, hipMemcpyAsync(d64, ids, sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_narrow_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                     d64, dids, n);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(dx, Xnew, xrow * n, hipMemcpyHostToDevice, c->stream));
+  if (Yinit) {
+    HIPCHK(c, hipMemcpyAsync(dyh, Yinit, sizeof(float) * n * c->d, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, fsne::launch_restride(dy, c->DP, dyh, c->d, n, c->d, c->DP, c->stream));
+  }
+  const fsne_status st = drift_apply(c, dids, dx, dy, n);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return st;
 }
 

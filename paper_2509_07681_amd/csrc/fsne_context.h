@@ -33,6 +33,7 @@ struct fsne_ctx {
   int32_t* memo = nullptr;   // cap x kMemo rejected HD candidates, -1 = empty
   float* Xu = nullptr;       // cap x D rows scaled to unit length (angular metric)
   uint8_t* rwork = nullptr;  // renumbering workspace (kept between calls)
+  void* scratch = nullptr;   // device address of the library's fixed staging array
   size_t rwork_bytes = 0;
   fsne::Scalars* sc = nullptr;
   std::string err;

@@ -73,6 +73,7 @@ def load_library(path: str = LIB_PATH):
     L.fsne_sync.argtypes = [P]
     L.fsne_insert_points.argtypes = [P, P, I64, P]
     L.fsne_drift_points.argtypes = [P, P, P, I64, P]
+    L.fsne_drift_points_noalloc.argtypes = [P, P, P, I64, P]
     L.fsne_implode.argtypes = [P, F]
     L.fsne_jump_start.argtypes = [P, I32, F]
     L.fsne_delete_points.argtypes = [P, P, I64]
@@ -87,7 +88,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("fsne_default_hparams", "fsne_init", "fsne_step", "fsne_set_hyperparams",
                  "fsne_get_hyperparams", "fsne_get_Y", "fsne_get_knn", "fsne_get_state",
                  "fsne_set_state", "fsne_get_stats", "fsne_sync", "fsne_insert_points",
-                 "fsne_drift_points", "fsne_implode", "fsne_jump_start", "fsne_delete_points",
+                 "fsne_drift_points", "fsne_drift_points_noalloc", "fsne_implode", "fsne_jump_start", "fsne_delete_points",
                  "fsne_cluster", "fsne_hierarchy_edges"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -256,6 +257,16 @@ def fsne_drift_points(ctx, ids, Xnew, Yinit=None):
     Xnew = np.ascontiguousarray(Xnew)
     Ya = None if Yinit is None else np.ascontiguousarray(Yinit, dtype=np.float32)
     _check(ctx, load_library().fsne_drift_points(ctx, _ptr(ids), _ptr(Xnew), ids.size, _ptr(Ya)))
+
+
+def fsne_drift_points_noalloc(ctx, ids, Xnew, Yinit=None):
+    """fsne_drift_points staged in the library's fixed device array (no device
+    allocation); ids strictly increasing."""
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    Xnew = np.ascontiguousarray(Xnew)
+    Ya = None if Yinit is None else np.ascontiguousarray(Yinit, dtype=np.float32)
+    _check(ctx, load_library().fsne_drift_points_noalloc(ctx, _ptr(ids), _ptr(Xnew), ids.size,
+                                                         _ptr(Ya)))
 
 
 def fsne_implode(ctx, factor: float):
