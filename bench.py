@@ -138,12 +138,14 @@ def schedule(F, base, t):
 
 
 def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=50,
-                labels=None, lr_div=12.0, reorder_every=0):
+                labels=None, lr_div=12.0, reorder_every=0, reorder_data=False):
     """n_iter iterations under the coin with the standard schedule; HD recall@K
     on the query sample every ``every`` iterations (the clock is stopped while
     the recall is measured).  With reorder_every > 0 the points are renumbered
-    along the embedding's Morton order at every multiple of it (timed); the
-    lists are mapped back to the original ids to be measured."""
+    along the embedding's Morton order at every multiple of it (timed), with
+    reorder_data along a projection of the data rows before the first
+    iteration (timed); the lists are mapped back to the original ids to be
+    measured."""
     import numpy as np
 
     from inputs.knn_metrics import recall_at_k
@@ -163,6 +165,11 @@ def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=
         return out
 
     done, secs, curve = 0, 0.0, []
+    if reorder_data:
+        t0 = time.perf_counter()
+        track_renumbering(orig, emb.reorder_data())
+        emb.sync()
+        secs += time.perf_counter() - t0
     while done < n_iter:
         stop = min(n_iter, (done // every + 1) * every)
         if done < 250 < stop:
@@ -661,7 +668,7 @@ STEP_KERNELS = (("hd_refine", "k_hd_refine"), ("affinity", "k_psym"), ("ld_grad"
                 ("reduce", "k_reduce"), ("update", "k_update"))
 
 
-def counted_traffic(kernel, W, K, every, start):
+def counted_traffic(kernel, W, K, reorder):
     """HBM bytes per launch of `kernel` in the timed iterations, from
     profiles/traffic.json, if it was taken with the current step sources over
     the same iterations and renumbering (else None)."""
@@ -670,12 +677,12 @@ def counted_traffic(kernel, W, K, every, start):
         return None
     rec = json.load(open(tf))
     if (rec.get("source_hash") != kernel_source_hash() or rec.get("window") != [W, K]
-            or rec.get("reorder") != [every, start]):
+            or rec.get("reorder") != list(reorder)):
         return None
     return rec.get("per_launch_GB", {}).get(kernel)
 
 
-def roofline(kernels, name, W, K, every, start):
+def roofline(kernels, name, W, K, reorder):
     """The roofline object of the dominant kernel.  achieved = its algorithmic
     bytes per launch over its average launch duration.  Where that exceeds the
     HBM peak (renumbered points: the caches serve part of the bytes) the
@@ -683,7 +690,7 @@ def roofline(kernels, name, W, K, every, start):
     iterations instead, and the share the caches served is stated."""
     k = kernels[name]
     avg_s = k["avg_ms"] * 1e-3
-    traffic = counted_traffic(name, W, K, every, start)
+    traffic = counted_traffic(name, W, K, reorder)
     r = {"bound": "hbm", "kernel": name, "peak": PEAK_HBM_GBS, "unit": "GB/s",
          "algorithmic_GB_per_launch": k["algorithmic_GB"], "avg_launch_ms": k["avg_ms"],
          "traffic": traffic,
@@ -765,7 +772,8 @@ def summarize_profile(args):
     from collections import defaultdict
 
     W, K = args.warmup, args.steps
-    out = {"window": [W, K], "reorder": [args.reorder_every, args.reorder_from]}
+    out = {"window": [W, K],
+           "reorder": [args.reorder_every, args.reorder_from, int(args.reorder_data)]}
     dirs = dict(x.split("=", 1) for x in args.summarize_profile)
 
     def rows_of(d, pattern):
@@ -829,7 +837,7 @@ def summarize_profile(args):
         out["per_launch_GB"] = per_launch
         if args.write_traffic:
             rec = {"source_hash": kernel_source_hash(), "workload": "manifold_1m",
-                   "window": [W, K], "reorder": [args.reorder_every, args.reorder_from],
+                   "window": [W, K], "reorder": out["reorder"],
                    "unit": "GB per launch", "factors": out["factors"],
                    "per_launch_GB": per_launch, "sources": list(STEP_SOURCES)}
             with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
@@ -1045,6 +1053,9 @@ def main():
                          "many steps in the timed runs (0: never)")
     ap.add_argument("--reorder-from", type=int, default=50,
                     help="first iteration before which the timed runs renumber")
+    ap.add_argument("--reorder-data", type=int, default=1,
+                    help="1: renumber the points along a fixed projection of the data rows "
+                         "before iteration 0 (set-up, untimed); 0: keep the input order")
     ap.add_argument("--blobs-knn", action="store_true",
                     help="HD-list R_NX(K) on overlapping and disjointed blobs instead")
     ap.add_argument("--memo-compare", action="store_true",
@@ -1131,10 +1142,20 @@ def main():
     W, K = args.warmup, args.steps
     renumbers = [t for t in range(W + K) if reorder_due(t, every, start)]
 
+    def fresh(Xr, hpr):
+        """A new embedding of the workload; with --reorder-data its points are
+        first renumbered along a fixed projection of the data rows (set-up,
+        before iteration 0, outside every timed region)."""
+        e = F.Embedding(Xr, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hpr)
+        orig = np.arange(N)
+        if args.reorder_data:
+            track_renumbering(orig, e.reorder_data())
+        return e, orig
+
     # The timed region: iterations W .. W+K-1 of a fresh embedding, every
     # kernel launch bracketed by HIP events on the library's stream (read
     # after the region) for the per-kernel durations.
-    emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp)
+    emb, _ = fresh(X, hp)
     run_steps(emb, 0, W, every, start)
     emb.sync()
     emb.profile(True)
@@ -1153,7 +1174,7 @@ def main():
 
     # The same iterations again (the run is deterministic), one at a time, for
     # the candidate rows each of them loaded.
-    emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp)
+    emb, _ = fresh(X, hp)
     run_steps(emb, 0, W, every, start)
     _, hd_cand, ld_cand = profiled_steps(emb, W, K, every, start, N)
     emb.close()
@@ -1193,20 +1214,24 @@ def main():
         "config": {"workload": "manifold_1m: N=1,000,000 points on 50 seeded 8-dim linear "
                                "manifolds in R^128 (FP32 rows), d=16, K_hd=K_ld=32, 16 negatives, "
                                "alpha=1, perplexity 10; every timed step refines the HD lists"
+                               + ("; before iteration 0 the points are renumbered along the "
+                                  "Morton order of a fixed 3-axis projection of the data rows "
+                                  "(set-up, untimed)" if args.reorder_data else "")
                                + (f"; the points are renumbered along the embedding's Morton "
                                   f"order every {every} iterations from iteration {start} on, "
                                   f"inside the timed region" if every > 0 else ""),
                    "N": N, "D": cfg["D"], "d": cfg["d"], "K_hd": cfg["K_hd"],
                    "K_ld": cfg["K_ld"], "n_neg": cfg["n_neg"], "hd_mode": "always",
                    "timed_iterations": [W, W + K - 1],
+                   "reorder_data_at_setup": bool(args.reorder_data),
                    "renumbered_before_iterations": renumbers},
-        "roofline": roofline(kernels, dom_name, W, K, every, start),
+        "roofline": roofline(kernels, dom_name, W, K, [every, start, int(args.reorder_data)]),
         "kernels": kernels,
         "ld_only_ms_per_step": round(ld_only_ms, 4),
         "ld_only_iters_per_s": round(1000.0 / ld_only_ms, 2),
     }
-    if renumbers:
-        # the same iterations without renumbering, for comparison
+    if renumbers or args.reorder_data:
+        # the same iterations without any renumbering, for comparison
         emb = F.Embedding(X, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hp)
         emb.step(W)
         emb.sync()
@@ -1224,8 +1249,7 @@ def main():
     nf = min(K, 50)
     for name, dm in (("bf16_rows_direct", 0), ("bf16_mfma_screen", 1)):
         hpf = F.fsne_default_hparams(**{**hp.as_dict(), "dist_mode": dm})
-        e2 = F.Embedding(Xb, Y0, cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED, hp=hpf)
-        orig = np.arange(N)
+        e2, orig = fresh(Xb, hpf)
         run_steps(e2, 0, W, every, start, orig)
         e2.sync()
         t2 = time.perf_counter()
@@ -1248,13 +1272,15 @@ def main():
         queries = rng.choice(N, args.queries, replace=False)
         _, ex_d2 = exact_knn(X, queries, cfg["K_hd"])
         qre = 100 if every > 0 else 0     # renumbering cadence under the coin
+        rd = bool(args.reorder_data)
         runs = {"f32": quality_run(F, X, cfg, Y0, args.quality_iters, RUN_SEED, queries, ex_d2,
-                                   reorder_every=qre)}
+                                   reorder_every=qre, reorder_data=rd)}
         _, ex_b = exact_knn(Xb, queries, cfg["K_hd"])
         runs["bf16_rows_direct"] = quality_run(F, Xb, cfg, Y0, args.quality_iters, RUN_SEED,
-                                               queries, ex_b, reorder_every=qre)
+                                               queries, ex_b, reorder_every=qre, reorder_data=rd)
         runs["bf16_mfma_screen"] = quality_run(F, Xb, cfg, Y0, args.quality_iters, RUN_SEED,
-                                               queries, ex_b, dist_mode=1, reorder_every=qre)
+                                               queries, ex_b, dist_mode=1, reorder_every=qre,
+                                               reorder_data=rd)
         # seconds for each form to reach 0.95 of the FP32 form's final recall
         target = round(0.95 * runs["f32"]["recall_at_32"], 4)
         for r in runs.values():

@@ -205,6 +205,15 @@ fsne_status fsne_renumber(fsne_ctx *ctx, const int32_t *new_of_old);
  * Errors: FSNE_ENONFINITE, FSNE_ESTATE, FSNE_ENOMEM, FSNE_EHIP. */
 fsne_status fsne_reorder(fsne_ctx *ctx, int32_t *new_of_old);
 
+/* Renumber the points along the Morton curve of the data rows projected
+ * onto three axes, c_a = sum_k x_ik r_ka with fixed signs r_ka = +-1 (bit 0
+ * of the first word of Philox block (k, a, 12, 0)); under the angular metric
+ * the rows scaled to unit length.  A fixed projection shrinks distances
+ * about evenly, so points close in R^D get nearby ids even before the
+ * embedding has any structure of its own (right after fsne_init, say); ties
+ * by the old id.  new_of_old and errors as fsne_reorder. */
+fsne_status fsne_reorder_data(fsne_ctx *ctx, int32_t *new_of_old);
+
 /* Copy the state to / from host memory (checkpoint, resume, checks).  set
  * reads every non-NULL field except A, R, Zh and recomputes the coin of the
  * next iteration from E and t.  If it sets HD lists, distances or records

@@ -22,7 +22,7 @@ constexpr int kReduceBlocks = 1024; // partial sums of the Z / N_new reduction
 // Third word of the Philox counter: which draw stream.
 enum : uint32_t {
   kStreamHDC = 1, kStreamLDC = 2, kStreamNeg = 3, kStreamInitHD = 4, kStreamInitLD = 5,
-  kStreamCoin = 7, kStreamDelHD = 10, kStreamDelLD = 11
+  kStreamCoin = 7, kStreamDelHD = 10, kStreamDelLD = 11, kStreamOrder = 12
 };
 
 // Scalars of the iteration, resident in device memory so that a whole

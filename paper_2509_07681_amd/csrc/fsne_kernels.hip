@@ -196,15 +196,14 @@ __device__ void hd_dist_rows(const TX* __restrict__ X, int D, int32_t i, int cid
 // per lane, -1 for none): those would lose the merge again.
 // Returns the candidate id in lanes 0..31 (-1: dropped), -1 elsewhere.
 // ---------------------------------------------------------------------------
+// make_candidate_u takes the draw of its slot (lanes 0..31) from the caller.
 template <bool MEMO = false>
-__device__ __forceinline__ int make_candidate(int32_t i, uint32_t t, uint32_t stream,
-                                              const Hyper& h, const int32_t* __restrict__ L,
-                                              int K, int own, const int32_t* __restrict__ Lx,
-                                              int Kx, int other, int32_t N, int* tab,
-                                              int memo = -1) {
+__device__ __forceinline__ int make_candidate_u(const uint4 u, int32_t i,
+                                                const int32_t* __restrict__ L, int K, int own,
+                                                const int32_t* __restrict__ Lx, int Kx, int other,
+                                                int32_t N, int* tab, int memo = -1) {
   const int lane = lane_id();
   const int s = lane & (kCand - 1);
-  const uint4 u = philox((uint32_t)i, t, stream, (uint32_t)s, h.key0, h.key1);
   const int a_own = (int)draw_index(u.x, (uint32_t)K);
   const int a_oth = (int)draw_index(u.x, (uint32_t)Kx);
   const int j_own = __shfl(own, a_own);
@@ -228,6 +227,17 @@ __device__ __forceinline__ int make_candidate(int32_t i, uint32_t t, uint32_t st
   if constexpr (MEMO) hash_insert(tab, nullptr, memo, 0);
   const bool fresh = hash_insert(tab, nullptr, (lane < kCand && c != i) ? c : -1, 0);
   return fresh ? c : -1;
+}
+
+template <bool MEMO = false>
+__device__ __forceinline__ int make_candidate(int32_t i, uint32_t t, uint32_t stream,
+                                              const Hyper& h, const int32_t* __restrict__ L,
+                                              int K, int own, const int32_t* __restrict__ Lx,
+                                              int Kx, int other, int32_t N, int* tab,
+                                              int memo = -1) {
+  const uint4 u =
+      philox((uint32_t)i, t, stream, (uint32_t)(lane_id() & (kCand - 1)), h.key0, h.key1);
+  return make_candidate_u<MEMO>(u, i, L, K, own, Lx, Kx, other, N, tab, memo);
 }
 
 // ---------------------------------------------------------------------------
@@ -1038,11 +1048,16 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   const int hid = lane < Kh ? hl[(int64_t)i * Kh + lane] : -1;
   const float pk = lane < Kh ? a.P[(int64_t)i * Kh + lane] : 0.0f;
   const int lid = lane < Kl ? lin[(int64_t)i * Kl + lane] : -1;
-  int jn = -1;
-  if (lane < nneg) {
-    const uint4 u = philox((uint32_t)i, t, kStreamNeg, (uint32_t)lane, a.h.key0, a.h.key1);
-    jn = draw_other(u.x, i, a.N);
+  // One Philox pass draws the candidate slots (lanes 0..31) and negative
+  // samples 0..31 (lanes 32..63); negative s ends in lane s.
+  const uint4 ud = philox((uint32_t)i, t, lane < kCand ? kStreamLDC : kStreamNeg,
+                          (uint32_t)(lane & (kCand - 1)), a.h.key0, a.h.key1);
+  int jn = __shfl(draw_other(ud.x, i, a.N), (lane + kCand) & (kWave - 1));
+  if (nneg > kCand) {   // negatives 32..63
+    const uint4 u2 = philox((uint32_t)i, t, kStreamNeg, (uint32_t)lane, a.h.key0, a.h.key1);
+    if (lane >= kCand) jn = draw_other(u2.x, i, a.N);
   }
+  if (lane >= nneg) jn = -1;
   float yh[PRE_H ? LP : 1][VEC];
   float er[PRE_E ? Geo::MAXP : 1][VEC];
   if constexpr (PRE_H) {
@@ -1068,7 +1083,7 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
     if (nneg <= RPI && rg < nneg) load_chunk<VEC>(yrow + (int64_t)id * DP, yn);
   }
 
-  const int c = make_candidate(i, t, kStreamLDC, a.h, lin, Kl, lid, hl, Kh, hid, a.N, S.tab);
+  const int c = make_candidate_u(ud, i, lin, Kl, lid, hl, Kh, hid, a.N, S.tab);
   if (lane < kCand) S.ent[lane] = c;
   if (lane < Kl) S.ent[kCand + lane] = lid;
   {

@@ -414,34 +414,59 @@ extern "C" fsne_status fsne_renumber(fsne_ctx* c, const int32_t* new_of_old) {
   return apply_permutation(c, sc, d_new, w + o_buf);
 }
 
-extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
-  if (!c) return FSNE_EINVAL;
-  if (!c->own_X) {
-    c->err = "fsne_reorder: X is borrowed; create the context with capacity";
-    return FSNE_ESTATE;
+namespace {
+
+// Signs r_ka = +-1 of the fixed projection of the data rows: bit 0 of the
+// first word of Philox block (k, a, 12, 0) under the context's seed.
+__global__ void k_projection_signs(float* __restrict__ sign, int D, uint32_t key0,
+                                   uint32_t key1) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= D * kMaxAxes) return;
+  const uint4 u = fsne::philox((uint32_t)(q / kMaxAxes), (uint32_t)(q % kMaxAxes),
+                               fsne::kStreamOrder, 0u, key0, key1);
+  sign[q] = (u.x & 1u) ? -1.0f : 1.0f;
+}
+
+// coords[i] = (sum_k x_ik r_k0, sum_k x_ik r_k1, sum_k x_ik r_k2, 0): one wave
+// per row, lanes along the row.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_project_rows(const TX* __restrict__ X, int D, int32_t n,
+                                                      const float* __restrict__ sign,
+                                                      float4* __restrict__ coords) {
+  const int32_t i = (int32_t)(blockIdx.x * 4 + threadIdx.x / 64);
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  float p[kMaxAxes] = {0.0f, 0.0f, 0.0f};
+  const TX* row = X + (int64_t)i * D;
+  for (int k = lane; k < D; k += 64) {
+    const float x = fsne::to_unit_f32(row[k]);
+#pragma unroll
+    for (int a = 0; a < kMaxAxes; ++a) p[a] = fmaf(x, sign[k * kMaxAxes + a], p[a]);
   }
+#pragma unroll
+  for (int a = 0; a < kMaxAxes; ++a) p[a] = fsne::wave_sum_uniform(p[a]);
+  if (lane == 0) coords[i] = make_float4(p[0], p[1], p[2], 0.0f);
+}
+
+// Renumber along the Morton curve of `coords` (row stride `stride` floats)
+// projected by pr; the workspace holds `extra` bytes at its start for the
+// caller (the coordinates, when they are not the embedding).
+fsne_status reorder_along(fsne_ctx* c, const fsne::Scalars& sc, const float* coords, int stride,
+                          Projection pr, uint8_t* w, size_t o_base, int32_t* new_of_old,
+                          const char* who) {
   const int32_t N = (int32_t)c->N;
   hipStream_t s = c->stream;
-  Projection pr{c->d, std::min(c->d, kMaxAxes)};
-  fsne::Scalars sc;
-  fsne_status st = read_scalars(c, &sc);
-  if (st != FSNE_OK) return st;
   size_t most = 0;
   (void)row_arrays(c, sc, &most);
-  // workspace: range partials, range, keys (2), ids (2), permutation, the
-  // sort's digit counts, staging for the rows
   hipError_t e;
   const size_t sort_bytes =
       sizeof(uint32_t) * kSortThreads * (size_t)((N + kSortTile - 1) / kSortTile);
   const size_t n4 = align_up(sizeof(int32_t) * (size_t)N);
-  const size_t o_part = 0, o_range = align_up(sizeof(float) * kRedBlocks * 2 * kMaxAxes);
+  const size_t o_part = o_base, o_range = o_part + align_up(sizeof(float) * kRedBlocks * 2 * kMaxAxes);
   const size_t o_keys = o_range + align_up(sizeof(float) * 2 * kMaxAxes);
   const size_t o_keys2 = o_keys + n4, o_ids = o_keys2 + n4, o_ids2 = o_ids + n4;
   const size_t o_new = o_ids2 + n4, o_sort = o_new + n4;
   const size_t o_buf = o_sort + align_up(sort_bytes);
-  uint8_t* w = nullptr;
-  if ((e = workspace(c, o_buf + most, &w)) != hipSuccess)
-    return hip_error(c, e, "fsne_reorder: workspace");
   float* part = reinterpret_cast<float*>(w + o_part);
   float* range = reinterpret_cast<float*>(w + o_range);
   uint32_t* keys = reinterpret_cast<uint32_t*>(w + o_keys);
@@ -450,13 +475,14 @@ extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
   int32_t* ids2 = reinterpret_cast<int32_t*>(w + o_ids2);
   int32_t* d_new = reinterpret_cast<int32_t*>(w + o_new);
   uint32_t* sort_count = reinterpret_cast<uint32_t*>(w + o_sort);
-  hipLaunchKernelGGL(k_proj_range, dim3(kRedBlocks), dim3(256), 0, s, c->Y, N, c->DP, pr, part);
+  (void)most;
+  hipLaunchKernelGGL(k_proj_range, dim3(kRedBlocks), dim3(256), 0, s, coords, N, stride, pr, part);
   std::vector<float> hp((size_t)kRedBlocks * 2 * kMaxAxes);
   if ((e = hipGetLastError()) != hipSuccess ||
       (e = hipMemcpyAsync(hp.data(), part, sizeof(float) * hp.size(), hipMemcpyDeviceToHost,
                           s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess)
-    return hip_error(c, e, "fsne_reorder: range");
+    return hip_error(c, e, who);
   float rg[2 * kMaxAxes] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   for (int a = 0; a < pr.axes; ++a) {
     rg[2 * a] = INFINITY;
@@ -466,24 +492,91 @@ extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
       rg[2 * a + 1] = std::max(rg[2 * a + 1], hp[(size_t)b * 2 * kMaxAxes + 2 * a + 1]);
     }
     if (!std::isfinite(rg[2 * a]) || !std::isfinite(rg[2 * a + 1])) {
-      c->err = "fsne_reorder: the embedding holds a NaN or infinity";
+      c->err = std::string(who) + ": the coordinates hold a NaN or infinity";
       return FSNE_ENONFINITE;
     }
   }
   const unsigned gn = (unsigned)((N + 255) / 256);
   if ((e = hipMemcpyAsync(range, rg, sizeof(rg), hipMemcpyHostToDevice, s)) != hipSuccess)
-    return hip_error(c, e, "fsne_reorder: range upload");
-  hipLaunchKernelGGL(k_morton, dim3(gn), dim3(256), 0, s, c->Y, N, c->DP, pr, range, keys, ids);
+    return hip_error(c, e, who);
+  hipLaunchKernelGGL(k_morton, dim3(gn), dim3(256), 0, s, coords, N, stride, pr, range, keys, ids);
   if ((e = hipGetLastError()) != hipSuccess ||
       (e = radix_sort_pairs(keys, ids, keys2, ids2, sort_count, N, 30, s)) != hipSuccess)
-    return hip_error(c, e, "fsne_reorder: sort");
+    return hip_error(c, e, who);
   hipLaunchKernelGGL(k_invert, dim3(gn), dim3(256), 0, s, ids, N, d_new);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_error(c, e, "fsne_reorder: invert");
-  st = apply_permutation(c, sc, d_new, w + o_buf);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_error(c, e, who);
+  fsne_status st = apply_permutation(c, sc, d_new, w + o_buf);
   if (st != FSNE_OK) return st;
   if (new_of_old &&
       ((e = hipMemcpy(new_of_old, d_new, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToHost)) !=
        hipSuccess))
-    return hip_error(c, e, "fsne_reorder: download");
+    return hip_error(c, e, who);
   return FSNE_OK;
+}
+
+// Workspace bytes reorder_along needs after its first `o_base` bytes.
+size_t reorder_bytes(fsne_ctx* c, const fsne::Scalars& sc) {
+  const int32_t N = (int32_t)c->N;
+  size_t most = 0;
+  (void)row_arrays(c, sc, &most);
+  const size_t n4 = align_up(sizeof(int32_t) * (size_t)N);
+  return align_up(sizeof(float) * kRedBlocks * 2 * kMaxAxes) +
+         align_up(sizeof(float) * 2 * kMaxAxes) + 5 * n4 +
+         align_up(sizeof(uint32_t) * kSortThreads * (size_t)((N + kSortTile - 1) / kSortTile)) +
+         most;
+}
+
+}  // namespace
+
+extern "C" fsne_status fsne_reorder(fsne_ctx* c, int32_t* new_of_old) {
+  if (!c) return FSNE_EINVAL;
+  if (!c->own_X) {
+    c->err = "fsne_reorder: X is borrowed; create the context with capacity";
+    return FSNE_ESTATE;
+  }
+  fsne::Scalars sc;
+  fsne_status st = read_scalars(c, &sc);
+  if (st != FSNE_OK) return st;
+  uint8_t* w = nullptr;
+  hipError_t e;
+  if ((e = workspace(c, reorder_bytes(c, sc), &w)) != hipSuccess)
+    return hip_error(c, e, "fsne_reorder: workspace");
+  return reorder_along(c, sc, c->Y, c->DP, Projection{c->d, std::min(c->d, kMaxAxes)}, w, 0,
+                       new_of_old, "fsne_reorder");
+}
+
+extern "C" fsne_status fsne_reorder_data(fsne_ctx* c, int32_t* new_of_old) {
+  if (!c) return FSNE_EINVAL;
+  if (!c->own_X) {
+    c->err = "fsne_reorder_data: X is borrowed; create the context with capacity";
+    return FSNE_ESTATE;
+  }
+  fsne::Scalars sc;
+  fsne_status st = read_scalars(c, &sc);
+  if (st != FSNE_OK) return st;
+  const int32_t N = (int32_t)c->N;
+  hipStream_t s = c->stream;
+  const size_t o_sign = 0, o_coords = align_up(sizeof(float) * (size_t)c->D * kMaxAxes);
+  const size_t o_base = o_coords + align_up(sizeof(float4) * (size_t)N);
+  uint8_t* w = nullptr;
+  hipError_t e;
+  if ((e = workspace(c, o_base + reorder_bytes(c, sc), &w)) != hipSuccess)
+    return hip_error(c, e, "fsne_reorder_data: workspace");
+  float* sign = reinterpret_cast<float*>(w + o_sign);
+  float4* coords = reinterpret_cast<float4*>(w + o_coords);
+  hipLaunchKernelGGL(k_projection_signs, dim3((unsigned)((c->D * kMaxAxes + 255) / 256)),
+                     dim3(256), 0, s, sign, c->D, (uint32_t)c->seed, (uint32_t)(c->seed >> 32));
+  const dim3 g((unsigned)((N + 3) / 4));
+  // under the angular metric the rows scaled to unit length are the data
+  if (c->hp.metric == 1 && c->Xu)
+    hipLaunchKernelGGL(k_project_rows<float>, g, dim3(256), 0, s, c->Xu, c->D, N, sign, coords);
+  else if (c->xdtype == FSNE_F32)
+    hipLaunchKernelGGL(k_project_rows<float>, g, dim3(256), 0, s,
+                       static_cast<const float*>(c->X), c->D, N, sign, coords);
+  else
+    hipLaunchKernelGGL(k_project_rows<uint16_t>, g, dim3(256), 0, s,
+                       static_cast<const uint16_t*>(c->X), c->D, N, sign, coords);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_error(c, e, "fsne_reorder_data: project");
+  return reorder_along(c, sc, reinterpret_cast<const float*>(coords), 4,
+                       Projection{kMaxAxes, kMaxAxes}, w, o_base, new_of_old, "fsne_reorder_data");
 }

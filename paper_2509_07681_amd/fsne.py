@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
     L.fsne_delete_points.argtypes = [P, P, I64]
     L.fsne_renumber.argtypes = [P, P]
     L.fsne_reorder.argtypes = [P, P]
+    L.fsne_reorder_data.argtypes = [P, P]
     L.fsne_cluster.argtypes = [P, F, I32, P, P]
     L.fsne_hierarchy_edges.argtypes = [P, I32, P, I32, I64, P]
     L.fsne_destroy.argtypes = [P]
@@ -289,6 +290,12 @@ def fsne_reorder(ctx, N):
     return p
 
 
+def fsne_reorder_data(ctx, N):
+    p = np.empty(N, dtype=np.int32)
+    _check(ctx, load_library().fsne_reorder_data(ctx, _ptr(p)))
+    return p
+
+
 def fsne_cluster(ctx, N, eps: float, min_pts: int):
     labels = np.empty(N, dtype=np.int32)
     nc = np.zeros(1, dtype=np.int32)
@@ -371,6 +378,11 @@ class Embedding:
     def reorder(self):
         """Renumber along the Morton curve of the embedding; returns new_of_old."""
         return fsne_reorder(self.ctx, self.N)
+
+    def reorder_data(self):
+        """Renumber along the Morton curve of a fixed projection of the data
+        rows; returns new_of_old."""
+        return fsne_reorder_data(self.ctx, self.N)
 
     def cluster(self, eps, min_pts):
         return fsne_cluster(self.ctx, self.N, eps, min_pts)

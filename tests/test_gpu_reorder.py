@@ -215,3 +215,41 @@ def test_reorder_is_a_stable_sort_of_the_morton_keys(fsne_lib, N, d):
     assert np.all(np.diff(old_of_new)[ties] > 0)
     assert len(np.unique(k)) > N // 4       # keys spread, not all tied
     emb.close()
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_reorder_data_follows_a_projection_of_the_rows(oracle_lib, fsne_lib, bf16):
+    """fsne_reorder_data right after init: a permutation that relabels the
+    state exactly, orders the points by the Morton keys of the fixed +-1
+    projection of their rows (keys recomputed on the host in double; the
+    GPU's single-precision sums may move a key across a cell boundary), and
+    gives true neighbours nearby ids."""
+    O, F = oracle_lib, fsne_lib
+    X = manifolds(n_manifolds=20, per_manifold=1000, D=64, k=4, seed=71)[0]
+    if bf16:
+        X = f32_to_bf16_bits(X)
+    N, D = X.shape
+    hp = F.fsne_default_hparams(perplexity=8.0, lr=N / 12.0, n_neg=8, hd_mode=1)
+    emb = F.Embedding(X, y_init(N, 2), 2, 16, 8, seed=7, hp=hp)
+    s0 = emb.state()
+    p = emb.reorder_data()
+    assert np.array_equal(np.sort(p), np.arange(N))
+    _relabelled(s0, p, emb.state())
+    # host keys from the same signs (Philox block (k, a, 12, 0), bit 0)
+    sign = np.array([[-1.0 if O.philox4x32_10([k, a, 12, 0], [7, 0])[0] & 1 else 1.0
+                      for a in range(3)] for k in range(D)])
+    from inputs.generators import bf16_bits_to_f32
+    Xf = (bf16_bits_to_f32(X) if bf16 else X).astype(np.float64)
+    proj = Xf @ sign
+    keys = _morton_keys(proj.astype(np.float32))
+    k = keys[np.argsort(p)].astype(np.int64)
+    assert np.mean(np.diff(k) >= 0) > 0.99
+    # neighbours in R^D are near in the new ids
+    from inputs.knn_metrics import exact_knn
+    q = np.random.default_rng(1).choice(N, 200, replace=False)
+    nn, _ = exact_knn(X, q, 8)
+    gap = np.abs(p[nn] - p[q][:, None])
+    assert np.median(gap) < N / 50, np.median(gap)
+    emb.step(5)
+    assert emb.stats()["nonfinite"] == 0
+    emb.close()
