@@ -264,13 +264,15 @@ def feedback_run(F, args):
     from inputs.knn_metrics import exact_knn, rnx_auc, rnx_curve
 
     X, _, cfg = make_workload("manifold_1m", N=args.fb_n)
-    N, K = X.shape[0], cfg["K_hd"]
+    N, K = X.shape[0], args.fb_k
+    perp = cfg["perplexity"] if K <= 32 else float(args.fb_perplexity)
     rng = np.random.default_rng(11)
     q = np.sort(rng.choice(N, min(1000, N), replace=False))
     ex, _ = exact_knn(X, q, K)
-    out = {"metric": "HD-list AUC of R_NX(K), K=1..32, fixed vs optimised embedding",
-           "config": {"workload": f"manifold rows, N={N}, D=128 FP32, K_hd=K_ld=32, 16 negatives, "
-                                  f"alpha=1, perplexity 10, HD refinement by the coin",
+    out = {"metric": f"HD-list AUC of R_NX(K), K=1..{K}, fixed vs optimised embedding",
+           "config": {"workload": f"manifold rows, N={N}, D=128 FP32, K_hd={K}, "
+                                  f"K_ld={cfg['K_ld']}, 16 negatives, alpha=1, perplexity {perp}, "
+                                  "HD refinement by the coin",
                       "iters": args.fb_iters, "every": args.fb_every, "queries": int(q.size)},
            "curves": {}}
     # jump start: two random projections, each held for js iterations at
@@ -279,8 +281,8 @@ def feedback_run(F, args):
     for d in (2, 8):
         for mode in ("fixed", "optimised", "jumpstart"):
             lr = 0.0 if mode == "fixed" else N / 12.0
-            base = dict(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=lr,
-                        n_neg=cfg["n_neg"], hd_mode=0)
+            base = dict(alpha=cfg["alpha"], perplexity=perp, lr=lr, n_neg=cfg["n_neg"],
+                        hd_mode=0)
             emb = F.Embedding(X, y_init(N, d), d, K, cfg["K_ld"], seed=RUN_SEED,
                               hp=schedule(F, base, 0))
             t0 = 2 * js if mode == "jumpstart" else 0   # where the schedule starts
@@ -313,11 +315,12 @@ def blobs_knn_run(F, args):
     neighbour finding in Sec. 4.1, without its NN-descent side): 'overlapping',
     5 Gaussian blobs whose centres lie close together against their spread,
     and 'disjointed', 1000 blobs of 30 points far apart against their spread.
-    N = 30,000, D = 50, d = 2, K_hd = K_ld = 32, 16 negatives, alpha = 1,
-    perplexity 10, the standard schedule, the HD refinement by the coin.
-    R_NX(K), K = 1 .. 32, of the HD lists against the exact neighbours of
-    3,000 query points: its mean and its spread (standard deviation) across
-    the points, at iterations 3000 and 9000."""
+    N = 30,000, D = 50, d = 2, K_hd = --fb-k (256 by default), K_ld = 32, 16
+    negatives, alpha = 1, perplexity --fb-perplexity (10 for K_hd = 32), the
+    standard schedule, the HD refinement by the coin.  R_NX(K), K = 1 .. K_hd,
+    of the HD lists against the exact neighbours of 3,000 query points: its
+    mean and its spread (standard deviation) across the points, at iterations
+    3000 and 9000."""
     import numpy as np
 
     from inputs.generators import RUN_SEED, blobs, y_init
@@ -325,11 +328,14 @@ def blobs_knn_run(F, args):
 
     sets = {"overlapping": dict(n_clusters=5, per_cluster=6000, mean_var=0.25, seed=1021),
             "disjointed": dict(n_clusters=1000, per_cluster=30, mean_var=100.0, seed=1023)}
+    Kh = args.fb_k
+    perp = 10.0 if Kh <= 32 else float(args.fb_perplexity)
     out = {"metric": "HD-list R_NX(K), mean and spread across points, at 3000 and 9000 iterations",
            "config": {"workload": "Gaussian blobs, N=30,000, D=50 FP32 (overlapping: 5 blobs, "
                                   "centres N(0, 0.25 I); disjointed: 1000 blobs of 30, centres "
-                                  "N(0, 100 I); unit spread in both), d=2, K_hd=K_ld=32, "
-                                  "16 negatives, alpha=1, perplexity 10, HD refinement by the coin",
+                                  f"N(0, 100 I); unit spread in both), d=2, K_hd={Kh}, K_ld=32, "
+                                  f"16 negatives, alpha=1, perplexity {perp}, HD refinement by "
+                                  "the coin",
                       "queries": 3000},
            "sets": {}}
     for name, kw in sets.items():
@@ -337,9 +343,9 @@ def blobs_knn_run(F, args):
         N = X.shape[0]
         rng = np.random.default_rng(13)
         q = np.sort(rng.choice(N, 3000, replace=False))
-        ex, _ = exact_knn(X, q, 32)
-        base = dict(alpha=1.0, perplexity=10.0, lr=N / 12.0, n_neg=16, hd_mode=0)
-        emb = F.Embedding(X, y_init(N, 2), 2, 32, 32, seed=RUN_SEED, hp=schedule(F, base, 0))
+        ex, _ = exact_knn(X, q, Kh)
+        base = dict(alpha=1.0, perplexity=perp, lr=N / 12.0, n_neg=16, hd_mode=0)
+        emb = F.Embedding(X, y_init(N, 2), 2, Kh, 32, seed=RUN_SEED, hp=schedule(F, base, 0))
         res, done, secs = {}, 0, 0.0
         for stop in (250, 3000, 9000):
             emb.sync()
@@ -1068,6 +1074,10 @@ def main():
     ap.add_argument("--write-traffic", action="store_true",
                     help="with --summarize-profile: write profiles/traffic.json")
     ap.add_argument("--fb-n", type=int, default=50000)
+    ap.add_argument("--fb-k", type=int, default=256,
+                    help="HD list length of the feedback and blob experiments (R_NX up to it)")
+    ap.add_argument("--fb-perplexity", type=float, default=50.0,
+                    help="perplexity of those experiments when --fb-k > 32")
     ap.add_argument("--fb-iters", type=int, default=2000)
     ap.add_argument("--fb-every", type=int, default=100)
     ap.add_argument("--dynamic", action="store_true",

@@ -139,7 +139,10 @@ fsne_status fsne_default_hparams(fsne_hparams *hp);
  *             must outlive the context (it is read, never written).
  *   Y0        N x d initial embedding, host memory (NULL: all zeros).
  *   d, K_hd, K_ld  embedding dimension and list lengths:
- *             1 <= d <= 64, 2 <= K_hd <= 64, 1 <= K_ld <= 64, K_hd, K_ld < N.
+ *             1 <= d <= 64, 2 <= K_hd <= 256, 1 <= K_ld <= 64, K_hd, K_ld < N.
+ *             HD lists longer than 64 (held in LDS, one point per wave)
+ *             take direct distances only (dist_mode 0) and no drift,
+ *             delete or metric switch (those return FSNE_EINVAL).
  *   alpha     tail of the LD kernel (eq. (4)), > 0; replaces hp->alpha.
  *   perplexity  of the HD affinities (eq. (1)), 1 < perplexity < K_hd;
  *             replaces hp->perplexity.

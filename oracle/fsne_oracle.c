@@ -334,9 +334,9 @@ static void psym_row_from(int64_t i, const int32_t *idx, const double *d2, int32
 void fsneo_psym_row(const fsneo_state *S, int64_t i, double *out)
 {
     const int32_t K = S->K_hd;
-    const int32_t *rows[64];
-    double recs[64][4];
-    const double *recp[64];
+    const int32_t *rows[FSNEO_KMAX];
+    double recs[FSNEO_KMAX][4];
+    const double *recp[FSNEO_KMAX];
     for (int32_t k = 0; k < K; ++k) {
         int64_t j = S->hd_idx[i * K + k];
         rows[k] = S->hd_idx + j * K;
@@ -416,7 +416,7 @@ void fsneo_hd_refine_point(const fsneo_state *S, int64_t i, uint32_t t, int32_t 
     int64_t cand[FSNEO_C];
     rows_t L = {S->hd_idx, K, 0, NULL, NULL}, Lx = {S->ld_idx, S->K_ld, 0, NULL, NULL};
     int nc = gather_candidates(i, t, FSNEO_S_HDC, S->seed, &L, &Lx, S->N, cand);
-    entry e[64 + FSNEO_C];
+    entry e[FSNEO_KMAX + FSNEO_C];
     for (int32_t k = 0; k < K; ++k) {
         e[k].key = S->hd_d2[i * K + k];
         e[k].idx = S->hd_idx[i * K + k];
@@ -456,7 +456,7 @@ static void ld_point(const fsneo_state *S, const fsneo_hp *hp, int64_t i, uint32
     int64_t cand[FSNEO_C];
     rows_t L = {S->ld_idx, K, 0, NULL, NULL};
     int nc = gather_candidates(i, t, FSNEO_S_LDC, S->seed, &L, hd_next, S->N, cand);
-    entry e[64 + FSNEO_C];
+    entry e[FSNEO_KMAX + FSNEO_C];
     for (int32_t k = 0; k < K; ++k) {
         e[k].idx = S->ld_idx[i * K + k];
         e[k].key = ld_dist2(S->Y, d, i, e[k].idx);
@@ -549,7 +549,7 @@ static void init_point_lists(fsneo_state *S, int64_t i, int64_t N)
     const int32_t K = S->K_hd;
     random_list(i, N, K, FSNEO_S_INIT_HD, 0, S->seed, S->hd_idx + i * K, 0);
     random_list(i, N, S->K_ld, FSNEO_S_INIT_LD, 0, S->seed, S->ld_idx + i * S->K_ld, 0);
-    entry e[64];
+    entry e[FSNEO_KMAX];
     for (int32_t k = 0; k < K; ++k) {
         e[k].idx = S->hd_idx[i * K + k];
         e[k].key = state_dist2(S, i, e[k].idx);
@@ -571,7 +571,8 @@ static void all_psym(fsneo_state *S)
 int fsneo_init(fsneo_state *S, const fsneo_hp *hp)
 {
     const int64_t N = S->N;
-    if (S->K_hd < 2 || S->K_hd > 64 || S->K_ld < 1 || S->K_ld > 64 || S->K_hd >= N ||
+    if (S->K_hd < 2 || S->K_hd > FSNEO_KMAX || S->K_ld < 1 || S->K_ld > FSNEO_KMAX ||
+        S->K_hd >= N ||
         S->K_ld >= N || S->d < 1 || S->d > 64)
         return -1;
 #pragma omp parallel for schedule(dynamic, 256)
@@ -696,8 +697,8 @@ int fsneo_step(fsneo_state *S, const fsneo_hp *hp, fsneo_stats *st, double *A_ou
 /* P row, new LD row and gradient partials.  Z is not formed.                */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int32_t idx[64];
-    double d2[64];
+    int32_t idx[FSNEO_KMAX];
+    double d2[FSNEO_KMAX];
     double rec[4];
 } point_next;
 
@@ -750,8 +751,8 @@ int fsneo_point_step(const fsneo_state *S, const fsneo_hp *hp, int64_t i, int32_
     for (int32_t k = 0; k < K; ++k) next_of(S, hp, pn[0].idx[k], fired, &pn[1 + k]);
     /* affinities of i from the next rows and records of its neighbours */
     {
-        const int32_t *rows_j[64] = {0};
-        const double *rec_j[64] = {0};
+        const int32_t *rows_j[FSNEO_KMAX] = {0};
+        const double *rec_j[FSNEO_KMAX] = {0};
         for (int32_t k = 0; k < K; ++k) {
             rows_j[k] = FSNEO_PLANT == 3 ? S->hd_idx + (int64_t)pn[0].idx[k] * K : pn[1 + k].idx;
             rec_j[k] = pn[1 + k].rec;
@@ -828,7 +829,7 @@ int fsneo_drift(fsneo_state *S, const fsneo_hp *hp, const int64_t *ids, int64_t 
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < N; ++i) {
         int touched = moved[i];
-        entry e[64];
+        entry e[FSNEO_KMAX];
         for (int32_t k = 0; k < K; ++k) {
             int64_t j = S->hd_idx[i * K + k];
             e[k].idx = j;
@@ -869,7 +870,7 @@ int fsneo_set_metric(fsneo_state *S, const fsneo_hp *hp, int32_t metric)
     const int32_t K = S->K_hd;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < N; ++i) {
-        entry e[64];
+        entry e[FSNEO_KMAX];
         for (int32_t k = 0; k < K; ++k) {
             e[k].idx = S->hd_idx[i * K + k];
             e[k].key = state_dist2(S, i, e[k].idx);
@@ -907,7 +908,7 @@ void fsneo_delete_fix(fsneo_state *S, const fsneo_hp *hp, const int32_t *newid)
     const uint32_t t = *S->t;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < N; ++i) {
-        int32_t ids[64];
+        int32_t ids[FSNEO_KMAX];
         int nk = 0;
         for (int32_t k = 0; k < Kl; ++k) {
             int32_t nj = newid[S->ld_idx[i * Kl + k]];
@@ -916,7 +917,7 @@ void fsneo_delete_fix(fsneo_state *S, const fsneo_hp *hp, const int32_t *newid)
         random_list(i, N, Kl, FSNEO_S_DEL_LD, t, S->seed, ids, nk);
         for (int32_t k = 0; k < Kl; ++k) S->ld_idx[i * Kl + k] = ids[k];
 
-        entry e[64];
+        entry e[FSNEO_KMAX];
         int changed = 0;
         nk = 0;
         for (int32_t k = 0; k < Kh; ++k) {

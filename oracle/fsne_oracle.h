@@ -19,6 +19,9 @@
 extern "C" {
 #endif
 
+/* Longest neighbour list (HD or LD). */
+#define FSNEO_KMAX 256
+
 /* Number of candidate slots per point and refinement, and their kinds. */
 #define FSNEO_C 32
 #define FSNEO_SAME_NON 16   /* slots  0..15: neighbour of neighbour, same space   */

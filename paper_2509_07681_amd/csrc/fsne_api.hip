@@ -163,6 +163,8 @@ fsne_status check_hparams(fsne_ctx* c, const fsne_hparams* hp, int32_t Kh, int32
   if (hp->metric < 0 || hp->metric > 1) return fail(c, FSNE_EINVAL, "metric must be 0 or 1");
   if (hp->metric == 1 && hp->dist_mode == 1)
     return fail(c, FSNE_EINVAL, "the BF16 screen needs metric 0 (it works on the raw rows)");
+  if (Kh > fsne::kWave && hp->dist_mode == 1)
+    return fail(c, FSNE_EINVAL, "the BF16 screen takes HD lists of at most 64");
   return FSNE_OK;
 }
 
@@ -487,8 +489,9 @@ fsne_status fsne_init(fsne_ctx** out, const void* X, int64_t N, int32_t D, int32
                       int32_t x_on_device, void* stream, int64_t capacity) {
   if (!out) return FSNE_EINVAL;
   *out = nullptr;
-  if (!X || N < 3 || N > 2147483647LL || D < 1 || d < 1 || d > 64 || K_hd < 2 || K_hd > 64 ||
-      K_ld < 1 || K_ld > 64 || K_hd >= N || K_ld >= N || (xdtype != FSNE_F32 && xdtype != FSNE_BF16))
+  if (!X || N < 3 || N > 2147483647LL || D < 1 || d < 1 || d > 64 || K_hd < 2 ||
+      K_hd > fsne::kMaxLong || K_ld < 1 || K_ld > 64 || K_hd >= N || K_ld >= N ||
+      (xdtype != FSNE_F32 && xdtype != FSNE_BF16))
     return FSNE_EINVAL;
   if (capacity < N || capacity > 2147483647LL) return FSNE_EINVAL;
   if (D > fsne_max_dim(xdtype, D)) return FSNE_EINVAL;
@@ -557,6 +560,8 @@ fsne_status fsne_set_hyperparams(fsne_ctx* c, const fsne_hparams* hp) {
   TRY(check_hparams(c, hp, c->Kh, c->xdtype, c->D));
   const bool perp_changed = hp->perplexity != c->hp.perplexity;
   const bool metric_changed = hp->metric != c->hp.metric;
+  if (metric_changed && c->Kh > fsne::kWave)
+    return fail(c, FSNE_EINVAL, "a metric switch takes HD lists of at most 64");
   // a rejection under one screen (or metric) need not be one under another
   const bool screen_changed =
       hp->dist_mode != c->hp.dist_mode || hp->rerank_margin != c->hp.rerank_margin;
@@ -739,6 +744,7 @@ fsne_status fsne_drift_points(fsne_ctx* c, const int64_t* ids, const void* Xnew,
   if (!c) return FSNE_EINVAL;
   if (!ids || !Xnew || n < 0) return fail(c, FSNE_EINVAL, "bad arguments to fsne_drift_points");
   if (n == 0) return FSNE_OK;
+  if (c->Kh > fsne::kWave) return fail(c, FSNE_EINVAL, "drift takes HD lists of at most 64");
   if (!c->own_X) return fail(c, FSNE_ESTATE, "X is borrowed; create the context with capacity");
   std::vector<uint8_t> seen((size_t)c->N, 0);
   std::vector<int32_t> ids32((size_t)n);
@@ -786,6 +792,7 @@ fsne_status fsne_drift_points_noalloc(fsne_ctx* c, const int64_t* ids, const voi
   if (!ids || !Xnew || n < 0)
     return fail(c, FSNE_EINVAL, "bad arguments to fsne_drift_points_noalloc");
   if (n == 0) return FSNE_OK;
+  if (c->Kh > fsne::kWave) return fail(c, FSNE_EINVAL, "drift takes HD lists of at most 64");
   if (!c->own_X) return fail(c, FSNE_ESTATE, "X is borrowed; create the context with capacity");
   if (!c->scratch) return fail(c, FSNE_ESTATE, "no device scratch for this context's device");
   for (int64_t k = 0; k < n; ++k) {
@@ -828,6 +835,7 @@ fsne_status fsne_delete_points(fsne_ctx* c, const int64_t* ids, int64_t n) {
   if (!c) return FSNE_EINVAL;
   if (!ids || n < 0) return fail(c, FSNE_EINVAL, "bad arguments to fsne_delete_points");
   if (n == 0) return FSNE_OK;
+  if (c->Kh > fsne::kWave) return fail(c, FSNE_EINVAL, "delete takes HD lists of at most 64");
   if (!c->own_X) return fail(c, FSNE_ESTATE, "X is borrowed; create the context with capacity");
   const int64_t N = c->N, N1 = N - n;
   if (N1 <= std::max(c->Kh, c->Kl)) return fail(c, FSNE_EINVAL, "too few points would remain");

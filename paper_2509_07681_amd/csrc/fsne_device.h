@@ -267,12 +267,13 @@ __device__ __forceinline__ void bitonic_sort(uint64_t& key, uint32_t& aux) {
   }
 }
 
-// Number of keys of the ascending array a[0..n) below k (n <= 64; keys past
-// n read as kNoKey).
+// Number of keys of the ascending array a[0..n) below k (n <= MAXN, a power
+// of two; keys past n are not read).
+template <int MAXN = 64>
 __device__ __forceinline__ int count_below(const uint64_t* a, int n, uint64_t k) {
   int pos = 0;
 #pragma unroll
-  for (int step = 64; step >= 1; step >>= 1) {
+  for (int step = MAXN; step >= 1; step >>= 1) {
     const int probe = pos + step;
     if (probe <= n && a[probe - 1] < k) pos = probe;
   }
@@ -283,16 +284,22 @@ __device__ __forceinline__ int count_below(const uint64_t* a, int n, uint64_t k)
 // Per-wave open-addressing set of point ids in LDS (kHashSlots entries,
 // -1 = empty), filled with LDS compare-and-swap; tag bits ride along.
 // ---------------------------------------------------------------------------
+// SLOTS entries (a power of two, 256 by default; 512 where lists longer than
+// a wave go in).
 constexpr int kHashSlots = 256;
 
+template <int SLOTS = kHashSlots>
 __device__ __forceinline__ int hash_slot(int id) {
-  return (int)(((uint32_t)id * 0x9E3779B1u) >> 24);
+  constexpr int kBits = SLOTS == 256 ? 8 : SLOTS == 512 ? 9 : 10;
+  static_assert(SLOTS == (1 << kBits), "256, 512 or 1024 slots");
+  return (int)(((uint32_t)id * 0x9E3779B1u) >> (32 - kBits));
 }
 
+template <int SLOTS = kHashSlots>
 __device__ __forceinline__ void hash_clear(int* tab, int* tag) {
   const int lane = lane_id();
 #pragma unroll
-  for (int k = 0; k < kHashSlots / kWave; ++k) {
+  for (int k = 0; k < SLOTS / kWave; ++k) {
     tab[k * kWave + lane] = -1;
     if (tag) tag[k * kWave + lane] = 0;
   }
@@ -302,18 +309,19 @@ __device__ __forceinline__ void hash_clear(int* tab, int* tag) {
 // Insert id (id >= 0); returns true if it was absent.  Lanes with id < 0 do
 // nothing and return false.  tag_bits (if a tag array is given) are OR-ed
 // into the slot's tag whether or not the id was new.
+template <int SLOTS = kHashSlots>
 __device__ __forceinline__ bool hash_insert(int* tab, int* tag, int id, int tag_bits) {
   bool fresh = false;
   if (id >= 0) {
-    int slot = hash_slot(id);
-    for (int probe = 0; probe < kHashSlots; ++probe) {
+    int slot = hash_slot<SLOTS>(id);
+    for (int probe = 0; probe < SLOTS; ++probe) {
       const int old = atomicCAS(&tab[slot], -1, id);
       if (old == -1 || old == id) {
         fresh = old == -1;
         if (tag) atomicOr(&tag[slot], tag_bits);
         break;
       }
-      slot = (slot + 1) & (kHashSlots - 1);
+      slot = (slot + 1) & (SLOTS - 1);
     }
   }
   wave_lds_sync();
@@ -321,14 +329,15 @@ __device__ __forceinline__ bool hash_insert(int* tab, int* tag, int id, int tag_
 }
 
 // Tag of id in the set (0 if absent or id < 0).
+template <int SLOTS = kHashSlots>
 __device__ __forceinline__ int hash_find(const int* tab, const int* tag, int id) {
   if (id < 0) return 0;
-  int slot = hash_slot(id);
-  for (int probe = 0; probe < kHashSlots; ++probe) {
+  int slot = hash_slot<SLOTS>(id);
+  for (int probe = 0; probe < SLOTS; ++probe) {
     const int v = tab[slot];
     if (v == id) return tag ? tag[slot] : 1;
     if (v == -1) return 0;
-    slot = (slot + 1) & (kHashSlots - 1);
+    slot = (slot + 1) & (SLOTS - 1);
   }
   return 0;
 }
@@ -382,6 +391,63 @@ __device__ inline float4 calibrate_row(float d2, int K, const Hyper& h, float be
     beta = bn;
   }
   const float S = wave_sum_uniform(act ? expf(-beta * D) : 0.0f);
+  return make_float4(beta, m, r, 1.0f / S);
+}
+
+// ---------------------------------------------------------------------------
+// The same calibration for a sorted row of K <= kMaxLong distances held in
+// LDS (lists longer than a wave): lane l takes entries l, l + 64, ...; each
+// sum adds a lane's entries in that order, then across the wave.
+// ---------------------------------------------------------------------------
+constexpr int kMaxLong = 256;   // longest HD list
+
+__device__ inline float4 calibrate_row_lds(const float* d2, int K, const Hyper& h,
+                                           float beta_prev) {
+  constexpr int R = kMaxLong / kWave;
+  const int lane = lane_id();
+  const float m = d2[0];
+  const float r = d2[K - 1];
+  float D[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = q * kWave + lane;
+    D[q] = k < K ? d2[k] - m : 0.0f;
+  }
+  if (!(r > m)) return make_float4(0.0f, m, r, 1.0f / (float)K);
+  int ties = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) ties += __popcll(__ballot(q * kWave + lane < K && D[q] == 0.0f));
+  if ((float)ties >= h.perplexity) return make_float4(1e30f, m, r, 1.0f / (float)ties);
+  auto lane_sum = [&](auto f) {
+    float v = 0.0f;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (q * kWave + lane < K) v += f(D[q]);
+    return wave_sum_uniform(v);
+  };
+  const float target = h.ln_perp;
+  float beta = beta_prev;
+  if (!(beta > 0.0f && beta < 1e29f)) beta = (float)K / lane_sum([](float x) { return x; });
+  float lo = 0.0f, hi = __int_as_float(0x7f800000);
+  for (int it = 0; it < 48; ++it) {
+    const float bl = beta * 1.44269504f;   // exp(-beta D) = 2^(-beta log2(e) D)
+    const float S = lane_sum([&](float x) { return exp2f(-bl * x); });
+    const float T = lane_sum([&](float x) { return exp2f(-bl * x) * x; });
+    const float U = lane_sum([&](float x) { return exp2f(-bl * x) * x * x; });
+    const float mean = T / S;
+    const float f = logf(S) + beta * mean - target;
+    if (fabsf(f) <= 1e-6f) break;
+    if (f > 0.0f)
+      lo = beta;
+    else
+      hi = beta;
+    if (hi < 3e38f && hi - lo <= 2e-7f * hi) break;
+    const float var = U / S - mean * mean;
+    float bn = beta + f / (beta * var);
+    if (!(bn > lo && bn < hi)) bn = (hi < 3e38f) ? 0.5f * (lo + hi) : 2.0f * beta;
+    beta = bn;
+  }
+  const float S = lane_sum([&](float x) { return expf(-beta * x); });
   return make_float4(beta, m, r, 1.0f / S);
 }
 

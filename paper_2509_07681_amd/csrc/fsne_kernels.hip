@@ -196,8 +196,10 @@ __device__ void hd_dist_rows(const TX* __restrict__ X, int D, int32_t i, int cid
 // per lane, -1 for none): those would lose the merge again.
 // Returns the candidate id in lanes 0..31 (-1: dropped), -1 elsewhere.
 // ---------------------------------------------------------------------------
-// make_candidate_u takes the draw of its slot (lanes 0..31) from the caller.
-template <bool MEMO = false>
+// make_candidate_u takes the draw of its slot (lanes 0..31) from the caller;
+// with OTHER_MEM, i's row of Lx is read from memory (lists longer than a
+// wave) instead of from `other`.
+template <bool MEMO = false, bool OTHER_MEM = false>
 __device__ __forceinline__ int make_candidate_u(const uint4 u, int32_t i,
                                                 const int32_t* __restrict__ L, int K, int own,
                                                 const int32_t* __restrict__ Lx, int Kx, int other,
@@ -207,7 +209,11 @@ __device__ __forceinline__ int make_candidate_u(const uint4 u, int32_t i,
   const int a_own = (int)draw_index(u.x, (uint32_t)K);
   const int a_oth = (int)draw_index(u.x, (uint32_t)Kx);
   const int j_own = __shfl(own, a_own);
-  const int j_oth = __shfl(other, a_oth);
+  int j_oth;
+  if constexpr (OTHER_MEM)
+    j_oth = Lx[(int64_t)i * Kx + a_oth];
+  else
+    j_oth = __shfl(other, a_oth);
   int c = -1;
   if (lane < kCand) {
     if (s < kSameNoN)
@@ -821,6 +827,208 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// HD lists longer than a wave (64 < K_hd <= kMaxLong, K_ld <= 64): one point
+// per wave, its list in LDS with entry k handled by lane k mod 64.  The same
+// candidates, merge rule, flags, remembered rejections and calibration as
+// k_hd_refine; the merge ranks the old entries against the sorted candidates
+// and the candidates against the old list by binary search.
+// ---------------------------------------------------------------------------
+constexpr int kLongSlots = 2 * kHashSlots;   // ids of the list, memory and candidates
+
+struct WaveLdsLong {
+  uint64_t ok[kMaxLong];    // list keys (d2 bits << 32 | id), ascending
+  float row[kMaxLong];      // distances of the new (or initial) list
+  int lst[kMaxLong];        // ids of the initial list; compaction scratch
+  uint64_t ck[kCand];       // sorted candidate keys
+  float d2[kWave];          // candidate distances
+  int tab[kLongSlots];
+};
+
+// Sorts the n <= kMaxLong distinct keys of a[] ascending in place: each lane
+// ranks its entries against all n, then writes them to their ranks.
+__device__ void rank_sort_lds(uint64_t* a, int n) {
+  constexpr int R = kMaxLong / kWave;
+  const int lane = lane_id();
+  uint64_t mine[R];
+  int rank[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = q * kWave + lane;
+    mine[q] = k < n ? a[k] : kNoKey;
+    rank[q] = 0;
+  }
+  for (int m = 0; m < n; ++m) {
+    const uint64_t v = a[m];
+#pragma unroll
+    for (int q = 0; q < R; ++q) rank[q] += v < mine[q] ? 1 : 0;
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (q * kWave + lane < n) a[rank[q]] = mine[q];
+  wave_lds_sync();
+}
+
+template <typename TX, int VEC, int CH>
+__global__ __launch_bounds__(kBlock) void k_hd_refine_long(StepArgs a) {
+  constexpr int R = kMaxLong / kWave;
+  const Scalars* sc = a.sc;
+  if (!sc->fire) return;
+  __shared__ WaveLdsLong lds_all[kWavesPerBlock];
+  WaveLdsLong& S = lds_all[threadIdx.x / kWave];
+  const int32_t i = (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  if (i >= a.N) return;
+  const int lane = lane_id();
+  const uint32_t t = sc->t;
+  const int cur = sc->hd_cur;
+  const int Kh = a.Kh, Kl = a.Kl;
+  const int32_t* hin = a.hd_idx[cur];
+  const float* din = a.hd_d2[cur];
+  const int32_t* lin = a.ld_idx[t & 1];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = q * kWave + lane;
+    if (k < Kh) S.ok[k] = pack_key(din[(int64_t)i * Kh + k], hin[(int64_t)i * Kh + k]);
+  }
+  const int oth = lane < Kl ? lin[(int64_t)i * Kl + lane] : -1;
+  const int memo = (a.memo && lane < a.memo_w) ? a.memo[(int64_t)i * kMemo + lane] : -1;
+  wave_lds_sync();
+  // candidates, as make_candidate with i's own list read from LDS (in its
+  // stored order: the draws index it)
+  const uint4 u =
+      philox((uint32_t)i, t, kStreamHDC, (uint32_t)(lane & (kCand - 1)), a.h.key0, a.h.key1);
+  const int j_oth = __shfl(oth, (int)draw_index(u.x, (uint32_t)Kl));
+  int c = -1;
+  if (lane < kCand) {
+    if (lane < kSameNoN) {
+      const int j = key_id(S.ok[draw_index(u.x, (uint32_t)Kh)]);
+      c = hin[(int64_t)j * Kh + draw_index(u.y, (uint32_t)Kh)];
+    } else if (lane < kCrossDir) {
+      c = j_oth;
+    } else if (lane < kCrossNoN) {
+      c = lin[(int64_t)j_oth * Kl + draw_index(u.y, (uint32_t)Kl)];
+    } else {
+      c = draw_other(u.x, i, a.N);
+    }
+  }
+  // the stored list is in key order except after a state load whose order
+  // came from other arithmetic: then sort it for the merge
+  bool unsorted = false;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = q * kWave + lane;
+    if (k + 1 < Kh) unsorted |= !(S.ok[k] < S.ok[k + 1]);
+  }
+  if (__ballot(unsorted) != 0ull) rank_sort_lds(S.ok, Kh);
+  hash_clear<kLongSlots>(S.tab, nullptr);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = q * kWave + lane;
+    hash_insert<kLongSlots>(S.tab, nullptr, k < Kh ? key_id(S.ok[k]) : -1, 0);
+  }
+  hash_insert<kLongSlots>(S.tab, nullptr, memo, 0);
+  const bool fresh =
+      hash_insert<kLongSlots>(S.tab, nullptr, (lane < kCand && c != i) ? c : -1, 0);
+  c = fresh ? c : -1;
+  const int n = compact_ids(c, S.lst);
+  hd_dist_rows<TX, VEC, CH>(static_cast<const TX*>(a.X), a.D, i, c, n, S.d2);
+  uint64_t ck = c >= 0 ? pack_key(S.d2[lane & (kCand - 1)], c) : kNoKey;
+  uint32_t aux = 0;
+  bitonic_sort<32>(ck, aux);
+  if (lane < kCand) S.ck[lane] = ck;
+  wave_lds_sync();
+  int32_t* hout = a.hd_idx[cur ^ 1];
+  float* dout = a.hd_d2[cur ^ 1];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = q * kWave + lane;
+    if (k < Kh) {
+      const uint64_t ko = S.ok[k];
+      const int ro = k + count_below<kCand>(S.ck, n, ko);
+      if (ro < Kh) {
+        hout[(int64_t)i * Kh + ro] = key_id(ko);
+        dout[(int64_t)i * Kh + ro] = key_d2(ko);
+        S.row[ro] = key_d2(ko);
+      }
+    }
+  }
+  bool enter = false;
+  if (lane < n) {
+    const int rc = lane + count_below<kMaxLong>(S.ok, Kh, ck);
+    enter = rc < Kh;
+    if (enter) {
+      hout[(int64_t)i * Kh + rc] = key_id(ck);
+      dout[(int64_t)i * Kh + rc] = key_d2(ck);
+      S.row[rc] = key_d2(ck);
+    }
+  }
+  wave_lds_sync();
+  const bool changed = __ballot(enter) != 0ull;
+  if (lane == 0) a.flags[i] = (uint8_t)((changed ? 1 : 0) | (n << 1));
+  if (a.memo) {
+    const int rejected = (lane < n && !enter) ? key_id(ck) : -1;
+    remember_rejections(a.memo + (int64_t)i * kMemo, a.memo_w, memo, -1, rejected, S.lst);
+  }
+  if (changed) {
+    const float4 r = calibrate_row_lds(S.row, Kh, a.h, a.rec[i].x);
+    if (lane == 0) a.rec[i] = r;
+  }
+}
+
+// Initial lists for K_hd > 64: the rule of k_init_lists, the HD list sorted
+// in LDS.
+template <typename TX, int VEC, int CH>
+__global__ __launch_bounds__(kBlock) void k_init_lists_long(const TX* __restrict__ X, int32_t N,
+                                                            int32_t i0, int D, int Kh, int Kl,
+                                                            Hyper h, int32_t* __restrict__ hd_idx,
+                                                            float* __restrict__ hd_d2,
+                                                            int32_t* __restrict__ ld_idx,
+                                                            float4* __restrict__ rec,
+                                                            uint8_t* __restrict__ flags) {
+  constexpr int R = kMaxLong / kWave;
+  __shared__ WaveLdsLong lds_all[kWavesPerBlock];
+  WaveLdsLong& S = lds_all[threadIdx.x / kWave];
+  const int32_t i = i0 + (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
+  if (i >= N) return;
+  const int lane = lane_id();
+  random_list(i, N, Kl, kStreamInitLD, 0u, h, S.lst, 0);
+  if (lane < Kl) ld_idx[(int64_t)i * Kl + lane] = S.lst[lane];
+  wave_lds_sync();
+  random_list(i, N, Kh, kStreamInitHD, 0u, h, S.lst, 0);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int base = q * kWave;
+    if (base < Kh) {
+      const int k = base + lane;
+      hd_dist_rows<TX, VEC, CH>(X, D, i, k < Kh ? S.lst[k] : -1, min(kWave, Kh - base),
+                                S.row + base);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = q * kWave + lane;
+    if (k < Kh) S.ok[k] = pack_key(S.row[k], S.lst[k]);
+  }
+  wave_lds_sync();
+  rank_sort_lds(S.ok, Kh);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = q * kWave + lane;
+    if (k < Kh) {
+      hd_idx[(int64_t)i * Kh + k] = key_id(S.ok[k]);
+      hd_d2[(int64_t)i * Kh + k] = key_d2(S.ok[k]);
+      S.row[k] = key_d2(S.ok[k]);
+    }
+  }
+  wave_lds_sync();
+  const float4 r = calibrate_row_lds(S.row, Kh, h, 0.0f);
+  if (lane == 0) {
+    rec[i] = r;
+    flags[i] = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Symmetrised affinities of point i (eq. (1)) over its HD list:
 //   P_ik = (p_{j|i} + p_{i|j}) / (2N), j = HD[i][k],
 //   p_{j|i} = exp(-beta_i (d2 - m_i)) invS_i,
@@ -978,6 +1186,7 @@ __device__ __forceinline__ float strided_sum(float v) {
   return v;
 }
 
+template <int HS = kHashSlots>
 struct LdLds {
   int ent[2 * kWave];     // LD entries: candidate slots, then the old list (-1: none)
   float dd[2 * kWave];    // their decision distances
@@ -985,8 +1194,8 @@ struct LdLds {
   int newl[kWave];        // new LD list
   int kind[2 * kWave];    // 1: entry kept and not an HD neighbour
   int neg[kWave];         // negative samples outside U (-1: none)
-  int tab[kHashSlots];    // hash set of ids (candidate dedupe, then U)
-  int tag[kHashSlots];    // 1: HD neighbour, 2: new LD neighbour
+  int tab[HS];            // hash set of ids (candidate dedupe, then U)
+  int tag[HS];            // 1: HD neighbour, 2: new LD neighbour
 };
 
 // Adds one neighbour's contribution to this lane's components:
@@ -1016,16 +1225,20 @@ __device__ __forceinline__ float pair_terms(const float* yi, const float* yj, fl
   return scale * w;
 }
 
-// KLM bounds the LD list length (32 or 64), which sizes the entry passes.
-template <int DP, int KLM>
+// KLM bounds the LD list length (32 or 64), which sizes the entry passes; HL
+// bounds the HD list length: 64 (held one entry per lane) or kMaxLong (read
+// from memory where it is used; the set U then needs a larger hash table).
+template <int DP, int KLM, int HL = kWave>
 __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   using Geo = LdGeom<DP, KLM>;
   constexpr int VEC = Geo::VEC, G = Geo::G, RPI = Geo::RPI;
-  constexpr int LP = (kWave + RPI - 1) / RPI;   // passes over a list of <= 64 rows
-  constexpr bool PRE_H = LP * VEC <= 8;         // HD rows kept in registers
+  constexpr bool LONG_H = HL > kWave;
+  constexpr int HS = LONG_H ? 2 * kHashSlots : kHashSlots;
+  constexpr int LP = (HL + RPI - 1) / RPI;      // passes over the HD list
+  constexpr bool PRE_H = !LONG_H && LP * VEC <= 8;   // HD rows kept in registers
   constexpr bool PRE_E = Geo::CACHE;            // entry rows kept in registers
-  __shared__ LdLds lds_all[kWavesPerBlock];
-  LdLds& S = lds_all[threadIdx.x / kWave];
+  __shared__ LdLds<HS> lds_all[kWavesPerBlock];
+  LdLds<HS>& S = lds_all[threadIdx.x / kWave];
   const int32_t i = (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
   if (i >= a.N) return;
   const Scalars* sc = a.sc;
@@ -1045,8 +1258,8 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   // HD neighbour rows, old LD neighbour rows, negative sample rows.
   float yi[VEC];
   load_chunk<VEC>(yrow + (int64_t)i * DP, yi);
-  const int hid = lane < Kh ? hl[(int64_t)i * Kh + lane] : -1;
-  const float pk = lane < Kh ? a.P[(int64_t)i * Kh + lane] : 0.0f;
+  const int hid = (!LONG_H && lane < Kh) ? hl[(int64_t)i * Kh + lane] : -1;
+  const float pk = (!LONG_H && lane < Kh) ? a.P[(int64_t)i * Kh + lane] : 0.0f;
   const int lid = lane < Kl ? lin[(int64_t)i * Kl + lane] : -1;
   // One Philox pass draws the candidate slots (lanes 0..31) and negative
   // samples 0..31 (lanes 32..63); negative s ends in lane s.
@@ -1083,7 +1296,7 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
     if (nneg <= RPI && rg < nneg) load_chunk<VEC>(yrow + (int64_t)id * DP, yn);
   }
 
-  const int c = make_candidate_u(ud, i, lin, Kl, lid, hl, Kh, hid, a.N, S.tab);
+  const int c = make_candidate_u<false, LONG_H>(ud, i, lin, Kl, lid, hl, Kh, hid, a.N, S.tab);
   if (lane < kCand) S.ent[lane] = c;
   if (lane < Kl) S.ent[kCand + lane] = lid;
   {
@@ -1170,13 +1383,18 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   wave_lds_sync();
   // U = HD list + new LD list as a tagged hash set: LD entries that are HD
   // neighbours too act once, as HD neighbours; negatives in U act not at all
-  hash_clear(S.tab, S.tag);
-  hash_insert(S.tab, S.tag, lane < Kh ? hid : -1, 1);
-  hash_insert(S.tab, S.tag, kid, 2);
-  for (int e = lane; e < ne; e += kWave) {
-    if (S.kind[e] == 2) S.kind[e] = (hash_find(S.tab, S.tag, S.ent[e]) & 1) ? 0 : 1;
+  hash_clear<HS>(S.tab, S.tag);
+  if constexpr (LONG_H) {
+    for (int b = 0; b < Kh; b += kWave)
+      hash_insert<HS>(S.tab, S.tag, b + lane < Kh ? hl[(int64_t)i * Kh + b + lane] : -1, 1);
+  } else {
+    hash_insert<HS>(S.tab, S.tag, lane < Kh ? hid : -1, 1);
   }
-  const bool n_in = hash_find(S.tab, S.tag, jn) != 0;
+  hash_insert<HS>(S.tab, S.tag, kid, 2);
+  for (int e = lane; e < ne; e += kWave) {
+    if (S.kind[e] == 2) S.kind[e] = (hash_find<HS>(S.tab, S.tag, S.ent[e]) & 1) ? 0 : 1;
+  }
+  const bool n_in = hash_find<HS>(S.tab, S.tag, jn) != 0;
   S.neg[lane] = (lane < nneg && !n_in) ? jn : -1;
   wave_lds_sync();
 
@@ -1189,16 +1407,21 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   for (int p = 0; p < LP; ++p) {
     if (p * RPI < Kh) {
       const int r = p * RPI + rg;
-      const float pr = __shfl(pk, r & (kWave - 1));
+      float pr;
       float yj[VEC];
 #pragma unroll
       for (int v = 0; v < VEC; ++v) yj[v] = yi[v];
-      if constexpr (PRE_H) {
+      if constexpr (LONG_H) {
+        pr = r < Kh ? a.P[(int64_t)i * Kh + r] : 0.0f;
+        if (r < Kh) load_chunk<VEC>(yrow + (int64_t)hl[(int64_t)i * Kh + r] * DP, yj);
+      } else if constexpr (PRE_H) {
+        pr = __shfl(pk, r & (kWave - 1));
         if (r < Kh) {
 #pragma unroll
           for (int v = 0; v < VEC; ++v) yj[v] = yh[p][v];
         }
       } else {
+        pr = __shfl(pk, r & (kWave - 1));
         const int id = __shfl(hid, r & (kWave - 1));
         if (r < Kh) load_chunk<VEC>(yrow + (int64_t)id * DP, yj);
       }
@@ -1437,6 +1660,20 @@ __global__ __launch_bounds__(kBlock) void k_calibrate_all(StepArgs a) {
   if (lane == 0) a.rec[i] = r;
 }
 
+// The same for lists longer than a wave (rows staged in LDS).
+__global__ __launch_bounds__(kBlock) void k_calibrate_all_long(StepArgs a) {
+  __shared__ float rows[kWavesPerBlock][kMaxLong];
+  const int w = threadIdx.x / kWave;
+  const int32_t i = (int32_t)(blockIdx.x * kWavesPerBlock + w);
+  if (i >= a.N) return;
+  const int lane = lane_id();
+  const float* hd = a.hd_d2[a.sc->hd_cur];
+  for (int k = lane; k < a.Kh; k += kWave) rows[w][k] = hd[(int64_t)i * a.Kh + k];
+  wave_lds_sync();
+  const float4 r = calibrate_row_lds(rows[w], a.Kh, a.h, a.rec[i].x);
+  if (lane == 0) a.rec[i] = r;
+}
+
 // ---------------------------------------------------------------------------
 // Drift: recompute every HD entry that pairs with a moved point (moved[] is
 // a per-point byte map), re-sort those rows, flag and recalibrate them.
@@ -1600,6 +1837,12 @@ static hipError_t dispatch_x(const StepArgs& a, Args&&... args) {
 template <typename TX, int VEC, int CH>
 struct InitLaunch {
   static hipError_t run(const StepArgs& a, int32_t i0, int32_t n, hipStream_t s) {
+    if (a.Kh > kWave)
+      hipLaunchKernelGGL((k_init_lists_long<TX, VEC, CH>), dim3(wave_blocks(n)), dim3(kBlock), 0,
+                         s, static_cast<const TX*>(a.X), i0 + n, i0, a.D, a.Kh, a.Kl, a.h,
+                         a.hd_idx[a.hd_buf_host], a.hd_d2[a.hd_buf_host],
+                         a.ld_idx[a.ld_buf_host], a.rec, a.flags);
+    else
     hipLaunchKernelGGL((k_init_lists<TX, VEC, CH>), dim3(wave_blocks(n)), dim3(kBlock), 0, s,
                        static_cast<const TX*>(a.X), i0 + n, i0, a.D, a.Kh, a.Kl, a.h,
                        a.hd_idx[a.hd_buf_host], a.hd_d2[a.hd_buf_host], a.ld_idx[a.ld_buf_host],
@@ -1611,7 +1854,10 @@ struct InitLaunch {
 template <typename TX, int VEC, int CH>
 struct RefineLaunch {
   static hipError_t run(const StepArgs& a, hipStream_t s) {
-    if (CH == 1 && a.Kh <= 32 && a.Kl <= 32 && a.memo_w == 64)
+    if (a.Kh > kWave)
+      hipLaunchKernelGGL((k_hd_refine_long<TX, VEC, CH>), dim3(wave_blocks(a.N)), dim3(kBlock),
+                         0, s, a);
+    else if (CH == 1 && a.Kh <= 32 && a.Kl <= 32 && a.memo_w == 64)
       hipLaunchKernelGGL((k_hd_refine2<TX, VEC, false, 64>), dim3(wave_blocks((a.N + 1) / 2)),
                          dim3(kBlock), 0, s, a);
     else if (CH == 1 && a.Kh <= 32 && a.Kl <= 32)
@@ -1626,7 +1872,7 @@ struct RefineLaunch {
 
 // BF16 rows, D % 16 == 0 (checked by the host), 16-byte aligned.
 hipError_t launch_hd_refine_bf16(const StepArgs& a, hipStream_t s) {
-  if (a.xdtype != 1 || a.D % 16 != 0 || !a.xvec_ok) return hipErrorInvalidValue;
+  if (a.xdtype != 1 || a.D % 16 != 0 || !a.xvec_ok || a.Kh > kWave) return hipErrorInvalidValue;
   const int chunks = (a.D / 8 + 63) / 64;
   if (chunks <= 1 && a.Kh <= 32 && a.Kl <= 32)
     hipLaunchKernelGGL((k_hd_refine2<uint16_t, 8, true, 32>), dim3(wave_blocks((a.N + 1) / 2)),
@@ -1694,16 +1940,21 @@ hipError_t launch_psym(const StepArgs& a, int standalone, hipStream_t s) {
 }
 
 hipError_t launch_calibrate_all(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_calibrate_all, dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a);
+  if (a.Kh > kWave)
+    hipLaunchKernelGGL(k_calibrate_all_long, dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_calibrate_all, dim3(wave_blocks(a.N)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_ld_grad(const StepArgs& a, hipStream_t s) {
   const dim3 g(wave_blocks(a.N)), b(kBlock);
-  const bool short_list = a.Kl <= 32;
+  const bool short_list = a.Kl <= 32, long_hd = a.Kh > kWave;
 #define FSNE_LD_CASE(DPV)                                                        \
   case DPV:                                                                      \
-    if (short_list)                                                              \
+    if (long_hd)                                                                 \
+      hipLaunchKernelGGL((k_ld_grad<DPV, kWave, kMaxLong>), g, b, 0, s, a);      \
+    else if (short_list)                                                         \
       hipLaunchKernelGGL((k_ld_grad<DPV, 32>), g, b, 0, s, a);                   \
     else                                                                         \
       hipLaunchKernelGGL((k_ld_grad<DPV, kWave>), g, b, 0, s, a);                \

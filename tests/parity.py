@@ -83,6 +83,14 @@ def compare_hd_rows(X, gpu_idx, ora_idx, ora_d2, tol, rows=None):
             continue
         if not np.all(np.abs(dg - ora_d2[i]) <= tol * np.maximum(ora_d2[i], 1e-30)):
             bad.append(i)
+            if len(bad) <= 2:
+                k = np.nonzero(g != o)[0]
+                print(f"HD row {i} differs beyond the tie rule at positions {k[:8]}: "
+                      f"gpu ids {g[k[:8]]} d2 {dg[k[:8]]}, oracle ids {o[k[:8]]} "
+                      f"d2 {np.asarray(ora_d2[i])[k[:8]]}; gpu ids missing from the oracle "
+                      f"row {sorted(set(g.tolist()) - set(o.tolist()))[:8]}, oracle ids "
+                      f"missing from the gpu row {sorted(set(o.tolist()) - set(g.tolist()))[:8]}",
+                      flush=True)
     return differ, len(bad), bad
 
 

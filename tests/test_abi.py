@@ -54,7 +54,9 @@ def test_defaults_and_argument_checks(fsne_lib):
                            a["stream"], a["cap"])
 
     assert init(Kh=100) == F.FSNE_EINVAL          # K_hd >= N
-    assert init(Kh=65) == F.FSNE_EINVAL           # list longer than a wave
+    X300 = np.zeros((300, 8), np.float32)
+    assert init(X=X300.ctypes.data, N=300, cap=300, Kh=257) == F.FSNE_EINVAL   # K_hd <= 256
+    assert init(Kl=65) == F.FSNE_EINVAL           # LD list longer than a wave
     assert init(Kh=1) == F.FSNE_EINVAL
     assert init(Kl=0) == F.FSNE_EINVAL
     assert init(d=0) == F.FSNE_EINVAL

@@ -70,6 +70,21 @@ WORKLOADS = {
     "odd_d1023_260": lambda: (manifolds(n_manifolds=4, per_manifold=65, D=1023, k=3,
                                         noise=0.005, seed=1011)[0],
                               dict(d=7, K_hd=12, K_ld=9, n_neg=5, alpha=1.3, perplexity=6.0)),
+    # HD lists longer than a wave (held in LDS): 128 and 256 entries, and 100
+    # (not a multiple of 8: the affinity pass scans the whole list) on rows of
+    # odd width
+    "long_hd128_2000": lambda: (manifolds(n_manifolds=10, per_manifold=200, D=32, k=3,
+                                          seed=1012)[0],
+                                dict(d=2, K_hd=128, K_ld=16, n_neg=8, alpha=1.0,
+                                     perplexity=30.0)),
+    "long_hd256_3000_bf16": lambda: (f32_to_bf16_bits(manifolds(n_manifolds=12, per_manifold=250,
+                                                                D=64, k=4, seed=1013)[0]),
+                                     # 8 times the entries per row of the 32-entry
+                                     # cases: 8 times the rows with a tie allowed
+                                     dict(d=8, K_hd=256, K_ld=32, n_neg=16, alpha=0.7,
+                                          perplexity=50.0, tie_rows=48)),
+    "long_hd100_777": lambda: (np.random.default_rng(4).normal(size=(777, 13)).astype(np.float32),
+                               dict(d=3, K_hd=100, K_ld=9, n_neg=5, alpha=1.3, perplexity=20.0)),
     # the smallest case: N = 6, one input dimension, d = 1
     "tiny_6": lambda: (np.array([[0.0], [0.3], [1.1], [2.0], [2.2], [5.0]], dtype=np.float32),
                        dict(d=1, K_hd=3, K_ld=2, n_neg=2, alpha=1.0, perplexity=2.0)),
@@ -365,4 +380,26 @@ def test_delete_matches_oracle(oracle_lib, fsne_lib, name):
     g = emb.state()
     same = _check_hd(Xl, c, g, S, X.dtype == np.uint16)
     assert np.all(np.isfinite(g["Y"])) and emb.stats()["nonfinite"] == 0
+    emb.close()
+
+
+def test_long_lists_reach_the_exact_neighbours(oracle_lib, fsne_lib):
+    """Lists of 256 on 3,000 blob points: after 400 GPU iterations the HD lists
+    hold nearly all exact 256 nearest neighbours and stay valid."""
+    O, F = oracle_lib, fsne_lib
+    X, lab = blobs(n_clusters=6, per_cluster=500, D=20, seed=1014)
+    N, K = X.shape[0], 256
+    hp_o, hp_g = make_hp(O, F, N, perplexity=60.0)
+    emb = F.Embedding(X, y_init(N, 2), 2, K, 16, seed=42, hp=hp_g)
+    emb.step(250)
+    emb.set_hyperparams(F.fsne_default_hparams(**{**hp_g.as_dict(), "attr": 1.0,
+                                                   "momentum": 0.8}))
+    emb.step(150)
+    idx, d2 = emb.knn(0)
+    assert np.all(np.diff(d2, axis=1) >= 0)
+    assert all(len(set(r.tolist())) == K and i not in set(r.tolist()) for i, r in enumerate(idx))
+    ex, _ = O.knn_exact(X, np.arange(N), K)
+    recall = np.mean([len(set(idx[i]) & set(ex[i])) for i in range(N)]) / K
+    assert recall > 0.95, recall
+    assert emb.stats()["nonfinite"] == 0
     emb.close()

@@ -137,11 +137,12 @@ def _complete_state(O, N=24, D=5, d=2, alpha=1.0, perp=6.0, seed=9):
 
 
 @pytest.mark.parametrize("alpha", [0.5, 1.0, 3.0])
-def test_complete_lists_give_exact_affinities_and_gradient(oracle_lib, alpha):
-    """With K_hd = N-1 the three sets of eq. (6) are exhaustive and nothing is sampled."""
+@pytest.mark.parametrize("N", [24, 200])
+def test_complete_lists_give_exact_affinities_and_gradient(oracle_lib, alpha, N):
+    """With K_hd = N-1 the three sets of eq. (6) are exhaustive and nothing is
+    sampled (N = 200: lists of 199, longer than a wave)."""
     O = oracle_lib
-    N = 24
-    X, S, hp = _complete_state(O, N=N, alpha=alpha)
+    X, S, hp = _complete_state(O, N=N, alpha=alpha, perp=6.0 if N < 100 else 40.0)
     hp = hp.copy(alpha=alpha)
     Pex, beta_ex = O.exact_P(X, hp.perplexity)
     # sparse affinities in dense form
