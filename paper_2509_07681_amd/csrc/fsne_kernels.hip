@@ -341,49 +341,60 @@ __device__ __forceinline__ int compact_ids(int& c, int* scratch) {
 }
 
 // ---------------------------------------------------------------------------
-// BF16 screen of the candidates: dot products x_i . x_c on the matrix cores.
-// The 32 candidate rows are the A operand (32 x 16 per instruction, lane l
-// supplying row l mod 32, k = 8 (l / 32) .. +8), x_i is broadcast into every
-// column of B, so every column of C = A B holds the 32 dot products; lanes 0
-// and 32 hold column 0 (rows 4 (l/32) + 8 (r/4) + r mod 4 in register r).
-// Accumulation is FP32.  Returns the dot product of this lane's slot.
+// BF16 screen of the candidates: dot products x_i . x_c on the matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  A pass takes 16 candidate
+// rows as A (16 x 32 per instruction: lane l supplies row l mod 16 and the 8
+// elements 8 (l / 16) .. +8 of each 32-wide step, so an instruction reads 64
+// contiguous bytes of each of its 16 rows); every column of B holds x_i, so
+// column 0 of C = A B holds the 16 dot products: lane 16 g, register r holds
+// row 4 g + r.  The slots' products go to sdot; returns this lane's (lanes
+// 0..31).
 // ---------------------------------------------------------------------------
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 
-__device__ __forceinline__ float screen_dots(const uint16_t* __restrict__ X, int D, int32_t i,
-                                             int c, float* sdot) {
-  const int lane = lane_id(), row = lane & (kCand - 1), half = lane >> 5;
-  const int cr = __shfl(c, row);
-  const uint16_t* ar = X + (int64_t)(cr >= 0 ? cr : i) * D + half * 8;
-  const uint16_t* br = X + (int64_t)i * D + half * 8;
-  f32x16_t acc = {};
-  // four k-steps per round: all their loads go out before the first product
-  constexpr int kSteps = 4;
-  for (int k0 = 0; k0 < D; k0 += 16 * kSteps) {
+constexpr int kScreenRows = 16;   // candidate rows per matrix-core pass
+constexpr int kScreenK = 32;      // elements of a row per instruction
+
+__device__ __forceinline__ f32x4_t screen_pass(const uint16_t* __restrict__ ar, bool have_a,
+                                               const uint16_t* __restrict__ br, int D, int kb) {
+  constexpr int kSteps = 2;   // loads of two steps go out before the first product
+  f32x4_t acc = {};
+  for (int k0 = 0; k0 < D; k0 += kScreenK * kSteps) {
     uint4 av[kSteps], bv[kSteps];
 #pragma unroll
     for (int u = 0; u < kSteps; ++u) {
-      const int k = k0 + 16 * u;
+      const int e = k0 + kScreenK * u + 8 * kb;   // this lane's 8 elements (D % 16 == 0)
       av[u] = make_uint4(0, 0, 0, 0);
       bv[u] = make_uint4(0, 0, 0, 0);
-      if (k < D) {
-        if (cr >= 0) av[u] = *reinterpret_cast<const uint4*>(ar + k);
-        bv[u] = *reinterpret_cast<const uint4*>(br + k);
+      if (e < D) {
+        if (have_a) av[u] = *reinterpret_cast<const uint4*>(ar + e);
+        bv[u] = *reinterpret_cast<const uint4*>(br + e);
       }
     }
 #pragma unroll
     for (int u = 0; u < kSteps; ++u)
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av[u]),
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, av[u]),
                                                     __builtin_bit_cast(bf16x8_t, bv[u]), acc,
                                                     0, 0, 0);
   }
-  if (row == 0) {
+  return acc;
+}
+
+__device__ __forceinline__ float screen_dots(const uint16_t* __restrict__ X, int D, int32_t i,
+                                             int c, float* sdot) {
+  const int lane = lane_id(), row = lane & (kScreenRows - 1), kb = lane >> 4;
+  const uint16_t* br = X + (int64_t)i * D;
+  for (int p = 0; p < kCand; p += kScreenRows) {
+    const int cr = __shfl(c, p + row);
+    const f32x4_t acc = screen_pass(X + (int64_t)(cr >= 0 ? cr : i) * D, cr >= 0, br, D, kb);
+    if (row == 0) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) sdot[(r & 3) + 8 * (r >> 2) + 4 * half] = acc[r];
+      for (int r = 0; r < 4; ++r) sdot[p + 4 * kb + r] = acc[r];
+    }
   }
   wave_lds_sync();
-  const float v = sdot[row];
+  const float v = sdot[lane & (kCand - 1)];
   wave_lds_sync();
   return v;
 }
@@ -628,46 +639,25 @@ __device__ void hd_dist_rows2(const TX* __restrict__ X, int D, int32_t i0, int32
 
 // The BF16 screen for two points at once.  Slots 0..n0-1 are the ids in
 // lanes 0..n0-1 (candidates of point i0), slots n0..n0+n1-1 those in lanes
-// 32..32+n1-1 (point i1).  Each pass takes 32 slots as the rows of A; the
-// columns of B hold x_i0 (0..15) and x_i1 (16..31), so the product of slot s
-// with its own point is column 0 or 16 of its row.  sdot[slot] gets it.
+// 32..32+n1-1 (point i1).  Each pass takes 16 slots as the rows of A; the
+// columns of B hold x_i0 (0..7) and x_i1 (8..15), so the product of slot s
+// with its own point is column 0 or 8 of its row.  sdot[slot] gets it.
 __device__ void screen_dots2(const uint16_t* __restrict__ X, int D, int32_t i0, int32_t i1,
                              int cid, int n0, int n1, float* sdot) {
-  const int lane = lane_id(), row = lane & 31, half = lane >> 5;
-  const uint16_t* br = X + (int64_t)(row < 16 ? i0 : i1) * D + half * 8;
+  const int lane = lane_id(), row = lane & (kScreenRows - 1), kb = lane >> 4;
+  const uint16_t* br = X + (int64_t)(row < 8 ? i0 : i1) * D;
   const int nrows = n0 + n1;
-  constexpr int kSteps = 4;
-  for (int p = 0; p < nrows; p += 32) {
+  for (int p = 0; p < nrows; p += kScreenRows) {
     const int slot = p + row;
     const int src = slot >= n0 ? 32 + slot - n0 : slot;
     const int cs = __shfl(cid, src & (kWave - 1));
     const int cr = slot < nrows ? cs : -1;
-    const uint16_t* ar = X + (int64_t)(cr >= 0 ? cr : i0) * D + half * 8;
-    f32x16_t acc = {};
-    for (int k0 = 0; k0 < D; k0 += 16 * kSteps) {
-      uint4 av[kSteps], bv[kSteps];
+    const f32x4_t acc = screen_pass(X + (int64_t)(cr >= 0 ? cr : i0) * D, cr >= 0, br, D, kb);
+    // lanes 16 g (column 0) and 16 g + 8 (column 8) hold rows 4 g .. 4 g + 3
+    if (row == 0 || row == 8) {
 #pragma unroll
-      for (int u = 0; u < kSteps; ++u) {
-        const int k = k0 + 16 * u;
-        av[u] = make_uint4(0, 0, 0, 0);
-        bv[u] = make_uint4(0, 0, 0, 0);
-        if (k < D) {
-          if (cr >= 0) av[u] = *reinterpret_cast<const uint4*>(ar + k);
-          bv[u] = *reinterpret_cast<const uint4*>(br + k);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kSteps; ++u)
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, av[u]),
-                                                      __builtin_bit_cast(bf16x8_t, bv[u]), acc,
-                                                      0, 0, 0);
-    }
-    // lanes 0 / 32 hold column 0 and lanes 16 / 48 column 16, for rows
-    // 4 half + 8 (r / 4) + r mod 4 in register r
-    if (row == 0 || row == 16) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int s = p + 4 * half + 8 * (r >> 2) + (r & 3);
+      for (int r = 0; r < 4; ++r) {
+        const int s = p + 4 * kb + r;
         if (s < nrows && ((s < n0) == (row == 0))) sdot[s] = acc[r];
       }
     }
