@@ -464,6 +464,8 @@ def large_run(F, args):
         emb = F.Embedding(Xb, Y0, cfg["d"], K, cfg["K_ld"], seed=RUN_SEED,
                           hp=F.fsne_default_hparams(**{**schedule(F, base, 0).as_dict(),
                                                        "hd_mode": mode, "dist_mode": dm}))
+        if args.reorder_data:
+            emb.reorder_data()
         emb.step(5)
         emb.sync()
         t0 = time.perf_counter()
@@ -495,12 +497,11 @@ def large_run(F, args):
         emb.sync()
         orig = np.arange(N)
         t0 = time.perf_counter()
+        if args.reorder_data:
+            track_renumbering(orig, emb.reorder_data())
         for done in range(0, 500, 100):
             if every and done > 0:
-                p = emb.reorder()
-                nxt = np.empty_like(orig)
-                nxt[p] = orig
-                orig = nxt
+                track_renumbering(orig, emb.reorder())
             if done < 250 < done + 100:
                 emb.step(250 - done)
                 emb.set_hyperparams(schedule(F, {**base, "hd_mode": hd_mode}, 250))
