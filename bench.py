@@ -1311,6 +1311,11 @@ def main():
         out["runs_recall_target"] = target
     if not args.no_dynamic:
         out["dynamic"] = dynamic_run(F, args)
+        # the same experiment on the image-like generator itself (independent
+        # pixel drops and jitter within a class: no low-dimensional structure
+        # within a class, so the LD recall target is a far weaker signal)
+        out["dynamic_image_generator"] = dynamic_run(F, argparse.Namespace(
+            **{**vars(args), "dyn_data": "image"}))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, cfg, Y0, RUN_SEED)
     print(json.dumps(out))

@@ -28,6 +28,7 @@ static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 namespace {
 
 constexpr int kMaxScratchDevices = 64;
+constexpr int32_t kGraphIters = 25;   // iterations per captured graph
 std::mutex g_scratch_mu;
 void* g_scratch[kMaxScratchDevices] = {};
 
@@ -77,7 +78,8 @@ Hyper make_hyper(const fsne_ctx* c) {
 }
 
 StepArgs make_args(const fsne_ctx* c) {
-  StepArgs a{};
+  StepArgs a;
+  std::memset(&a, 0, sizeof a);   // padding too: the graph cache compares whole structs
   a.X = c->X;
   a.xnorm = c->xnorm;
   a.xdtype = c->xdtype;
@@ -391,6 +393,12 @@ fsne_status timed_launch(fsne_ctx* c, int kernel, Launch&& launch) {
   return FSNE_OK;
 }
 
+void drop_graph(fsne_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->gn = 0;
+}
+
 void release(fsne_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -399,12 +407,48 @@ void release(fsne_ctx* c) {
     (void)hipEventDestroy(t.stop);
   }
   for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
+  drop_graph(c);
   c->pending.clear();
   c->spare.clear();
   for (void* p : c->owned) (void)hipFree(p);
   c->owned.clear();
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   c->stream = nullptr;
+}
+
+// One iteration's five launches (each timed when profiling is on).
+fsne_status launch_iteration(fsne_ctx* c, const StepArgs& a, hipStream_t s) {
+  TRY(timed_launch(c, FSNE_K_HD_REFINE, [&] { return fsne::launch_hd_refine(a, s); }));
+  TRY(timed_launch(c, FSNE_K_AFFINITY, [&] { return fsne::launch_psym(a, 0, s); }));
+  TRY(timed_launch(c, FSNE_K_LD_GRAD, [&] { return fsne::launch_ld_grad(a, s); }));
+  TRY(timed_launch(c, FSNE_K_REDUCE, [&] { return fsne::launch_reduce(a, s); }));
+  TRY(timed_launch(c, FSNE_K_UPDATE, [&] { return fsne::launch_update(a, s); }));
+  return FSNE_OK;
+}
+
+// A graph of n iterations for these kernel arguments (captured on first use).
+fsne_status ensure_graph(fsne_ctx* c, const StepArgs& a, int32_t n) {
+  if (c->gexec && c->gn == n && std::memcmp(&c->gargs, &a, sizeof a) == 0) return FSNE_OK;
+  drop_graph(c);
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  fsne_status st = FSNE_OK;
+  for (int32_t k = 0; k < n && st == FSNE_OK; ++k) st = launch_iteration(c, a, s);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != FSNE_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "graph capture");
+  hipGraphExec_t x = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return hip_fail(c, e2, "graph instantiate");
+  c->gexec = x;
+  c->gn = n;
+  c->gargs = a;
+  return FSNE_OK;
 }
 
 // Apply a drift whose staging is on the device: n ids (int32), their new X
@@ -545,13 +589,19 @@ fsne_status fsne_step(fsne_ctx* c, int32_t n_iters) {
   if (n_iters < 0) return fail(c, FSNE_EINVAL, "n_iters < 0");
   const StepArgs a = make_args(c);
   hipStream_t s = c->stream;
-  for (int32_t it = 0; it < n_iters; ++it) {
-    TRY(timed_launch(c, FSNE_K_HD_REFINE, [&] { return fsne::launch_hd_refine(a, s); }));
-    TRY(timed_launch(c, FSNE_K_AFFINITY, [&] { return fsne::launch_psym(a, 0, s); }));
-    TRY(timed_launch(c, FSNE_K_LD_GRAD, [&] { return fsne::launch_ld_grad(a, s); }));
-    TRY(timed_launch(c, FSNE_K_REDUCE, [&] { return fsne::launch_reduce(a, s); }));
-    TRY(timed_launch(c, FSNE_K_UPDATE, [&] { return fsne::launch_update(a, s); }));
+  int32_t it = 0;
+  // Without per-kernel timing, whole chunks of iterations go out as one
+  // captured HIP graph (the iteration's five launches, kGraphIters times):
+  // one launch instead of five per iteration.  The graph is kept while the
+  // kernel arguments stay the same.
+  if (!c->prof && c->use_graph) {
+    const int32_t chunk = std::min<int32_t>(n_iters, kGraphIters);
+    if (chunk >= 2) {
+      TRY(ensure_graph(c, a, chunk));
+      for (; it + chunk <= n_iters; it += chunk) HIPCHK(c, hipGraphLaunch(c->gexec, s));
+    }
   }
+  for (; it < n_iters; ++it) TRY(launch_iteration(c, a, s));
   return FSNE_OK;
 }
 

@@ -34,6 +34,11 @@ struct fsne_ctx {
   float* Xu = nullptr;       // cap x D rows scaled to unit length (angular metric)
   uint8_t* rwork = nullptr;  // renumbering workspace (kept between calls)
   void* scratch = nullptr;   // device address of the library's fixed staging array
+  // fsne_step's captured graph: gn iterations for the kernel arguments gargs
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
+  int32_t gn = 0;
+  fsne::StepArgs gargs{};
   size_t rwork_bytes = 0;
   fsne::Scalars* sc = nullptr;
   std::string err;

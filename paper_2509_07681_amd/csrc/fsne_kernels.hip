@@ -1331,21 +1331,29 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   bool keep = false;
   int kid = -1;
   if (Geo::MAXE <= kWave || ne <= kWave) {
+    // each entry's rank among all entries by (distance, index), counted
+    // against every key read back from LDS: the valid keys are distinct (the
+    // candidates differ from the list and from one another), so the kept
+    // entries take the ranks 0 .. Kl-1
     const int e = lane;
     const int id = e < ne ? S.ent[e] : -1;
-    uint64_t key = id >= 0 ? pack_key(S.dd[e], id) : kNoKey;
-    uint32_t slot = (uint32_t)e;
-    bitonic_sort<kWave>(key, slot);
-    S.kind[lane] = 0;
-    S.kind[kWave + lane] = 0;
-    keep = lane < Kl && key != kNoKey;
-    kid = keep ? key_id(key) : -1;
+    const uint64_t key = id >= 0 ? pack_key(S.dd[e], id) : kNoKey;
+    uint64_t* keys = reinterpret_cast<uint64_t*>(S.key);
+    keys[lane] = key;
     wave_lds_sync();
-    if (keep) {
-      lout[(int64_t)i * Kl + lane] = kid;
-      S.newl[lane] = kid;
-      S.kind[slot] = 2;   // kept; refined below
+    int rank = 0;
+#pragma unroll
+    for (int m = 0; m < kWave; ++m) rank += keys[m] < key ? 1 : 0;
+    const bool kept = key != kNoKey && rank < Kl;
+    S.kind[lane] = kept ? 2 : 0;   // kept; refined below
+    S.kind[kWave + lane] = 0;
+    if (kept) {
+      lout[(int64_t)i * Kl + rank] = id;
+      S.newl[rank] = id;
     }
+    wave_lds_sync();
+    keep = lane < Kl;
+    kid = keep ? S.newl[lane] : -1;
   } else {
     const int eA = lane, eB = kWave + lane;
     const int idA = eA < ne ? S.ent[eA] : -1;

@@ -403,3 +403,37 @@ def test_long_lists_reach_the_exact_neighbours(oracle_lib, fsne_lib):
     assert recall > 0.95, recall
     assert emb.stats()["nonfinite"] == 0
     emb.close()
+
+
+def test_captured_graph_equals_eager_launches(fsne_lib):
+    """fsne_step runs chunks of 25 iterations as one captured HIP graph unless
+    kernel timing is on; with timing on every launch goes out on its own.
+    Both give the same state bit for bit over several replays, with a
+    hyperparameter change (a new capture), a state load and host reads
+    between them."""
+    F = fsne_lib
+    X, _ = blobs(seed=1001)
+    N = X.shape[0]
+    hp = F.fsne_default_hparams(perplexity=10.0, lr=N / 12.0, attr=12.0, n_neg=8)
+    eager = F.Embedding(X, y_init(N, 2), 2, 32, 16, seed=9, hp=hp)
+    graph = F.Embedding(X, y_init(N, 2), 2, 32, 16, seed=9, hp=hp)
+    eager.profile(True)
+    fields = ["Y", "V", "hd_idx", "hd_d2", "ld_idx", "rec", "P", "flags"]
+    for k in range(5):
+        eager.step(55)      # 2 graph replays + 5 single iterations on the other side
+        graph.step(55)
+        ge, gg = eager.state(fields), graph.state(fields)
+        for f in fields:
+            assert np.array_equal(ge[f], gg[f]), (k, f)
+        assert eager.stats()["t"] == graph.stats()["t"] == 55 * (k + 1)
+        if k == 1:
+            hp2 = F.fsne_default_hparams(**{**hp.as_dict(), "attr": 1.0, "momentum": 0.8})
+            eager.set_hyperparams(hp2)
+            graph.set_hyperparams(hp2)
+        if k == 2:
+            s = graph.state()
+            graph.set_state({f: v for f, v in s.items() if f not in ("A", "R", "Zh")})
+            s = eager.state()
+            eager.set_state({f: v for f, v in s.items() if f not in ("A", "R", "Zh")})
+    eager.close()
+    graph.close()
