@@ -80,6 +80,11 @@ def all_slot_bytes_per_point(cfg, xbytes):
     return dict(hd_refine=hd, ld_grad=ld, update=6 * sy)
 
 
+def progress(msg):
+    """A line on stderr as each leg ends (the JSON result goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def reorder_due(t, every, start):
     """Whether the points are renumbered before iteration t: every `every`
     iterations from iteration `start` on (before it the embedding has no
@@ -186,6 +191,8 @@ def quality_run(F, X, cfg, Y0, n_iter, seed, queries, ex_d2, dist_mode=0, every=
         secs += time.perf_counter() - t0
         done = stop
         if done % every == 0 or done == n_iter:
+            if done % 500 == 0:
+                progress(f"run (dist_mode {dist_mode}): iteration {done}")
             idx, _ = emb.knn(0)
             curve.append([done, round(secs, 4),
                           round(recall_at_k(in_original_ids(idx), X, queries, ex_d2), 4)])
@@ -682,11 +689,12 @@ def counted_traffic(kernel, W, K, reorder):
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(tf):
         return None
-    rec = json.load(open(tf))
-    if (rec.get("source_hash") != kernel_source_hash() or rec.get("window") != [W, K]
-            or rec.get("reorder") != list(reorder)):
-        return None
-    return rec.get("per_launch_GB", {}).get(kernel)
+    recs = json.load(open(tf))
+    for rec in (recs if isinstance(recs, list) else [recs]):
+        if (rec.get("source_hash") == kernel_source_hash() and rec.get("window") == [W, K]
+                and rec.get("reorder") == list(reorder)):
+            return rec.get("per_launch_GB", {}).get(kernel)
+    return None
 
 
 def roofline(kernels, name, W, K, reorder):
@@ -843,12 +851,18 @@ def summarize_profile(args):
         out["factors"] = {"FETCH_SIZE": f_fetch, "WRITE_SIZE": f_write}
         out["per_launch_GB"] = per_launch
         if args.write_traffic:
+            # one record per (window, renumbering policy, sources); others are kept
             rec = {"source_hash": kernel_source_hash(), "workload": "manifold_1m",
                    "window": [W, K], "reorder": out["reorder"],
                    "unit": "GB per launch", "factors": out["factors"],
                    "per_launch_GB": per_launch, "sources": list(STEP_SOURCES)}
-            with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
-                json.dump(rec, fh, indent=1)
+            tf = os.path.join(ROOT, "profiles", "traffic.json")
+            old = json.load(open(tf)) if os.path.exists(tf) else []
+            old = [r for r in (old if isinstance(old, list) else [old])
+                   if r.get("source_hash") == rec["source_hash"]
+                   and (r.get("window"), r.get("reorder")) != (rec["window"], rec["reorder"])]
+            with open(tf, "w") as fh:
+                json.dump(old + [rec], fh, indent=1)
     print(json.dumps(out, indent=1))
 
 
@@ -938,6 +952,7 @@ def dynamic_run(F, args):
     loss = net.train(base)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    progress(f"online use ({args.dyn_data}): base embedded, network trained")
     o = F.fsne_mlp_default_opts()
     flops = o.epochs * mlp_flops(Xb.shape[1], o.hidden1, o.hidden2, d, N0)
 
@@ -969,6 +984,7 @@ def dynamic_run(F, args):
             ft = F.Mlp(emb, F.fsne_mlp_default_opts(epochs=1))
             ft.set_params(*net.params())
         for b, (Xn, ids, Xd, sample, lab) in enumerate(batches):
+            progress(f"online use ({args.dyn_data}, {mode} placement): batch {b}")
             place = 0.0
             if mode == "mlp":
                 torch.cuda.synchronize()
@@ -1275,6 +1291,7 @@ def main():
             forms["bf16_error"] = bf16_error_statement(F, X[orig], Xb[orig], e2, cfg)
         e2.close()
     out["forms"] = forms
+    progress(f"headline {out['value']} it/s and BF16 forms done")
 
     if not args.no_quality:
         from inputs.knn_metrics import exact_knn
@@ -1309,14 +1326,19 @@ def main():
                                   "profiled steps"}
         out["runs"] = runs
         out["runs_recall_target"] = target
+    if not args.no_quality:
+        progress("1000-iteration runs done")
     if not args.no_dynamic:
         out["dynamic"] = dynamic_run(F, args)
+        progress("online-use experiment (styled generator) done")
         # the same experiment on the image-like generator itself (independent
         # pixel drops and jitter within a class: no low-dimensional structure
         # within a class, so the LD recall target is a far weaker signal)
         out["dynamic_image_generator"] = dynamic_run(F, argparse.Namespace(
             **{**vars(args), "dyn_data": "image"}))
     if not args.no_cpu_baseline:
+        progress("online-use experiment (image-like generator) done" if not args.no_dynamic
+                 else "starting the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(X, cfg, Y0, RUN_SEED)
     print(json.dumps(out))
 
