@@ -866,6 +866,43 @@ def summarize_profile(args):
     print(json.dumps(out, indent=1))
 
 
+def summarize_phases(d):
+    """Per-embedding figures from a rocprofv3 kernel trace of a command that
+    builds several embeddings one after another (`--large`): the dispatches
+    are split into phases at each launch of the list initialisation, and for
+    every phase each step kernel's launches, mean duration over all of them
+    and over the last 10 (microseconds) are printed."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    rows = []
+    for fn in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
+        with open(fn) as fh:
+            rows += list(csv.DictReader(fh))
+    assert rows, f"no kernel trace under {d}"
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    phases, cur = [], None
+    for r in rows:
+        kname = r["Kernel_Name"]
+        if "k_init_lists" in kname:
+            cur = defaultdict(list)
+            phases.append(cur)
+            continue
+        if cur is None:
+            continue
+        for key, pat in STEP_KERNELS:
+            if pat in kname:
+                cur[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    out = []
+    for k, ph in enumerate(phases):
+        out.append({"phase": k, **{key: {"launches": len(v),
+                                          "mean_us": round(sum(v) / len(v), 1),
+                                          "last10_mean_us": round(sum(v[-10:]) / len(v[-10:]), 1)}
+                                    for key, v in ph.items() if v}})
+    print(json.dumps(out, indent=1))
+
+
 def mlp_flops(D, H1, H2, d, n):
     """Multiply-add flops of one training pass over n rows: the forward pass,
     the weight gradients of all three layers and the input gradients of the
@@ -1083,6 +1120,8 @@ def main():
                     help="HD-list R_NX(K) on overlapping and disjointed blobs instead")
     ap.add_argument("--memo-compare", action="store_true",
                     help="HD kernel with the memory of rejected candidates off and on instead")
+    ap.add_argument("--summarize-phases", metavar="DIR",
+                    help="per-embedding step-kernel durations from a rocprofv3 kernel trace")
     ap.add_argument("--summarize-profile", nargs="+", metavar="NAME=DIR",
                     help="summarize rocprofv3 CSV output of this command's timed iterations "
                          "instead (trace=, fetch=, write=, cfetch=, cwrite= directories)")
@@ -1107,6 +1146,9 @@ def main():
                     help="styles: classes with a 3-dim style manifold; image: independent "
                          "pixel drops and jitter within a class")
     args = ap.parse_args()
+    if args.summarize_phases:
+        summarize_phases(args.summarize_phases)
+        return
     if args.summarize_profile:
         summarize_profile(args)
         return

@@ -62,8 +62,11 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    // each 32 x 32 -> 64-bit product in one multiply (v_mad_u64_u32) rather
+    // than separate low and high halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t n0 = hi1 ^ c1 ^ k0;
     const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -292,7 +295,12 @@ template <int SLOTS = kHashSlots>
 __device__ __forceinline__ int hash_slot(int id) {
   constexpr int kBits = SLOTS == 256 ? 8 : SLOTS == 512 ? 9 : 10;
   static_assert(SLOTS == (1 << kBits), "256, 512 or 1024 slots");
-  return (int)(((uint32_t)id * 0x9E3779B1u) >> (32 - kBits));
+  // multiplicative hash on a 24-bit multiply (full rate; a 32-bit multiply
+  // is not), the id's bits above 24 folded into the low ones first; the
+  // product is shifted as unsigned (__umul24 is declared to return int)
+  const uint32_t v = (uint32_t)id ^ ((uint32_t)id >> 24);
+  const uint32_t h = (uint32_t)__umul24(v, 0x9E3779u);
+  return (int)(h >> (32 - kBits));
 }
 
 template <int SLOTS = kHashSlots>

@@ -1331,19 +1331,27 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   bool keep = false;
   int kid = -1;
   if (Geo::MAXE <= kWave || ne <= kWave) {
-    // each entry's rank among all entries by (distance, index), counted
-    // against every key read back from LDS: the valid keys are distinct (the
-    // candidates differ from the list and from one another), so the kept
-    // entries take the ranks 0 .. Kl-1
+    // each entry's rank among all entries by (distance, index): the valid
+    // keys are distinct (the candidates differ from the list and from one
+    // another), so the kept entries take the ranks 0 .. Kl-1.  The rank is
+    // counted within the entry's half (candidate slots in lanes 0..31, the
+    // old list in 32..63), each half is laid out in that order, and the
+    // other half's keys below are found by binary search.
     const int e = lane;
     const int id = e < ne ? S.ent[e] : -1;
     const uint64_t key = id >= 0 ? pack_key(S.dd[e], id) : kNoKey;
-    uint64_t* keys = reinterpret_cast<uint64_t*>(S.key);
+    uint64_t* keys = reinterpret_cast<uint64_t*>(S.key);   // [0, 64): by lane
+    uint64_t* sorted = keys + kWave;                        // [64, 128): halves sorted
+    const int half = lane & kCand;
     keys[lane] = key;
+    sorted[lane] = kNoKey;
     wave_lds_sync();
     int rank = 0;
 #pragma unroll
-    for (int m = 0; m < kWave; ++m) rank += keys[m] < key ? 1 : 0;
+    for (int m = 0; m < kCand; ++m) rank += keys[half + m] < key ? 1 : 0;
+    if (key != kNoKey) sorted[half + rank] = key;
+    wave_lds_sync();
+    rank += count_below<kCand>(sorted + (half ^ kCand), kCand, key);
     const bool kept = key != kNoKey && rank < Kl;
     S.kind[lane] = kept ? 2 : 0;   // kept; refined below
     S.kind[kWave + lane] = 0;

@@ -136,10 +136,11 @@ __global__ void k_morton(const float* __restrict__ Y, int32_t n, int DP, Project
 // Stable least-significant-digit radix sort of (key, id) pairs by 8-bit
 // digits (four passes cover the 30-bit keys).  A block owns a tile of
 // kSortItems rounds of 256 consecutive elements.  Per pass: every block counts
-// its digits; one block turns the digit-major count table into exclusive
-// offsets (digit d of block b starts after every smaller digit and after
-// digit d of the blocks before b); every block scatters its tile in element
-// order, each element at its digit's offset plus the number of equal digits
+// its digits into a digit-major table; one block per digit turns its row
+// into exclusive offsets and sums the digit's total; every block scatters
+// its tile in element order (digit d of block b starts after every smaller
+// digit, from a scan of the totals, and after digit d of the blocks before
+// b), each element at its digit's offset plus the number of equal digits
 // before it in the tile (found with ballots within a wave, per-wave counts
 // across the waves of a round, running counts across rounds).  Equal keys
 // keep their order, so the result is deterministic.
@@ -164,40 +165,55 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_count(const uint32_t* __
   count[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = c[threadIdx.x];
 }
 
-// In-place exclusive prefix sum of a[0..len) by one block of 1024 threads:
-// each thread sums a contiguous chunk, the chunk sums are scanned in LDS,
-// then each thread rewrites its chunk.
-__global__ __launch_bounds__(1024) void k_exclusive_scan(uint32_t* __restrict__ a, int64_t len) {
-  __shared__ uint32_t part[1024];
+// Inclusive prefix sum of part[0..kSortThreads) in LDS by the whole block
+// (log2 steps, each read, barrier, add, barrier).
+__device__ __forceinline__ void block_inclusive_scan(uint32_t* part) {
   const int tid = threadIdx.x;
-  const int64_t chunk = (len + 1023) / 1024;
-  const int64_t lo = std::min<int64_t>(len, tid * chunk), hi = std::min<int64_t>(len, lo + chunk);
-  uint32_t s = 0u;
-  for (int64_t k = lo; k < hi; ++k) s += a[k];
-  part[tid] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t v = tid >= off ? part[tid - off] : 0u;
+  for (int off = 1; off < kSortThreads; off <<= 1) {
+    const uint32_t u = tid >= off ? part[tid - off] : 0u;
     __syncthreads();
-    part[tid] += v;
+    part[tid] += u;
     __syncthreads();
   }
-  uint32_t run = part[tid] - s;
-  for (int64_t k = lo; k < hi; ++k) {
-    const uint32_t v = a[k];
-    a[k] = run;
-    run += v;
+}
+
+// One block per digit d: row d of the count table (the nb per-block counts
+// of digit d) becomes its exclusive prefix sums, and total[d] its sum.  Rows
+// are contiguous, so every load and store is coalesced.
+__global__ __launch_bounds__(kSortThreads) void k_digit_row_scan(uint32_t* __restrict__ count,
+                                                                 int32_t nb,
+                                                                 uint32_t* __restrict__ total) {
+  __shared__ uint32_t part[kSortThreads];
+  uint32_t* row = count + (int64_t)blockIdx.x * nb;
+  const int tid = threadIdx.x;
+  uint32_t carry = 0u;
+  for (int32_t t0 = 0; t0 < nb; t0 += kSortThreads) {
+    const int32_t k = t0 + tid;
+    const uint32_t v = k < nb ? row[k] : 0u;
+    part[tid] = v;
+    __syncthreads();
+    block_inclusive_scan(part);
+    if (k < nb) row[k] = carry + part[tid] - v;
+    carry += part[kSortThreads - 1];
+    __syncthreads();
   }
+  if (tid == 0) total[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
     const uint32_t* __restrict__ keys, const int32_t* __restrict__ ids, int32_t n, int shift,
-    const uint32_t* __restrict__ offset, uint32_t* __restrict__ keys_out,
-    int32_t* __restrict__ ids_out) {
+    const uint32_t* __restrict__ offset, const uint32_t* __restrict__ total,
+    uint32_t* __restrict__ keys_out, int32_t* __restrict__ ids_out) {
   __shared__ uint32_t run[kSortThreads];             // next position of each digit
   __shared__ uint32_t wcount[kSortWaves][kSortThreads];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  run[tid] = offset[(int64_t)tid * gridDim.x + blockIdx.x];
+  // digit tid starts after every smaller digit (exclusive scan of the
+  // totals) and after digit tid of the blocks before this one
+  const uint32_t own = total[tid];
+  run[tid] = own;
+  __syncthreads();
+  block_inclusive_scan(run);
+  run[tid] = run[tid] - own + offset[(int64_t)tid * gridDim.x + blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = base + (int64_t)r * kSortThreads + tid;
@@ -235,12 +251,18 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(
   }
 }
 
+// Words of the count table and digit totals for n elements.
+size_t sort_count_words(int32_t n) {
+  return (size_t)kSortThreads * (size_t)((n + kSortTile - 1) / kSortTile) + kSortThreads;
+}
+
 // Sorts (keys, ids) by the low `bits` bits of the keys (bits <= 32, even
 // number of passes: the result ends in keys / ids; tmp_* are the other
-// buffers of the ping-pong, count holds 256 x ceil(n / kSortTile) words).
+// buffers of the ping-pong, count holds sort_count_words(n) words).
 hipError_t radix_sort_pairs(uint32_t* keys, int32_t* ids, uint32_t* tmp_keys, int32_t* tmp_ids,
                             uint32_t* count, int32_t n, int bits, hipStream_t s) {
   const unsigned nb = (unsigned)((n + kSortTile - 1) / kSortTile);
+  uint32_t* total = count + (size_t)kSortThreads * nb;
   int passes = (bits + 7) / 8;
   passes += passes & 1;
   uint32_t *ka = keys, *kb = tmp_keys;
@@ -248,10 +270,10 @@ hipError_t radix_sort_pairs(uint32_t* keys, int32_t* ids, uint32_t* tmp_keys, in
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
     hipLaunchKernelGGL(k_digit_count, dim3(nb), dim3(kSortThreads), 0, s, ka, n, shift, count);
-    hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(1024), 0, s, count,
-                       (int64_t)kSortThreads * nb);
+    hipLaunchKernelGGL(k_digit_row_scan, dim3(kSortThreads), dim3(kSortThreads), 0, s, count,
+                       (int32_t)nb, total);
     hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortThreads), 0, s, ka, ia, n, shift,
-                       count, kb, ib);
+                       count, total, kb, ib);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     std::swap(ka, kb);
@@ -459,8 +481,7 @@ fsne_status reorder_along(fsne_ctx* c, const fsne::Scalars& sc, const float* coo
   size_t most = 0;
   (void)row_arrays(c, sc, &most);
   hipError_t e;
-  const size_t sort_bytes =
-      sizeof(uint32_t) * kSortThreads * (size_t)((N + kSortTile - 1) / kSortTile);
+  const size_t sort_bytes = sizeof(uint32_t) * sort_count_words(N);
   const size_t n4 = align_up(sizeof(int32_t) * (size_t)N);
   const size_t o_part = o_base, o_range = o_part + align_up(sizeof(float) * kRedBlocks * 2 * kMaxAxes);
   const size_t o_keys = o_range + align_up(sizeof(float) * 2 * kMaxAxes);
@@ -522,7 +543,7 @@ size_t reorder_bytes(fsne_ctx* c, const fsne::Scalars& sc) {
   const size_t n4 = align_up(sizeof(int32_t) * (size_t)N);
   return align_up(sizeof(float) * kRedBlocks * 2 * kMaxAxes) +
          align_up(sizeof(float) * 2 * kMaxAxes) + 5 * n4 +
-         align_up(sizeof(uint32_t) * kSortThreads * (size_t)((N + kSortTile - 1) / kSortTile)) +
+         align_up(sizeof(uint32_t) * sort_count_words(N)) +
          most;
 }
 
