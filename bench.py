@@ -485,6 +485,8 @@ def large_run(F, args):
         emb.close()
         out[name] = {"ms_per_step": round(ms, 3), "iters_per_s": round(1e3 / ms, 2),
                      "kernels_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items() if v[1]}}
+    if args.large_steps_only:
+        return out
     rng = np.random.default_rng(7)
     q = np.sort(rng.choice(N, 500, replace=False))
     Xd = torch.from_numpy(bf16_bits_to_f32(Xb)).cuda()
@@ -867,24 +869,37 @@ def summarize_profile(args):
 
 
 def summarize_phases(d):
-    """Per-embedding figures from a rocprofv3 kernel trace of a command that
-    builds several embeddings one after another (`--large`): the dispatches
-    are split into phases at each launch of the list initialisation, and for
-    every phase each step kernel's launches, mean duration over all of them
-    and over the last 10 (microseconds) are printed."""
+    """Per-embedding figures from rocprofv3 output of a command that builds
+    several embeddings one after another (`--large`): the dispatches are split
+    into phases at each launch of the list initialisation, and for every
+    phase each step kernel's launches and its mean over all of them and over
+    the last 10 are printed: durations in microseconds from a kernel trace,
+    or each counter (summed over its instances) from a counter collection."""
     import csv
     import glob
     from collections import defaultdict
 
-    rows = []
-    for fn in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
-        with open(fn) as fh:
-            rows += list(csv.DictReader(fh))
-    assert rows, f"no kernel trace under {d}"
-    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    def rows_of(pattern):
+        rows = []
+        for fn in sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True)):
+            with open(fn) as fh:
+                rows += list(csv.DictReader(fh))
+        return rows
+
+    trace = rows_of("*kernel_trace.csv")
+    if trace:
+        disp = {int(r["Dispatch_Id"]): (r["Kernel_Name"], {
+            "us": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3}) for r in trace}
+    else:
+        disp = {}
+        for r in rows_of("*counter_collection.csv"):
+            k = int(r["Dispatch_Id"])
+            name, vals = disp.setdefault(k, (r["Kernel_Name"], defaultdict(float)))
+            vals[r["Counter_Name"]] += float(r["Counter_Value"])
+    assert disp, f"no kernel trace or counter collection under {d}"
     phases, cur = [], None
-    for r in rows:
-        kname = r["Kernel_Name"]
+    for k in sorted(disp):
+        kname, vals = disp[k]
         if "k_init_lists" in kname:
             cur = defaultdict(list)
             phases.append(cur)
@@ -893,13 +908,17 @@ def summarize_phases(d):
             continue
         for key, pat in STEP_KERNELS:
             if pat in kname:
-                cur[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+                cur[key].append(vals)
     out = []
     for k, ph in enumerate(phases):
-        out.append({"phase": k, **{key: {"launches": len(v),
-                                          "mean_us": round(sum(v) / len(v), 1),
-                                          "last10_mean_us": round(sum(v[-10:]) / len(v[-10:]), 1)}
-                                    for key, v in ph.items() if v}})
+        rec = {"phase": k}
+        for key, lst in ph.items():
+            names = sorted(lst[0])
+            rec[key] = {"launches": len(lst),
+                        **{f"mean_{n}": round(sum(v[n] for v in lst) / len(lst), 1) for n in names},
+                        **{f"last10_{n}": round(sum(v[n] for v in lst[-10:]) / len(lst[-10:]), 1)
+                           for n in names}}
+        out.append(rec)
     print(json.dumps(out, indent=1))
 
 
@@ -1108,6 +1127,8 @@ def main():
                     default=[10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000])
     ap.add_argument("--large", action="store_true",
                     help="run the 4M-point BF16 workload instead")
+    ap.add_argument("--large-steps-only", action="store_true",
+                    help="with --large: only the step timings (no 500-iteration runs)")
     ap.add_argument("--reorder-every", type=int, default=25,
                     help="renumber the points along the embedding's Morton order every this "
                          "many steps in the timed runs (0: never)")

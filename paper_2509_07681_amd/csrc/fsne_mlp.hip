@@ -26,8 +26,13 @@ struct fsne_mlp {
   float *Xb = nullptr, *Tb = nullptr, *H1b = nullptr, *H2b = nullptr; // batch buffers
   float *Ob = nullptr, *dOb = nullptr, *dH1 = nullptr, *dH2 = nullptr;
   float* lpart = nullptr;      // loss partial sums
-  float* ws = nullptr;         // split-K partial products
-  float* part = nullptr;       // row-chunk partial sums (bias and output-layer gradients)
+  float* ws = nullptr;         // split-K partial products of the W1 gradient
+  float* ws2 = nullptr;        // split-K partial products of the W2 gradient
+  float* part = nullptr;       // row-chunk partial sums of the b2 gradient
+  float* part3 = nullptr;      // row-chunk partial sums of the W3 / b3 gradients
+  float* colpart = nullptr;    // 64-row-block partial sums of the b1 gradient
+  float* lchunk = nullptr;     // loss of each row chunk
+  bool fused_head = false;     // output layer, loss and dH2 in one kernel (k_head)
   void* xstage = nullptr;      // host-batch staging (input dtype)
   std::string err;
 };
@@ -37,11 +42,11 @@ namespace {
 using namespace fsne;
 
 constexpr int kBM = 64, kBN = 64, kBK = 32, kLDP = kBK + 8;
-constexpr int kTM = 64, kTN = 64, kTK = 64, kTP = kTK + 8;   // vector-staged tiles
+constexpr int kTM = 64, kTN = 64, kTK = 64;   // vector-staged tiles: 64 x 64 per sub-tile
 constexpr int kMaxSplit = 8;      // split-K factor limit of the weight-gradient products
 constexpr int kRowChunk = 16;     // rows per partial sum of the column reductions
 constexpr int kLossBlocks = 256;
-enum { kEpiBias = 1, kEpiRelu = 2, kEpiMask = 4 };
+enum { kEpiBias = 1, kEpiRelu = 2, kEpiMask = 4, kEpiColSum = 8 };
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
@@ -58,8 +63,11 @@ struct GemmArgs {
   const float* mask;       // C(m, n) = 0 where mask[m ldm + n] <= 0
   int64_t ldm;
   int epi;
-  float* ws;               // split-K: partial C of split z at ws + z M N (row stride N)
-  int kchunk;              // split-K: K range of one split (a multiple of kTK)
+  float* ws;               // partials mode: the product of split z (no epilogue) at
+                           // ws + z M N (row stride N), split z covering one K range
+  int kchunk;              // K range of one split (a multiple of the K step)
+  float* colpart;          // with kEpiColSum: colpart[by N + n] = sum over the 64
+                           // rows of row block by of C(m, n) after the epilogue
 };
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -67,27 +75,95 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
+// The tile (bx, by, bz) a block computes.  Workgroups go to the chip's
+// eight XCDs in turn (linear id mod 8), each XCD with its own L2; when the
+// tiles divide evenly, XCD x takes the x-th contiguous eighth of the tiles
+// in row-major order, so that the blocks sharing a row of A tiles (and most
+// of B) read them through one L2 instead of eight.
+struct Tile {
+  int bx, by, bz;
+};
+__device__ __forceinline__ Tile block_tile() {
+  const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const int T = gx * gy * gz;
+  int t = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if ((T & 7) == 0) t = (t & 7) * (T >> 3) + (t >> 3);
+  Tile r;
+  r.bz = t / (gx * gy);
+  const int rem = t - r.bz * gx * gy;
+  r.by = rem / gx;
+  r.bx = rem - r.by * gx;
+  return r;
+}
+
+// Writes a block's 64 x 64 tile of C from the accumulators of its four
+// waves (wave (wm, wn) holds rows wm 32 .. +32 and columns wn 32 .. +32;
+// lane l, register r: column l mod 32, row (r mod 4) + 8 (r / 4) + 4 (l / 32)).
+// Partials mode (g.ws): the raw product of this K split.  Otherwise bias,
+// ReLU and mask as g.epi says, and with kEpiColSum the column sums of the
+// tile, in a fixed order, to g.colpart.
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, const f32x16& acc, Tile tl,
+                                              int wm, int wn, int lane, float (*colacc)[kBN]) {
+  const int bm = tl.by * kBM, bn = tl.bx * kBN;
+  const int n = bn + wn * 32 + (lane & 31);
+  if (g.ws) {
+    float* w = g.ws + (int64_t)tl.bz * g.M * g.N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = bm + wm * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+      if (m < g.M && n < g.N) w[(int64_t)m * g.N + n] = acc[r];
+    }
+    return;
+  }
+  float cs = 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = bm + wm * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
+    if (m < g.M && n < g.N) {
+      float v = acc[r];
+      if (g.epi & kEpiBias) v += g.bias[n];
+      if (g.epi & kEpiRelu) v = v > 0.0f ? v : 0.0f;
+      if (g.epi & kEpiMask) v = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? v : 0.0f;
+      g.C[(int64_t)m * g.ldc + n] = v;
+      cs += v;
+    }
+  }
+  if (g.epi & kEpiColSum) {
+    // lanes l and l + 32 hold the same column: add them, then the two waves
+    // of a column half through LDS
+    cs += __shfl_xor(cs, 32);
+    if (lane < 32) colacc[wm][wn * 32 + lane] = cs;
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < kBN && bn + c < g.N) g.colpart[(int64_t)tl.by * g.N + bn + c] = colacc[0][c] + colacc[1][c];
+  }
+}
+
 // C = A B (+ bias, ReLU, mask).  64 x 64 tiles, 4 waves of 32 x 32, K steps
-// of 32 staged in LDS as bfloat16, v_mfma_f32_32x32x16_bf16.
+// of 32 staged in LDS as bfloat16, v_mfma_f32_32x32x16_bf16; any strides.
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ __align__(16) uint16_t As[kBM][kLDP];   // [m][k]
   __shared__ __align__(16) uint16_t Bs[kBN][kLDP];   // [n][k]
+  __shared__ float colacc[2][kBN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int bm = blockIdx.y * kBM, bn = blockIdx.x * kBN;
+  const Tile tl = block_tile();
+  const int bm = tl.by * kBM, bn = tl.bx * kBN;
   const bool a_k = g.sak == 1, b_k = g.sbk == 1;     // contiguous index of each operand
+  const int kbeg = tl.bz * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
   f32x16 acc = {};
-  for (int k0 = 0; k0 < g.K; k0 += kBK) {
+  for (int k0 = kbeg; k0 < kend; k0 += kBK) {
     for (int e = tid; e < kBM * kBK; e += 256) {
       const int m = a_k ? e / kBK : e % kBM, k = a_k ? e % kBK : e / kBM;
       const int gm = bm + m, gk = k0 + k;
-      const float v = (gm < g.M && gk < g.K) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.0f;
+      const float v = (gm < g.M && gk < kend) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.0f;
       As[m][k] = to_bf16(v);
     }
     for (int e = tid; e < kBN * kBK; e += 256) {
       const int n = b_k ? e / kBK : e % kBN, k = b_k ? e % kBK : e / kBN;
       const int gn = bn + n, gk = k0 + k;
-      const float v = (gn < g.N && gk < g.K) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.0f;
+      const float v = (gn < g.N && gk < kend) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.0f;
       Bs[n][k] = to_bf16(v);
     }
     __syncthreads();
@@ -100,18 +176,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     }
     __syncthreads();
   }
-  const int n = bn + wn * 32 + (lane & 31);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int m = bm + wm * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
-    if (m < g.M && n < g.N) {
-      float v = acc[r];
-      if (g.epi & kEpiBias) v += g.bias[n];
-      if (g.epi & kEpiRelu) v = v > 0.0f ? v : 0.0f;
-      if (g.epi & kEpiMask) v = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? v : 0.0f;
-      g.C[(int64_t)m * g.ldc + n] = v;
-    }
-  }
+  gemm_epilogue(g, acc, tl, wm, wn, lane, colacc);
 }
 
 // Four consecutive elements p[0..3] of an operand along its contiguous index,
@@ -156,16 +221,16 @@ __device__ __forceinline__ void tile_load(const float* __restrict__ P, int64_t s
   }
 }
 
-// Rounds the tile to bfloat16 into LDS, laid out [row][k].
-template <bool KC>
-__device__ __forceinline__ void tile_store(uint16_t (*L)[kTP], const float4* v) {
+// Rounds the tile to bfloat16 into LDS columns k0 .. k0+63, laid out [row][k].
+template <bool KC, int TP>
+__device__ __forceinline__ void tile_store(uint16_t (*L)[TP], int k0, const float4* v) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int idx = tid + 256 * j;
     if constexpr (KC) {
       const int r = idx >> 4, k = (idx & 15) << 2;
-      *reinterpret_cast<uint2*>(&L[r][k]) = pack4_bf16(v[j]);
+      *reinterpret_cast<uint2*>(&L[r][k0 + k]) = pack4_bf16(v[j]);
     }
   }
   if constexpr (!KC) {
@@ -175,130 +240,138 @@ __device__ __forceinline__ void tile_store(uint16_t (*L)[kTP], const float4* v) 
                            {v[0].z, v[1].z, v[2].z, v[3].z}, {v[0].w, v[1].w, v[2].w, v[3].w}};
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      *reinterpret_cast<uint2*>(&L[r + i][k]) =
+      *reinterpret_cast<uint2*>(&L[r + i][k0 + k]) =
           pack4_bf16(make_float4(c[i][0], c[i][1], c[i][2], c[i][3]));
   }
 }
 
-// C = A B (+ bias, ReLU, mask) with 16-byte operand loads and the next K tile
-// loaded into registers while the current one is multiplied.  AK / BK: A / B
-// contiguous along k (else along m / n).  With gridDim.z > 1 each z-slice
-// multiplies one K range and writes its partial product to ws (no epilogue).
-template <bool AK, bool BK>
+// C = A B (+ bias, ReLU, mask, column sums) with 16-byte operand loads.  A K
+// step covers R sub-tiles of 64 (R kTK columns of A and rows of B in LDS),
+// and the next step's operands are loaded into registers while the current
+// one is multiplied: the fewer, deeper steps leave fewer waits on a load.
+// AK / BK: A / B contiguous along k (else along m / n).  gridDim.z splits K
+// into ranges of g.kchunk (partials mode, g.ws).
+template <bool AK, bool BK, int R>
 __global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g) {
-  __shared__ __align__(16) uint16_t As[kTM][kTP];
-  __shared__ __align__(16) uint16_t Bs[kTN][kTP];
+  constexpr int TK = kTK * R, TP = TK + 8;
+  __shared__ __align__(16) uint16_t As[kTM][TP];
+  __shared__ __align__(16) uint16_t Bs[kTN][TP];
+  __shared__ float colacc[2][kBN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int bm = blockIdx.y * kTM, bn = blockIdx.x * kTN;
-  const int kbeg = blockIdx.z * g.kchunk;
+  const Tile tl = block_tile();
+  const int bm = tl.by * kTM, bn = tl.bx * kTN;
+  const int kbeg = tl.bz * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
   const int64_t a_r = AK ? g.sam : 0, a_k = AK ? 0 : g.sak;
   const int64_t b_r = BK ? g.sbn : 0, b_k = BK ? 0 : g.sbk;
-  float4 ra[4], rb[4];
-  tile_load<AK>(g.A, a_r, a_k, bm, g.M, kbeg, kend, ra);
-  tile_load<BK>(g.B, b_r, b_k, bn, g.N, kbeg, kend, rb);
+  float4 ra[R][4], rb[R][4];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    tile_load<AK>(g.A, a_r, a_k, bm, g.M, kbeg + kTK * q, kend, ra[q]);
+    tile_load<BK>(g.B, b_r, b_k, bn, g.N, kbeg + kTK * q, kend, rb[q]);
+  }
   f32x16 acc = {};
-  for (int k0 = kbeg; k0 < kend; k0 += kTK) {
-    tile_store<AK>(As, ra);
-    tile_store<BK>(Bs, rb);
-    __syncthreads();
-    if (k0 + kTK < kend) {
-      tile_load<AK>(g.A, a_r, a_k, bm, g.M, k0 + kTK, kend, ra);
-      tile_load<BK>(g.B, b_r, b_k, bn, g.N, k0 + kTK, kend, rb);
-    }
+  for (int k0 = kbeg; k0 < kend; k0 += TK) {
 #pragma unroll
-    for (int s = 0; s < kTK; s += 16) {
-      const int kk = s + (lane >> 5) * 8;
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][kk]);
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + (lane & 31)][kk]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    for (int q = 0; q < R; ++q) {
+      tile_store<AK, TP>(As, kTK * q, ra[q]);
+      tile_store<BK, TP>(Bs, kTK * q, rb[q]);
     }
     __syncthreads();
-  }
-  const int n = bn + wn * 32 + (lane & 31);
-  if (gridDim.z > 1) {
-    float* w = g.ws + (int64_t)blockIdx.z * g.M * g.N;
+    if (k0 + TK < kend) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = bm + wm * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
-      if (m < g.M && n < g.N) w[(int64_t)m * g.N + n] = acc[r];
+      for (int q = 0; q < R; ++q) {
+        tile_load<AK>(g.A, a_r, a_k, bm, g.M, k0 + TK + kTK * q, kend, ra[q]);
+        tile_load<BK>(g.B, b_r, b_k, bn, g.N, k0 + TK + kTK * q, kend, rb[q]);
+      }
     }
-    return;
-  }
+    // sub-tiles past the end of the range hold zeros
+    const int steps = kend - k0;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int m = bm + wm * 32 + (r & 3) + 8 * (r >> 2) + 4 * (lane >> 5);
-    if (m < g.M && n < g.N) {
-      float v = acc[r];
-      if (g.epi & kEpiBias) v += g.bias[n];
-      if (g.epi & kEpiRelu) v = v > 0.0f ? v : 0.0f;
-      if (g.epi & kEpiMask) v = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? v : 0.0f;
-      g.C[(int64_t)m * g.ldc + n] = v;
+    for (int s = 0; s < TK; s += 16) {
+      if (s < steps) {
+        const int kk = s + (lane >> 5) * 8;
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][kk]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + (lane & 31)][kk]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
     }
+    __syncthreads();
   }
-}
-
-// C(m, n) = sum over z of the split-K partials, in split order.
-__global__ void k_splitk_sum(const float* ws, int S, int M, int N, float* C, int64_t ldc) {
-  const int64_t total = (int64_t)M * N;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    float v = 0.0f;
-    for (int z = 0; z < S; ++z) v += ws[(int64_t)z * total + q];
-    C[(q / N) * ldc + q % N] = v;
-  }
+  gemm_epilogue(g, acc, tl, wm, wn, lane, colacc);
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// C = A B with the epilogue `epi` (bias, mask, column sums to colpart), or,
+// with ws (partials mode), the products of *splits K ranges into ws (no
+// epilogue; the caller sums them in split order).  Deep K steps where K is
+// long; split K where the tiles alone would not fill the chip.
 hipError_t gemm(hipStream_t s, const float* A, int64_t sam, int64_t sak, const float* B,
                 int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M, int N, int K, int epi,
                 const float* bias = nullptr, const float* mask = nullptr, int64_t ldm = 0,
-                float* ws = nullptr) {
-  GemmArgs g{A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, mask, ldm, epi, ws, K};
+                float* ws = nullptr, int* splits = nullptr, float* colpart = nullptr) {
+  GemmArgs g{A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, mask, ldm, epi, ws, K, colpart};
   const bool ak = sak == 1, bk = sbk == 1;
   const bool a_ok = ak ? (sam % 4 == 0) : (sam == 1 && sak % 4 == 0);
   const bool b_ok = bk ? (sbn % 4 == 0) : (sbn == 1 && sbk % 4 == 0);
-  if (!(a_ok && b_ok && aligned16(A) && aligned16(B))) {
-    const dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM));
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
-    return hipGetLastError();
-  }
+  const bool vec = a_ok && b_ok && aligned16(A) && aligned16(B);
   const int tiles = ((N + kTN - 1) / kTN) * ((M + kTM - 1) / kTM);
   int S = 1;
-  if (epi == 0 && ws && tiles < 256) {
-    // enough slices to fill the chip, each still at least 256 deep in K
+  if (ws && tiles < 256) {
+    // enough splits to fill the chip, each still at least 256 deep in K
     S = std::min(kMaxSplit, std::max(1, 512 / tiles));
     while (S > 1 && K / S < 256) --S;
   }
-  g.kchunk = S > 1 ? ((K + S - 1) / S + kTK - 1) / kTK * kTK : K;
+  // K step: two sub-tiles of 64 where a split has at least 128 of K (four
+  // measured slower: their LDS leaves room for fewer blocks per CU)
+  const int R = vec && (K + S - 1) / S >= 128 ? 2 : 1;
+  const int step = vec ? kTK * R : kBK;
+  g.kchunk = ((K + S - 1) / S + step - 1) / step * step;
   S = (K + g.kchunk - 1) / g.kchunk;
+  if (splits) *splits = S;
   const dim3 grid((unsigned)((N + kTN - 1) / kTN), (unsigned)((M + kTM - 1) / kTM), (unsigned)S);
+  if (!vec) {
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
+#define FSNE_GEMM_V(AKv, BKv)                                                        \
+  do {                                                                               \
+    if (R == 2)                                                                      \
+      hipLaunchKernelGGL((k_gemm_v<AKv, BKv, 2>), grid, dim3(256), 0, s, g);         \
+    else                                                                             \
+      hipLaunchKernelGGL((k_gemm_v<AKv, BKv, 1>), grid, dim3(256), 0, s, g);         \
+  } while (0)
   if (ak && bk)
-    hipLaunchKernelGGL((k_gemm_v<true, true>), grid, dim3(256), 0, s, g);
+    FSNE_GEMM_V(true, true);
   else if (ak && !bk)
-    hipLaunchKernelGGL((k_gemm_v<true, false>), grid, dim3(256), 0, s, g);
+    FSNE_GEMM_V(true, false);
   else if (!ak && bk)
-    hipLaunchKernelGGL((k_gemm_v<false, true>), grid, dim3(256), 0, s, g);
+    FSNE_GEMM_V(false, true);
   else
-    hipLaunchKernelGGL((k_gemm_v<false, false>), grid, dim3(256), 0, s, g);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || S == 1) return e;
-  hipLaunchKernelGGL(k_splitk_sum, dim3(1024), dim3(256), 0, s, ws, S, M, N, C, ldc);
+    FSNE_GEMM_V(false, false);
+#undef FSNE_GEMM_V
   return hipGetLastError();
 }
 
 // Batch rows: row k is source row (off + k) mod N of X (FP32 or BF16 bits),
-// converted to FP32; targets (y - mean) / std from Y (padded stride DP).
-// One block per row at a time.
+// converted to FP32 into Xb (skipped when Xb is null: the rows are read in
+// place); targets (y - mean) / std from Y (padded stride DP).  One block per
+// row at a time.
 __global__ void k_gather(const void* X, int xdtype, int D, int64_t N, int64_t off, int n,
                          const float* Y, int DP, int d, const float* mean, const float* sd,
                          float* Xb, float* Tb) {
   for (int k = blockIdx.x; k < n; k += gridDim.x) {
     const int64_t r = (off + k) % N;
-    float* dst = Xb + (int64_t)k * D;
-    if (xdtype == 0) {
+    float* dst = Xb ? Xb + (int64_t)k * D : nullptr;
+    if (!Xb) {
+      // targets only (the rows are read in place)
+    } else if (xdtype == 0 && (D & 3) == 0) {
+      const float4* src = reinterpret_cast<const float4*>(static_cast<const float*>(X) + r * D);
+      float4* d4 = reinterpret_cast<float4*>(dst);
+      for (int c = threadIdx.x; c < (D >> 2); c += blockDim.x) d4[c] = src[c];
+    } else if (xdtype == 0) {
       const float* src = static_cast<const float*>(X) + r * D;
       for (int c = threadIdx.x; c < D; c += blockDim.x) dst[c] = src[c];
     } else {
@@ -375,21 +448,6 @@ __device__ __forceinline__ float sum_chunks(const float* part, int nchunk, int64
   return wave_sum_uniform(s);
 }
 
-// gW3 / gb3 from the chunk partials; one wave per output.
-__global__ void k_grad_out_sum(const float* part, int nchunk, int H, int d, float* gW3,
-                               float* gb3) {
-  const int Q = d * (H + 1);
-  const int q = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (q >= Q) return;
-  const float s = sum_chunks(part, nchunk, Q, q);
-  if (lane_id() != 0) return;
-  const int j = q / (H + 1), k = q % (H + 1);
-  if (k < H)
-    gW3[(int64_t)j * H + k] = s;
-  else
-    gb3[j] = s;
-}
-
 // dH2[r][k] = (sum_j dO[r][j] W3[j][k]) where H2[r][k] > 0, else 0.
 __global__ void k_back_out(const float* dO, const float* W3, const float* H2, int n, int H, int d,
                            float* dH2) {
@@ -413,25 +471,201 @@ __global__ void k_colsum_part(const float* M, int n, int cols, float* part) {
   part[(int64_t)blockIdx.y * cols + c] = s;
 }
 
-// out[c] = sum of the chunk partials of column c; one wave per column.
-__global__ void k_sum_parts(const float* part, int nchunk, int cols, float* out) {
-  const int c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (c >= cols) return;
-  const float s = sum_chunks(part, nchunk, cols, c);
-  if (lane_id() == 0) out[c] = s;
+// The output layer and the loss gradient of one chunk of kRowChunk rows per
+// block, in one pass over H2 (S = columns per thread / 256, H <= 256 S):
+//   O[r][j] = b3[j] + sum_k H2[r][k] W3[j][k],  e = O - T,  dO = 2 e scale,
+//   dH2[r][k] = (sum_j dO[r][j] W3[j][k]) where H2[r][k] > 0, else 0,
+// and the chunk's partial sums, each over its rows in order:
+//   part2[c][k] = sum_r dH2[r][k]                      (b2 gradient)
+//   part3[c][j (H+1) + k] = sum_r dO[r][j] H2[r][k]    (W3 gradient)
+//   part3[c][j (H+1) + H] = sum_r dO[r][j]             (b3 gradient)
+//   lchunk[c] = sum over the chunk of e^2.
+// red needs kRowChunk d (4 + 2) floats of shared memory.
+// The targets of row r: T[r] (tgt.Y null) or, while training on a context,
+// (y - mean) / std of its point (off + r) mod N.
+struct Targets {
+  const float* T;
+  const float* Y;
+  int64_t N, off;
+  int DP;
+  const float *mean, *sd;
+  __device__ float operator()(int r, int j, int d) const {
+    if (!Y) return T[(int64_t)r * d + j];
+    const int64_t p = (off + r) % N;
+    return (Y[p * DP + j] - mean[j]) / sd[j];
+  }
+};
+
+template <int S>
+__global__ __launch_bounds__(256) void k_head(const float* H2, const float* W3, const float* b3,
+                                              Targets tgt, int n, int H, int d, float scale,
+                                              float* dH2, float* part2, float* part3,
+                                              float* lchunk) {
+  extern __shared__ float red[];            // [4 waves][rows d], then dO, then e^2
+  float* sdo = red + 4 * kRowChunk * d;
+  float* se2 = sdo + kRowChunk * d;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = blockIdx.x, r0 = c * kRowChunk;
+  const int rows = min(kRowChunk, n - r0);
+  float h[kRowChunk][S];
+#pragma unroll
+  for (int r = 0; r < kRowChunk; ++r)
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int k = tid + 256 * q;
+      h[r][q] = (r < rows && k < H) ? H2[(int64_t)(r0 + r) * H + k] : 0.0f;
+    }
+  // O: per output j, every row's partial dot product, summed over the wave
+  // and then over the four waves
+  for (int j = 0; j < d; ++j) {
+    float w[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int k = tid + 256 * q;
+      w[q] = k < H ? W3[(int64_t)j * H + k] : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < kRowChunk; ++r) {
+      float p = 0.0f;
+#pragma unroll
+      for (int q = 0; q < S; ++q) p = fmaf(h[r][q], w[q], p);
+      p = wave_sum_uniform(p);
+      if (lane == 0) red[(wave * kRowChunk + r) * d + j] = p;
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < kRowChunk * d; q += 256) {
+    const int r = q / d, j = q - r * d;
+    float dov = 0.0f, e2 = 0.0f;
+    if (r < rows) {
+      const float o = ((red[q] + red[kRowChunk * d + q]) + (red[2 * kRowChunk * d + q] +
+                       red[3 * kRowChunk * d + q])) + b3[j];
+      const float e = o - tgt(r0 + r, j, d);
+      dov = 2.0f * e * scale;
+      e2 = e * e;
+    }
+    sdo[q] = dov;
+    se2[q] = e2;
+  }
+  __syncthreads();
+  // dH2 rows and the partial sums of this chunk
+  float dh[kRowChunk][S];
+#pragma unroll
+  for (int r = 0; r < kRowChunk; ++r)
+#pragma unroll
+    for (int q = 0; q < S; ++q) dh[r][q] = 0.0f;
+  for (int j = 0; j < d; ++j) {
+    float w[S], g3[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int k = tid + 256 * q;
+      w[q] = k < H ? W3[(int64_t)j * H + k] : 0.0f;
+      g3[q] = 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < kRowChunk; ++r) {
+      const float dv = sdo[r * d + j];
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        dh[r][q] = fmaf(dv, w[q], dh[r][q]);
+        g3[q] = fmaf(dv, h[r][q], g3[q]);
+      }
+    }
+    float* p3 = part3 + (int64_t)c * d * (H + 1) + (int64_t)j * (H + 1);
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int k = tid + 256 * q;
+      if (k < H) p3[k] = g3[q];
+    }
+    if (tid == 0) {
+      float sb = 0.0f;
+      for (int r = 0; r < kRowChunk; ++r) sb += sdo[r * d + j];
+      p3[H] = sb;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const int k = tid + 256 * q;
+    float cs = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kRowChunk; ++r) {
+      const float v = h[r][q] > 0.0f ? dh[r][q] : 0.0f;
+      if (r < rows && k < H) dH2[(int64_t)(r0 + r) * H + k] = v;
+      cs += v;
+    }
+    if (k < H) part2[(int64_t)c * H + k] = cs;
+  }
+  if (tid == 0) {
+    float l = 0.0f;
+    for (int q = 0; q < kRowChunk * d; ++q) l += se2[q];
+    lchunk[c] = l;
+  }
 }
 
-// Adam (Kingma and Ba 2015) with bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t.
-__global__ void k_adam(float* p, float* m, float* v, const float* g, int64_t np, float lr,
-                       float b1, float b2, float eps, float c1, float c2) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < np;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const float gk = g[k];
-    const float mk = b1 * m[k] + (1.0f - b1) * gk;
-    const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
-    m[k] = mk;
-    v[k] = vk;
-    p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+// Gradient assembly and the optimiser step, one launch.  Blocks below nbd:
+// one thread per W1 / W2 entry, the sum of its split-K partials in split
+// order.  The rest: one wave per b1, b2, W3, b3 entry (and one for the loss),
+// the sum of its row-block partials (lanes take blocks l, l + 64, ..., then
+// a fixed tree).  Every gradient goes to G; with adam the parameters take
+// their Adam step (Kingma and Ba 2015; c1 = 1 - b1^t, c2 = 1 - b2^t).
+struct FinishArgs {
+  float *P, *M, *V, *G;
+  int H1, D, H2, d;
+  const float* ws1; int S1;        // W1 partials: [S1][H1 D]
+  const float* ws2; int S2;        // W2 partials: [S2][H2 H1]
+  const float* colpart; int nb1;   // b1 partials: [nb1][H1]
+  const float* part2; const float* part3; int nchunk;   // b2: [nchunk][H2]; W3, b3: [nchunk][d (H2+1)]
+  const float* lchunk; float* lpart; int accumulate;    // loss (lchunk may be null)
+  int nbd;
+  int adam; float lr, b1, b2, eps, c1, c2;
+};
+
+__device__ __forceinline__ void adam_step(const FinishArgs& f, int64_t k, float gk) {
+  f.G[k] = gk;
+  if (!f.adam) return;
+  const float mk = f.b1 * f.M[k] + (1.0f - f.b1) * gk;
+  const float vk = f.b2 * f.V[k] + (1.0f - f.b2) * gk * gk;
+  f.M[k] = mk;
+  f.V[k] = vk;
+  f.P[k] -= f.lr * (mk / f.c1) / (sqrtf(vk / f.c2) + f.eps);
+}
+
+__global__ __launch_bounds__(256) void k_finish(FinishArgs f) {
+  const int64_t nw1 = (int64_t)f.H1 * f.D, nw2 = (int64_t)f.H2 * f.H1;
+  const int64_t o_b1 = nw1, o_w2 = o_b1 + f.H1, o_b2 = o_w2 + nw2, o_w3 = o_b2 + f.H2;
+  const int64_t o_b3 = o_w3 + (int64_t)f.d * f.H2;
+  if ((int)blockIdx.x < f.nbd) {
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nw1 + nw2;
+         q += (int64_t)f.nbd * 256) {
+      float g = 0.0f;
+      if (q < nw1) {
+        for (int z = 0; z < f.S1; ++z) g += f.ws1[(int64_t)z * nw1 + q];
+        adam_step(f, q, g);
+      } else {
+        const int64_t q2 = q - nw1;
+        for (int z = 0; z < f.S2; ++z) g += f.ws2[(int64_t)z * nw2 + q2];
+        adam_step(f, o_w2 + q2, g);
+      }
+    }
+    return;
+  }
+  const int w = ((int)blockIdx.x - f.nbd) * 4 + (int)(threadIdx.x >> 6);
+  const int n3 = f.d * (f.H2 + 1);
+  if (w < f.H1) {
+    const float g = sum_chunks(f.colpart, f.nb1, f.H1, w);
+    if (lane_id() == 0) adam_step(f, o_b1 + w, g);
+  } else if (w < f.H1 + f.H2) {
+    const int k = w - f.H1;
+    const float g = sum_chunks(f.part2, f.nchunk, f.H2, k);
+    if (lane_id() == 0) adam_step(f, o_b2 + k, g);
+  } else if (w < f.H1 + f.H2 + n3) {
+    const int q = w - f.H1 - f.H2;
+    const float g = sum_chunks(f.part3, f.nchunk, n3, q);
+    const int j = q / (f.H2 + 1), k = q - j * (f.H2 + 1);
+    if (lane_id() == 0) adam_step(f, k < f.H2 ? o_w3 + (int64_t)j * f.H2 + k : o_b3 + j, g);
+  } else if (w == f.H1 + f.H2 + n3 && f.lchunk) {
+    const float l = sum_chunks(f.lchunk, f.nchunk, 1, 0);
+    if (lane_id() == 0) f.lpart[0] = (f.accumulate ? f.lpart[0] : 0.0f) + l;
   }
 }
 
@@ -528,74 +762,113 @@ Views views(const fsne_mlp* m, float* base) {
   return v;
 }
 
-// Forward of n batch rows already in Xb: H1b, H2b, Ob.
-fsne_status forward(fsne_mlp* m, int n) {
+// Forward of n batch rows (FP32, row stride D: Xb, or xin when given): H1b,
+// H2b, and with out the network's output Ob (training takes the output
+// inside the loss kernel).
+fsne_status forward(fsne_mlp* m, int n, bool out = true, const float* xin = nullptr) {
   hipStream_t s = m->stream;
   const Views P = views(m, m->P);
-  MCHK(m, gemm(s, m->Xb, m->D, 1, P.W1, 1, m->D, m->H1b, m->H1, n, m->H1, m->D,
+  const float* X = xin ? xin : m->Xb;
+  MCHK(m, gemm(s, X, m->D, 1, P.W1, 1, m->D, m->H1b, m->H1, n, m->H1, m->D,
                kEpiBias | kEpiRelu, P.b1));
   MCHK(m, gemm(s, m->H1b, m->H1, 1, P.W2, 1, m->H1, m->H2b, m->H2, n, m->H2, m->H1,
                kEpiBias | kEpiRelu, P.b2));
-  hipLaunchKernelGGL(k_out_layer, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, m->H2b, P.W3,
-                     P.b3, n, m->H2, m->d, m->Ob);
-  MCHK(m, hipGetLastError());
+  if (out || !m->fused_head) {
+    hipLaunchKernelGGL(k_out_layer, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, m->H2b, P.W3,
+                       P.b3, n, m->H2, m->d, m->Ob);
+    MCHK(m, hipGetLastError());
+  }
   return FSNE_OK;
 }
 
-// Column sums of an n x cols batch matrix into out, via row-chunk partials.
-fsne_status colsum(fsne_mlp* m, const float* M, int n, int cols, float* out) {
-  const int nchunk = (n + kRowChunk - 1) / kRowChunk;
-  const unsigned gx = (unsigned)((cols + 255) / 256);
-  hipLaunchKernelGGL(k_colsum_part, dim3(gx, (unsigned)nchunk), dim3(256), 0, m->stream, M, n,
-                     cols, m->part);
-  MCHK(m, hipGetLastError());
-  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((cols + 3) / 4)), dim3(256), 0, m->stream,
-                     m->part, nchunk, cols, out);
-  MCHK(m, hipGetLastError());
-  return FSNE_OK;
-}
-
-// Loss and gradient (into G) of n batch rows with targets in Tb; the loss
-// partials are added to the running sums when accumulate is set.
-fsne_status backward(fsne_mlp* m, int n, int accumulate = 0) {
+// Loss and gradient (into G) of n batch rows with targets in Tb, and with
+// adam the Adam step; the loss of the batch is added to the running sum when
+// accumulate is set.  Launches: the output layer and loss gradient (one
+// kernel), the W2 gradient (split-K partials), dH1 with the b1 column sums,
+// the W1 gradient (partials), and one kernel that sums every gradient and
+// steps the parameters.
+fsne_status backward(fsne_mlp* m, int n, int accumulate, bool adam_step_on,
+                     const float* xin = nullptr, Targets tgt = Targets{}) {
   hipStream_t s = m->stream;
+  const float* X = xin ? xin : m->Xb;
   const Views P = views(m, m->P);
-  const Views Gv = views(m, m->G);
   const int64_t cnt = (int64_t)n * m->d;
-  hipLaunchKernelGGL(k_dout, dim3(kLossBlocks), dim3(256), 0, s, m->Ob, m->Tb, cnt,
-                     1.0f / (float)cnt, m->dOb, m->lpart, accumulate);
-  MCHK(m, hipGetLastError());
-  const int q = m->d * (m->H2 + 1);
   const int nchunk = (n + kRowChunk - 1) / kRowChunk;
-  hipLaunchKernelGGL(k_grad_out_part, dim3((unsigned)((q + 255) / 256), (unsigned)nchunk),
-                     dim3(256), 0, s, m->dOb, m->H2b, n, m->H2, m->d, m->part);
-  MCHK(m, hipGetLastError());
-  hipLaunchKernelGGL(k_grad_out_sum, dim3((unsigned)((q + 3) / 4)), dim3(256), 0, s, m->part,
-                     nchunk, m->H2, m->d, Gv.W3, Gv.b3);
-  MCHK(m, hipGetLastError());
-  hipLaunchKernelGGL(k_back_out, dim3(1024), dim3(256), 0, s, m->dOb, P.W3, m->H2b, n, m->H2,
-                     m->d, m->dH2);
-  MCHK(m, hipGetLastError());
-  // gW2 = dH2^T H1, gb2 = column sums of dH2
-  MCHK(m, gemm(s, m->dH2, 1, m->H2, m->H1b, m->H1, 1, Gv.W2, m->H1, m->H2, m->H1, n, 0,
-               nullptr, nullptr, 0, m->ws));
-  MTRY(colsum(m, m->dH2, n, m->H2, Gv.b2));
-  // dH1 = (dH2 W2) where H1 > 0
-  MCHK(m, gemm(s, m->dH2, m->H2, 1, P.W2, m->H1, 1, m->dH1, m->H1, n, m->H1, m->H2, kEpiMask,
-               nullptr, m->H1b, m->H1));
-  // gW1 = dH1^T X, gb1 = column sums of dH1
-  MCHK(m, gemm(s, m->dH1, 1, m->H1, m->Xb, m->D, 1, Gv.W1, m->D, m->H1, m->D, n, 0,
-               nullptr, nullptr, 0, m->ws));
-  MTRY(colsum(m, m->dH1, n, m->H1, Gv.b1));
-  return FSNE_OK;
-}
-
-fsne_status adam(fsne_mlp* m) {
-  m->t += 1;
-  const fsne_mlp_opts& o = m->opts;
-  const float c1 = 1.0f - powf(o.beta1, (float)m->t), c2 = 1.0f - powf(o.beta2, (float)m->t);
-  hipLaunchKernelGGL(k_adam, dim3(1024), dim3(256), 0, m->stream, m->P, m->Mo, m->Vo, m->G, m->np,
-                     o.lr, o.beta1, o.beta2, o.eps, c1, c2);
+  if (m->fused_head) {
+    const size_t shm = sizeof(float) * 6 * kRowChunk * m->d;
+    const float sc = 1.0f / (float)cnt;
+    if (!tgt.Y) tgt.T = m->Tb;
+#define FSNE_HEAD(Sv)                                                                            \
+  hipLaunchKernelGGL((k_head<Sv>), dim3((unsigned)nchunk), dim3(256), shm, s, m->H2b, P.W3, P.b3,  \
+                     tgt, n, m->H2, m->d, sc, m->dH2, m->part, m->part3, m->lchunk)
+    if (m->H2 <= 256)
+      FSNE_HEAD(1);
+    else if (m->H2 <= 512)
+      FSNE_HEAD(2);
+    else
+      FSNE_HEAD(4);
+#undef FSNE_HEAD
+    MCHK(m, hipGetLastError());
+  } else {
+    hipLaunchKernelGGL(k_dout, dim3(kLossBlocks), dim3(256), 0, s, m->Ob, m->Tb, cnt,
+                       1.0f / (float)cnt, m->dOb, m->lpart, accumulate);
+    MCHK(m, hipGetLastError());
+    const int q = m->d * (m->H2 + 1);
+    hipLaunchKernelGGL(k_grad_out_part, dim3((unsigned)((q + 255) / 256), (unsigned)nchunk),
+                       dim3(256), 0, s, m->dOb, m->H2b, n, m->H2, m->d, m->part3);
+    MCHK(m, hipGetLastError());
+    hipLaunchKernelGGL(k_back_out, dim3(1024), dim3(256), 0, s, m->dOb, P.W3, m->H2b, n, m->H2,
+                       m->d, m->dH2);
+    MCHK(m, hipGetLastError());
+    hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((m->H2 + 255) / 256), (unsigned)nchunk),
+                       dim3(256), 0, s, m->dH2, n, m->H2, m->part);
+    MCHK(m, hipGetLastError());
+  }
+  // W2 gradient dH2^T H1 as split-K partials
+  int S2 = 1, S1 = 1;
+  MCHK(m, gemm(s, m->dH2, 1, m->H2, m->H1b, m->H1, 1, nullptr, m->H1, m->H2, m->H1, n, 0,
+               nullptr, nullptr, 0, m->ws2, &S2));
+  // dH1 = (dH2 W2) where H1 > 0, with its column sums per 64-row block (b1)
+  MCHK(m, gemm(s, m->dH2, m->H2, 1, P.W2, m->H1, 1, m->dH1, m->H1, n, m->H1, m->H2,
+               kEpiMask | kEpiColSum, nullptr, m->H1b, m->H1, nullptr, nullptr, m->colpart));
+  // W1 gradient dH1^T X as split-K partials
+  MCHK(m, gemm(s, m->dH1, 1, m->H1, X, m->D, 1, nullptr, m->D, m->H1, m->D, n, 0,
+               nullptr, nullptr, 0, m->ws, &S1));
+  FinishArgs f{};
+  f.P = m->P;
+  f.M = m->Mo;
+  f.V = m->Vo;
+  f.G = m->G;
+  f.H1 = m->H1;
+  f.D = m->D;
+  f.H2 = m->H2;
+  f.d = m->d;
+  f.ws1 = m->ws;
+  f.S1 = S1;
+  f.ws2 = m->ws2;
+  f.S2 = S2;
+  f.colpart = m->colpart;
+  f.nb1 = (n + kTM - 1) / kTM;
+  f.part2 = m->part;
+  f.part3 = m->part3;
+  f.nchunk = nchunk;
+  f.lchunk = m->fused_head ? m->lchunk : nullptr;
+  f.lpart = m->lpart;
+  f.accumulate = accumulate;
+  f.nbd = 1024;
+  f.adam = adam_step_on ? 1 : 0;
+  if (adam_step_on) {
+    m->t += 1;
+    const fsne_mlp_opts& o = m->opts;
+    f.lr = o.lr;
+    f.b1 = o.beta1;
+    f.b2 = o.beta2;
+    f.eps = o.eps;
+    f.c1 = 1.0f - powf(o.beta1, (float)m->t);
+    f.c2 = 1.0f - powf(o.beta2, (float)m->t);
+  }
+  const int waves = m->H1 + m->H2 + m->d * (m->H2 + 1) + 1;
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)(f.nbd + (waves + 3) / 4)), dim3(256), 0, s, f);
   MCHK(m, hipGetLastError());
   return FSNE_OK;
 }
@@ -670,6 +943,9 @@ fsne_status fsne_mlp_create(const fsne_ctx* ctx, const fsne_mlp_opts* opts, fsne
   m->opts = *opts;
   m->np = (int64_t)m->H1 * m->D + m->H1 + (int64_t)m->H2 * m->H1 + m->H2 + (int64_t)m->d * m->H2 + m->d;
   const size_t B = (size_t)opts->batch;
+  const size_t nchunk_max = (B + kRowChunk - 1) / kRowChunk;
+  // the output layer goes into one kernel while H2 fits four columns a thread
+  m->fused_head = m->H2 <= 1024 && m->d <= 64;
   auto bad = [&](fsne_status st) {
     fsne_mlp_destroy(m);
     return st;
@@ -684,15 +960,17 @@ fsne_status fsne_mlp_create(const fsne_ctx* ctx, const fsne_mlp_opts* opts, fsne
       (st = malloc_dev(m, &m->Ob, B * m->d)) || (st = malloc_dev(m, &m->dOb, B * m->d)) ||
       (st = malloc_dev(m, &m->dH1, B * m->H1)) || (st = malloc_dev(m, &m->dH2, B * m->H2)) ||
       (st = malloc_dev(m, &m->lpart, kLossBlocks)) ||
-      (st = malloc_dev(m, &m->ws, (size_t)kMaxSplit *
-                                      std::max<size_t>((size_t)m->H1 * m->D, (size_t)m->H2 * m->H1))) ||
-      (st = malloc_dev(m, &m->part, ((B + kRowChunk - 1) / kRowChunk) *
-                                        std::max<size_t>(std::max(m->H1, m->H2),
-                                                         (size_t)m->d * (m->H2 + 1)))) ||
+      (st = malloc_dev(m, &m->ws, (size_t)kMaxSplit * m->H1 * m->D)) ||
+      (st = malloc_dev(m, &m->ws2, (size_t)kMaxSplit * m->H2 * m->H1)) ||
+      (st = malloc_dev(m, &m->part, nchunk_max * m->H2)) ||
+      (st = malloc_dev(m, &m->part3, nchunk_max * m->d * (m->H2 + 1))) ||
+      (st = malloc_dev(m, &m->colpart, ((B + kTM - 1) / kTM) * m->H1)) ||
+      (st = malloc_dev(m, &m->lchunk, nchunk_max)) ||
       (st = malloc_dev(m, reinterpret_cast<uint8_t**>(&m->xstage), B * m->D * 4)))
     return bad(st);
   if (hipMemsetAsync(m->Mo, 0, sizeof(float) * m->np, m->stream) != hipSuccess ||
-      hipMemsetAsync(m->Vo, 0, sizeof(float) * m->np, m->stream) != hipSuccess)
+      hipMemsetAsync(m->Vo, 0, sizeof(float) * m->np, m->stream) != hipSuccess ||
+      hipMemsetAsync(m->lpart, 0, sizeof(float) * kLossBlocks, m->stream) != hipSuccess)
     return bad(FSNE_EHIP);
   const Views P = views(m, m->P);
   float* layer_base[3] = {P.W1, P.W2, P.W3};
@@ -735,12 +1013,22 @@ fsne_status fsne_mlp_train(fsne_mlp* m, fsne_ctx* ctx, float* final_loss) {
     const int last = e == m->opts.epochs - 1;
     for (int64_t b = 0; b < nb; ++b) {
       const int n = (int)std::min<int64_t>(B, N - b * B);
-      hipLaunchKernelGGL(k_gather, dim3(1024), dim3(256), 0, m->stream, ctx->X, ctx->xdtype, m->D,
-                         N, off + b * B, n, ctx->Y, ctx->DP, m->d, m->ymean, m->ystd, m->Xb, m->Tb);
-      MCHK(m, hipGetLastError());
-      MTRY(forward(m, n));
-      MTRY(backward(m, n, last));
-      MTRY(adam(m));
+      const int64_t row0 = (off + b * B) % N;
+      // FP32 rows that do not wrap around are read where they are
+      const float* xin = ctx->xdtype == FSNE_F32 && (m->D & 3) == 0 && row0 + n <= N
+                             ? static_cast<const float*>(ctx->X) + row0 * m->D
+                             : nullptr;
+      // with the fused loss kernel the targets are read there from Y
+      Targets tgt{};
+      if (m->fused_head) tgt = Targets{nullptr, ctx->Y, N, off + b * B, ctx->DP, m->ymean, m->ystd};
+      if (!xin || !m->fused_head) {
+        hipLaunchKernelGGL(k_gather, dim3(1024), dim3(256), 0, m->stream, ctx->X, ctx->xdtype,
+                           m->D, N, off + b * B, n, ctx->Y, ctx->DP, m->d, m->ymean, m->ystd,
+                           xin ? nullptr : m->Xb, m->Tb);
+        MCHK(m, hipGetLastError());
+      }
+      MTRY(forward(m, n, false, xin));
+      MTRY(backward(m, n, last, true, xin, tgt));
     }
   }
   // mean squared error over the last epoch (each of the N rows once)
@@ -793,8 +1081,8 @@ fsne_status fsne_mlp_loss_grad(fsne_mlp* m, const void* X, const float* T, int64
   if (!X || !T || n < 1 || n > m->opts.batch)
     return mfail(m, FSNE_EINVAL, "bad arguments to fsne_mlp_loss_grad");
   MTRY(upload_batch(m, X, T, n));
-  MTRY(forward(m, (int)n));
-  MTRY(backward(m, (int)n));
+  MTRY(forward(m, (int)n, false));
+  MTRY(backward(m, (int)n, 0, false));
   if (grad)
     MCHK(m, hipMemcpyAsync(grad, m->G, sizeof(float) * m->np, hipMemcpyDeviceToHost, m->stream));
   const float l = loss_of(m, n * m->d);
@@ -807,9 +1095,8 @@ fsne_status fsne_mlp_train_batch(fsne_mlp* m, const void* X, const float* T, int
   if (!X || !T || n < 1 || n > m->opts.batch)
     return mfail(m, FSNE_EINVAL, "bad arguments to fsne_mlp_train_batch");
   MTRY(upload_batch(m, X, T, n));
-  MTRY(forward(m, (int)n));
-  MTRY(backward(m, (int)n));
-  MTRY(adam(m));
+  MTRY(forward(m, (int)n, false));
+  MTRY(backward(m, (int)n, 0, true));
   MCHK(m, hipStreamSynchronize(m->stream));
   return FSNE_OK;
 }
@@ -818,7 +1105,8 @@ void fsne_mlp_destroy(fsne_mlp* m) {
   if (!m) return;
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   void* bufs[] = {m->P, m->G, m->Mo, m->Vo, m->ymean, m->ystd, m->Xb, m->Tb, m->H1b, m->H2b,
-                  m->Ob, m->dOb, m->dH1, m->dH2, m->lpart, m->ws, m->part, m->xstage};
+                  m->Ob, m->dOb, m->dH1, m->dH2, m->lpart, m->ws, m->ws2, m->part, m->part3,
+                  m->colpart, m->lchunk, m->xstage};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (m->stream) (void)hipStreamDestroy(m->stream);

@@ -1,10 +1,16 @@
 """Dynamic data with learned placement (scaled version of the 500k-point
 insertion workload): new points placed by the trained network reach the
-LD neighbour recall target in fewer iterations than points placed at random."""
+LD neighbour recall target in fewer iterations than points placed at random.
+
+The rows come from the styled image-like generator (a 3-dimensional style
+manifold within each class), as in the benchmark's online-use leg: with
+independent pixel drops the exact neighbours have no low-dimensional
+structure, the base embedding's recall sits near chance, and a target
+derived from it does not separate the two placements."""
 import numpy as np
 import pytest
 
-from inputs.generators import image_like, y_init
+from inputs.generators import image_styles, y_init
 from inputs.knn_metrics import exact_knn
 
 pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::RuntimeWarning")]
@@ -25,7 +31,8 @@ def ld_recall(Y, rows, hd_nn, K):
 def test_learned_placement_beats_random_init(fsne_lib):
     F = fsne_lib
     N0, n_new, K = 12000, 1200, 32
-    X, _ = image_like(n_per_class=(N0 + n_new) // 10, seed=1004, proto_seed=1002)
+    classes = np.random.default_rng(1004).integers(0, 10, N0 + n_new)
+    X, _ = image_styles(classes, seed=1004, proto_seed=1002)
     Xb, Xn = X[:N0], X[N0:N0 + n_new]
     hp = F.fsne_default_hparams(perplexity=10.0, lr=N0 / 12.0, attr=12.0, n_neg=16)
     base = F.Embedding(Xb, y_init(N0, 2), 2, K, K, seed=5, hp=hp)
@@ -56,6 +63,6 @@ def test_learned_placement_beats_random_init(fsne_lib):
         iters[mode] = 10_000 if reached is None else reached
         emb.close()
     print("iterations to the recall target", iters, "target", target)
-    assert iters["mlp"] < iters["random"], iters
+    assert iters["mlp"] <= 600 and iters["mlp"] < iters["random"], iters
     net.close()
     base.close()
