@@ -370,8 +370,12 @@ fsne_status fsne_mlp_create(const fsne_ctx *ctx, const fsne_mlp_opts *opts, fsne
 /* Fit the network to ctx's current points (x_i, y_i), i < N: the
  * standardisation is taken from ctx's Y, then opts.epochs passes of Adam
  * steps over batches of opts.batch consecutive rows (epoch e starts at row
- * 104729 e mod N).  *final_loss (may be NULL) gets the mean loss of the last
- * epoch.  Synchronises ctx's stream first.  Errors: FSNE_EINVAL, FSNE_EHIP. */
+ * 104729 e mod N).  The products read their operands as bfloat16: with FP32
+ * rows, D a multiple of 8 and more than one epoch, the call holds a
+ * bfloat16 copy of X (N D 2 bytes of device memory, freed before it
+ * returns; if it cannot be allocated the rows are rounded batch by batch).
+ * *final_loss (may be NULL) gets the mean loss of the last epoch.
+ * Synchronises ctx's stream first.  Errors: FSNE_EINVAL, FSNE_EHIP. */
 fsne_status fsne_mlp_train(fsne_mlp *m, fsne_ctx *ctx, float *final_loss);
 
 /* Predict y for n host rows X (the context's dtype) into host Y (n x d). */

@@ -2,7 +2,10 @@
 // layers, trained by mean squared error on (x, standardised y) pairs of a
 // context's embedding with Adam, then used to place inserted or drifted
 // points.  The three large products run as BF16 MFMA GEMMs with FP32
-// accumulation (operands rounded to nearest even when staged into LDS); the
+// accumulation; their operands are kept in memory as bfloat16 (rounded to
+// nearest even once, where they are produced: the batch rows by the gather,
+// W1 and W2 by the optimiser step, H1, dH1 and dH2 by the kernels that
+// compute them), so a GEMM reads half the bytes and converts nothing.  The
 // d-wide output layer, the loss, the reductions and Adam are FP32 vector
 // code.  Parameters are one flat FP32 buffer:
 //   W1 (H1 x D), b1 (H1), W2 (H2 x H1), b2 (H2), W3 (d x H2), b3 (d).
@@ -23,8 +26,10 @@ struct fsne_mlp {
   hipStream_t stream = nullptr;
   float *P = nullptr, *G = nullptr, *Mo = nullptr, *Vo = nullptr;   // params, grad, Adam moments
   float *ymean = nullptr, *ystd = nullptr;                            // d each
-  float *Xb = nullptr, *Tb = nullptr, *H1b = nullptr, *H2b = nullptr; // batch buffers
-  float *Ob = nullptr, *dOb = nullptr, *dH1 = nullptr, *dH2 = nullptr;
+  float *Tb = nullptr, *H2b = nullptr, *Ob = nullptr, *dOb = nullptr, *dH2 = nullptr;  // batch, FP32
+  uint16_t *Xb = nullptr, *H1b = nullptr, *dH1b = nullptr, *dH2b = nullptr;        // batch, BF16
+  uint16_t *W1b = nullptr, *W2b = nullptr;   // W1, W2 rounded to BF16
+  bool wdirty = true;          // W1b / W2b must be rounded again from P
   float* lpart = nullptr;      // loss partial sums
   float* ws = nullptr;         // split-K partial products of the W1 gradient
   float* ws2 = nullptr;        // split-K partial products of the W2 gradient
@@ -52,15 +57,16 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 struct GemmArgs {
-  const float* A;
+  const uint16_t* A;       // bfloat16 bits
   int64_t sam, sak;        // A(m, k) = A[m sam + k sak]
-  const float* B;
+  const uint16_t* B;       // bfloat16 bits
   int64_t sbk, sbn;        // B(k, n) = B[k sbk + n sbn]
-  float* C;
+  float* C;                // FP32 output, or
+  uint16_t* Cb;            // bfloat16 output (rounded to nearest even)
   int64_t ldc;             // C(m, n) = C[m ldc + n]
   int M, N, K;
   const float* bias;       // C(m, n) += bias[n]
-  const float* mask;       // C(m, n) = 0 where mask[m ldm + n] <= 0
+  const uint16_t* mask;    // C(m, n) = 0 unless the bfloat16 mask[m ldm + n] > 0
   int64_t ldm;
   int epi;
   float* ws;               // partials mode: the product of split z (no epilogue) at
@@ -70,10 +76,13 @@ struct GemmArgs {
                            // rows of row block by of C(m, n) after the epilogue
 };
 
+// bfloat16 bits of f, rounded to nearest even (v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint16_t to_bf16(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
+
+// True where the bfloat16 value is > 0 (sign clear, not zero).
+__device__ __forceinline__ bool bf16_pos(uint16_t b) { return b != 0 && !(b & 0x8000u); }
 
 // The tile (bx, by, bz) a block computes.  Workgroups go to the chip's
 // eight XCDs in turn (linear id mod 8), each XCD with its own L2; when the
@@ -123,8 +132,11 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, const f32x16& a
       float v = acc[r];
       if (g.epi & kEpiBias) v += g.bias[n];
       if (g.epi & kEpiRelu) v = v > 0.0f ? v : 0.0f;
-      if (g.epi & kEpiMask) v = g.mask[(int64_t)m * g.ldm + n] > 0.0f ? v : 0.0f;
-      g.C[(int64_t)m * g.ldc + n] = v;
+      if (g.epi & kEpiMask) v = bf16_pos(g.mask[(int64_t)m * g.ldm + n]) ? v : 0.0f;
+      if (g.Cb)
+        g.Cb[(int64_t)m * g.ldc + n] = to_bf16(v);
+      else
+        g.C[(int64_t)m * g.ldc + n] = v;
       cs += v;
     }
   }
@@ -140,7 +152,7 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, const f32x16& a
 }
 
 // C = A B (+ bias, ReLU, mask).  64 x 64 tiles, 4 waves of 32 x 32, K steps
-// of 32 staged in LDS as bfloat16, v_mfma_f32_32x32x16_bf16; any strides.
+// of 32 staged in LDS, v_mfma_f32_32x32x16_bf16; any strides.
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ __align__(16) uint16_t As[kBM][kLDP];   // [m][k]
   __shared__ __align__(16) uint16_t Bs[kBN][kLDP];   // [n][k]
@@ -157,14 +169,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     for (int e = tid; e < kBM * kBK; e += 256) {
       const int m = a_k ? e / kBK : e % kBM, k = a_k ? e % kBK : e / kBM;
       const int gm = bm + m, gk = k0 + k;
-      const float v = (gm < g.M && gk < kend) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0.0f;
-      As[m][k] = to_bf16(v);
+      As[m][k] = (gm < g.M && gk < kend) ? g.A[(int64_t)gm * g.sam + (int64_t)gk * g.sak] : 0;
     }
     for (int e = tid; e < kBN * kBK; e += 256) {
       const int n = b_k ? e / kBK : e % kBN, k = b_k ? e % kBK : e / kBN;
       const int gn = bn + n, gk = k0 + k;
-      const float v = (gn < g.N && gk < kend) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0.0f;
-      Bs[n][k] = to_bf16(v);
+      Bs[n][k] = (gn < g.N && gk < kend) ? g.B[(int64_t)gk * g.sbk + (int64_t)gn * g.sbn] : 0;
     }
     __syncthreads();
 #pragma unroll
@@ -179,74 +189,70 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   gemm_epilogue(g, acc, tl, wm, wn, lane, colacc);
 }
 
-// Four consecutive elements p[0..3] of an operand along its contiguous index,
-// which starts at c; elements at or beyond lim read as 0.
-__device__ __forceinline__ float4 load4(const float* p, int c, int lim) {
-  if (c + 3 < lim) return *reinterpret_cast<const float4*>(p);
-  float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  if (c < lim) v.x = p[0];
-  if (c + 1 < lim) v.y = p[1];
-  if (c + 2 < lim) v.z = p[2];
-  return v;
+// Eight consecutive bfloat16 elements p[0..7] of an operand along its
+// contiguous index, which starts at c; elements at or beyond lim read as 0.
+__device__ __forceinline__ uint4 load8(const uint16_t* p, int c, int lim) {
+  if (c + 7 < lim) return *reinterpret_cast<const uint4*>(p);
+  uint16_t e[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) e[i] = c + i < lim ? p[i] : 0;
+  return make_uint4(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
+                    e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16));
 }
 
-__device__ __forceinline__ uint2 pack4_bf16(float4 v) {
-  return make_uint2((uint32_t)to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16),
-                    (uint32_t)to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16));
+__device__ __forceinline__ uint32_t half_of(const uint4& v, int i) {
+  const uint32_t w = i < 2 ? v.x : i < 4 ? v.y : i < 6 ? v.z : v.w;
+  return (i & 1) ? w >> 16 : w & 0xFFFFu;
 }
 
-// One 64 x 64 FP32 tile of an operand as 4 float4 per thread.  KC: the
-// operand is contiguous along k (rows r of the tile are its m or n index),
-// and each thread loads 4 rows of 4 k; otherwise it is contiguous along
-// m / n, and each thread loads a 4 (k) x 4 (r) block, so that it can store
-// 4 consecutive k of one row at once.
+// One 64 x 64 bfloat16 tile of an operand as two 16-byte loads per thread.
+// KC: the operand is contiguous along k (rows r of the tile are its m or n
+// index): each load takes 8 k of one row.  Otherwise it is contiguous along
+// m / n: the thread loads 8 rows at k and at k + 1, so that it can store
+// both k of one row at once.
 template <bool KC>
-__device__ __forceinline__ void tile_load(const float* __restrict__ P, int64_t s_r, int64_t s_k,
-                                          int r0, int rlim, int k0, int klim, float4* v) {
+__device__ __forceinline__ void tile_load(const uint16_t* __restrict__ P, int64_t s_r,
+                                          int64_t s_k, int r0, int rlim, int k0, int klim,
+                                          uint4* v) {
   const int tid = threadIdx.x;
+  if constexpr (KC) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int idx = tid + 256 * j;
-    if constexpr (KC) {
-      const int r = idx >> 4, k = (idx & 15) << 2;
+    for (int j = 0; j < 2; ++j) {
+      const int idx = tid + 256 * j;
+      const int r = idx >> 3, k = (idx & 7) << 3;
       const int gr = r0 + r, gk = k0 + k;
-      v[j] = gr < rlim ? load4(P + (int64_t)gr * s_r + gk, gk, klim)
-                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    } else {
-      const int k = ((tid >> 4) << 2) + j, r = (tid & 15) << 2;
-      const int gr = r0 + r, gk = k0 + k;
-      v[j] = gk < klim ? load4(P + (int64_t)gk * s_k + gr, gr, rlim)
-                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      v[j] = gr < rlim ? load8(P + (int64_t)gr * s_r + gk, gk, klim) : make_uint4(0, 0, 0, 0);
+    }
+  } else {
+    const int k = (tid >> 3) << 1, r = (tid & 7) << 3;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gk = k0 + k + j, gr = r0 + r;
+      v[j] = gk < klim ? load8(P + (int64_t)gk * s_k + gr, gr, rlim) : make_uint4(0, 0, 0, 0);
     }
   }
 }
 
-// Rounds the tile to bfloat16 into LDS columns k0 .. k0+63, laid out [row][k].
+// Stores the tile into LDS columns k0 .. k0+63, laid out [row][k].
 template <bool KC, int TP>
-__device__ __forceinline__ void tile_store(uint16_t (*L)[TP], int k0, const float4* v) {
+__device__ __forceinline__ void tile_store(uint16_t (*L)[TP], int k0, const uint4* v) {
   const int tid = threadIdx.x;
+  if constexpr (KC) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int idx = tid + 256 * j;
-    if constexpr (KC) {
-      const int r = idx >> 4, k = (idx & 15) << 2;
-      *reinterpret_cast<uint2*>(&L[r][k0 + k]) = pack4_bf16(v[j]);
+    for (int j = 0; j < 2; ++j) {
+      const int idx = tid + 256 * j;
+      *reinterpret_cast<uint4*>(&L[idx >> 3][k0 + ((idx & 7) << 3)]) = v[j];
     }
-  }
-  if constexpr (!KC) {
-    // v[j] holds rows r .. r+3 at k + j: row r + i gets k .. k+3 in one store
-    const int k = (tid >> 4) << 2, r = (tid & 15) << 2;
-    const float c[4][4] = {{v[0].x, v[1].x, v[2].x, v[3].x}, {v[0].y, v[1].y, v[2].y, v[3].y},
-                           {v[0].z, v[1].z, v[2].z, v[3].z}, {v[0].w, v[1].w, v[2].w, v[3].w}};
+  } else {
+    const int k = (tid >> 3) << 1, r = (tid & 7) << 3;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      *reinterpret_cast<uint2*>(&L[r + i][k0 + k]) =
-          pack4_bf16(make_float4(c[i][0], c[i][1], c[i][2], c[i][3]));
+    for (int i = 0; i < 8; ++i)
+      *reinterpret_cast<uint32_t*>(&L[r + i][k0 + k]) = half_of(v[0], i) | (half_of(v[1], i) << 16);
   }
 }
 
-// C = A B (+ bias, ReLU, mask, column sums) with 16-byte operand loads.  A K
-// step covers R sub-tiles of 64 (R kTK columns of A and rows of B in LDS),
+// C = A B (+ bias, ReLU, mask, column sums) with 16-byte bfloat16 operand
+// loads.  A K step covers R sub-tiles of 64 (R kTK columns of A and rows of B in LDS),
 // and the next step's operands are loaded into registers while the current
 // one is multiplied: the fewer, deeper steps leave fewer waits on a load.
 // AK / BK: A / B contiguous along k (else along m / n).  gridDim.z splits K
@@ -265,7 +271,7 @@ __global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g) {
   const int kend = min(g.K, kbeg + g.kchunk);
   const int64_t a_r = AK ? g.sam : 0, a_k = AK ? 0 : g.sak;
   const int64_t b_r = BK ? g.sbn : 0, b_k = BK ? 0 : g.sbk;
-  float4 ra[R][4], rb[R][4];
+  uint4 ra[R][2], rb[R][2];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     tile_load<AK>(g.A, a_r, a_k, bm, g.M, kbeg + kTK * q, kend, ra[q]);
@@ -308,14 +314,15 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 // with ws (partials mode), the products of *splits K ranges into ws (no
 // epilogue; the caller sums them in split order).  Deep K steps where K is
 // long; split K where the tiles alone would not fill the chip.
-hipError_t gemm(hipStream_t s, const float* A, int64_t sam, int64_t sak, const float* B,
-                int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M, int N, int K, int epi,
-                const float* bias = nullptr, const float* mask = nullptr, int64_t ldm = 0,
-                float* ws = nullptr, int* splits = nullptr, float* colpart = nullptr) {
-  GemmArgs g{A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, bias, mask, ldm, epi, ws, K, colpart};
+hipError_t gemm(hipStream_t s, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
+                int64_t sbk, int64_t sbn, float* C, uint16_t* Cb, int64_t ldc, int M, int N,
+                int K, int epi, const float* bias = nullptr, const uint16_t* mask = nullptr,
+                int64_t ldm = 0, float* ws = nullptr, int* splits = nullptr,
+                float* colpart = nullptr) {
+  GemmArgs g{A, sam, sak, B, sbk, sbn, C, Cb, ldc, M, N, K, bias, mask, ldm, epi, ws, K, colpart};
   const bool ak = sak == 1, bk = sbk == 1;
-  const bool a_ok = ak ? (sam % 4 == 0) : (sam == 1 && sak % 4 == 0);
-  const bool b_ok = bk ? (sbn % 4 == 0) : (sbn == 1 && sbk % 4 == 0);
+  const bool a_ok = ak ? (sam % 8 == 0) : (sam == 1 && sak % 8 == 0);
+  const bool b_ok = bk ? (sbn % 8 == 0) : (sbn == 1 && sbk % 8 == 0);
   const bool vec = a_ok && b_ok && aligned16(A) && aligned16(B);
   const int tiles = ((N + kTN - 1) / kTN) * ((M + kTM - 1) / kTM);
   int S = 1;
@@ -356,34 +363,44 @@ hipError_t gemm(hipStream_t s, const float* A, int64_t sam, int64_t sak, const f
 }
 
 // Batch rows: row k is source row (off + k) mod N of X (FP32 or BF16 bits),
-// converted to FP32 into Xb (skipped when Xb is null: the rows are read in
+// rounded to bfloat16 into Xb (skipped when Xb is null: the rows are read in
 // place); targets (y - mean) / std from Y (padded stride DP).  One block per
 // row at a time.
 __global__ void k_gather(const void* X, int xdtype, int D, int64_t N, int64_t off, int n,
                          const float* Y, int DP, int d, const float* mean, const float* sd,
-                         float* Xb, float* Tb) {
+                         uint16_t* Xb, float* Tb) {
   for (int k = blockIdx.x; k < n; k += gridDim.x) {
     const int64_t r = (off + k) % N;
-    float* dst = Xb ? Xb + (int64_t)k * D : nullptr;
-    if (!Xb) {
-      // targets only (the rows are read in place)
-    } else if (xdtype == 0 && (D & 3) == 0) {
-      const float4* src = reinterpret_cast<const float4*>(static_cast<const float*>(X) + r * D);
-      float4* d4 = reinterpret_cast<float4*>(dst);
-      for (int c = threadIdx.x; c < (D >> 2); c += blockDim.x) d4[c] = src[c];
-    } else if (xdtype == 0) {
-      const float* src = static_cast<const float*>(X) + r * D;
-      for (int c = threadIdx.x; c < D; c += blockDim.x) dst[c] = src[c];
-    } else {
-      const uint16_t* src = static_cast<const uint16_t*>(X) + r * D;
-      for (int c = threadIdx.x; c < D; c += blockDim.x)
-        dst[c] = __uint_as_float((uint32_t)src[c] << 16);
+    if (Xb) {
+      uint16_t* dst = Xb + (int64_t)k * D;
+      if (xdtype == 0 && (D & 3) == 0) {
+        const float4* src = reinterpret_cast<const float4*>(static_cast<const float*>(X) + r * D);
+        for (int c = threadIdx.x; c < (D >> 2); c += blockDim.x) {
+          const float4 v = src[c];
+          reinterpret_cast<uint2*>(dst)[c] =
+              make_uint2(to_bf16(v.x) | ((uint32_t)to_bf16(v.y) << 16),
+                         to_bf16(v.z) | ((uint32_t)to_bf16(v.w) << 16));
+        }
+      } else if (xdtype == 0) {
+        const float* src = static_cast<const float*>(X) + r * D;
+        for (int c = threadIdx.x; c < D; c += blockDim.x) dst[c] = to_bf16(src[c]);
+      } else {
+        const uint16_t* src = static_cast<const uint16_t*>(X) + r * D;
+        for (int c = threadIdx.x; c < D; c += blockDim.x) dst[c] = src[c];
+      }
     }
     if (Y && (int)threadIdx.x < d) {
       const int c = threadIdx.x;
       Tb[(int64_t)k * d + c] = (Y[r * DP + c] - mean[c]) / sd[c];
     }
   }
+}
+
+// dst[k] = src[k] rounded to bfloat16, k < n.
+__global__ void k_to_bf16(const float* src, uint16_t* dst, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = to_bf16(src[k]);
 }
 
 // Output layer: O[r][j] = b3[j] + sum_k H2[r][k] W3[j][k]; one wave per row.
@@ -448,16 +465,19 @@ __device__ __forceinline__ float sum_chunks(const float* part, int nchunk, int64
   return wave_sum_uniform(s);
 }
 
-// dH2[r][k] = (sum_j dO[r][j] W3[j][k]) where H2[r][k] > 0, else 0.
+// dH2[r][k] = (sum_j dO[r][j] W3[j][k]) where H2[r][k] > 0, else 0 (and
+// its bfloat16 rounding, the operand of the products that follow).
 __global__ void k_back_out(const float* dO, const float* W3, const float* H2, int n, int H, int d,
-                           float* dH2) {
+                           float* dH2, uint16_t* dH2b) {
   const int64_t total = (int64_t)n * H;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
        q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = q / H, k = q % H;
     float s = 0.0f;
     for (int j = 0; j < d; ++j) s = fmaf(dO[r * d + j], W3[(int64_t)j * H + k], s);
-    dH2[q] = H2[q] > 0.0f ? s : 0.0f;
+    const float v = H2[q] > 0.0f ? s : 0.0f;
+    dH2[q] = v;
+    dH2b[q] = to_bf16(v);
   }
 }
 
@@ -474,7 +494,8 @@ __global__ void k_colsum_part(const float* M, int n, int cols, float* part) {
 // The output layer and the loss gradient of one chunk of kRowChunk rows per
 // block, in one pass over H2 (S = columns per thread / 256, H <= 256 S):
 //   O[r][j] = b3[j] + sum_k H2[r][k] W3[j][k],  e = O - T,  dO = 2 e scale,
-//   dH2[r][k] = (sum_j dO[r][j] W3[j][k]) where H2[r][k] > 0, else 0,
+//   dH2[r][k] = (sum_j dO[r][j] W3[j][k]) where H2[r][k] > 0, else 0
+//               (stored rounded to bfloat16: it is only a product operand),
 // and the chunk's partial sums, each over its rows in order:
 //   part2[c][k] = sum_r dH2[r][k]                      (b2 gradient)
 //   part3[c][j (H+1) + k] = sum_r dO[r][j] H2[r][k]    (W3 gradient)
@@ -499,7 +520,7 @@ struct Targets {
 template <int S>
 __global__ __launch_bounds__(256) void k_head(const float* H2, const float* W3, const float* b3,
                                               Targets tgt, int n, int H, int d, float scale,
-                                              float* dH2, float* part2, float* part3,
+                                              uint16_t* dH2, float* part2, float* part3,
                                               float* lchunk) {
   extern __shared__ float red[];            // [4 waves][rows d], then dO, then e^2
   float* sdo = red + 4 * kRowChunk * d;
@@ -590,7 +611,7 @@ __global__ __launch_bounds__(256) void k_head(const float* H2, const float* W3, 
 #pragma unroll
     for (int r = 0; r < kRowChunk; ++r) {
       const float v = h[r][q] > 0.0f ? dh[r][q] : 0.0f;
-      if (r < rows && k < H) dH2[(int64_t)(r0 + r) * H + k] = v;
+      if (r < rows && k < H) dH2[(int64_t)(r0 + r) * H + k] = to_bf16(v);
       cs += v;
     }
     if (k < H) part2[(int64_t)c * H + k] = cs;
@@ -607,9 +628,11 @@ __global__ __launch_bounds__(256) void k_head(const float* H2, const float* W3, 
 // order.  The rest: one wave per b1, b2, W3, b3 entry (and one for the loss),
 // the sum of its row-block partials (lanes take blocks l, l + 64, ..., then
 // a fixed tree).  Every gradient goes to G; with adam the parameters take
-// their Adam step (Kingma and Ba 2015; c1 = 1 - b1^t, c2 = 1 - b2^t).
+// their Adam step (Kingma and Ba 2015; c1 = 1 - b1^t, c2 = 1 - b2^t), and the
+// new W1 and W2 are rounded to bfloat16 for the next products.
 struct FinishArgs {
   float *P, *M, *V, *G;
+  uint16_t *W1b, *W2b;             // with adam: the stepped W1, W2 rounded to bfloat16
   int H1, D, H2, d;
   const float* ws1; int S1;        // W1 partials: [S1][H1 D]
   const float* ws2; int S2;        // W2 partials: [S2][H2 H1]
@@ -620,14 +643,16 @@ struct FinishArgs {
   int adam; float lr, b1, b2, eps, c1, c2;
 };
 
-__device__ __forceinline__ void adam_step(const FinishArgs& f, int64_t k, float gk) {
+__device__ __forceinline__ float adam_step(const FinishArgs& f, int64_t k, float gk) {
   f.G[k] = gk;
-  if (!f.adam) return;
+  if (!f.adam) return 0.0f;
   const float mk = f.b1 * f.M[k] + (1.0f - f.b1) * gk;
   const float vk = f.b2 * f.V[k] + (1.0f - f.b2) * gk * gk;
   f.M[k] = mk;
   f.V[k] = vk;
-  f.P[k] -= f.lr * (mk / f.c1) / (sqrtf(vk / f.c2) + f.eps);
+  const float p = f.P[k] - f.lr * (mk / f.c1) / (sqrtf(vk / f.c2) + f.eps);
+  f.P[k] = p;
+  return p;
 }
 
 __global__ __launch_bounds__(256) void k_finish(FinishArgs f) {
@@ -640,11 +665,13 @@ __global__ __launch_bounds__(256) void k_finish(FinishArgs f) {
       float g = 0.0f;
       if (q < nw1) {
         for (int z = 0; z < f.S1; ++z) g += f.ws1[(int64_t)z * nw1 + q];
-        adam_step(f, q, g);
+        const float p = adam_step(f, q, g);
+        if (f.adam) f.W1b[q] = to_bf16(p);
       } else {
         const int64_t q2 = q - nw1;
         for (int z = 0; z < f.S2; ++z) g += f.ws2[(int64_t)z * nw2 + q2];
-        adam_step(f, o_w2 + q2, g);
+        const float p = adam_step(f, o_w2 + q2, g);
+        if (f.adam) f.W2b[q2] = to_bf16(p);
       }
     }
     return;
@@ -762,16 +789,24 @@ Views views(const fsne_mlp* m, float* base) {
   return v;
 }
 
-// Forward of n batch rows (FP32, row stride D: Xb, or xin when given): H1b,
-// H2b, and with out the network's output Ob (training takes the output
-// inside the loss kernel).
-fsne_status forward(fsne_mlp* m, int n, bool out = true, const float* xin = nullptr) {
+// Forward of n batch rows (bfloat16, row stride D: Xb, or xin when given):
+// H1b (bfloat16), H2b, and with out the network's output Ob (training takes
+// the output inside the loss kernel).
+fsne_status forward(fsne_mlp* m, int n, bool out = true, const uint16_t* xin = nullptr) {
   hipStream_t s = m->stream;
   const Views P = views(m, m->P);
-  const float* X = xin ? xin : m->Xb;
-  MCHK(m, gemm(s, X, m->D, 1, P.W1, 1, m->D, m->H1b, m->H1, n, m->H1, m->D,
+  if (m->wdirty) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(1024), dim3(256), 0, s, P.W1, m->W1b,
+                       (int64_t)m->H1 * m->D);
+    hipLaunchKernelGGL(k_to_bf16, dim3(1024), dim3(256), 0, s, P.W2, m->W2b,
+                       (int64_t)m->H2 * m->H1);
+    MCHK(m, hipGetLastError());
+    m->wdirty = false;
+  }
+  const uint16_t* X = xin ? xin : m->Xb;
+  MCHK(m, gemm(s, X, m->D, 1, m->W1b, 1, m->D, nullptr, m->H1b, m->H1, n, m->H1, m->D,
                kEpiBias | kEpiRelu, P.b1));
-  MCHK(m, gemm(s, m->H1b, m->H1, 1, P.W2, 1, m->H1, m->H2b, m->H2, n, m->H2, m->H1,
+  MCHK(m, gemm(s, m->H1b, m->H1, 1, m->W2b, 1, m->H1, m->H2b, nullptr, m->H2, n, m->H2, m->H1,
                kEpiBias | kEpiRelu, P.b2));
   if (out || !m->fused_head) {
     hipLaunchKernelGGL(k_out_layer, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, m->H2b, P.W3,
@@ -788,9 +823,9 @@ fsne_status forward(fsne_mlp* m, int n, bool out = true, const float* xin = null
 // the W1 gradient (partials), and one kernel that sums every gradient and
 // steps the parameters.
 fsne_status backward(fsne_mlp* m, int n, int accumulate, bool adam_step_on,
-                     const float* xin = nullptr, Targets tgt = Targets{}) {
+                     const uint16_t* xin = nullptr, Targets tgt = Targets{}) {
   hipStream_t s = m->stream;
-  const float* X = xin ? xin : m->Xb;
+  const uint16_t* X = xin ? xin : m->Xb;
   const Views P = views(m, m->P);
   const int64_t cnt = (int64_t)n * m->d;
   const int nchunk = (n + kRowChunk - 1) / kRowChunk;
@@ -800,7 +835,7 @@ fsne_status backward(fsne_mlp* m, int n, int accumulate, bool adam_step_on,
     if (!tgt.Y) tgt.T = m->Tb;
 #define FSNE_HEAD(Sv)                                                                            \
   hipLaunchKernelGGL((k_head<Sv>), dim3((unsigned)nchunk), dim3(256), shm, s, m->H2b, P.W3, P.b3,  \
-                     tgt, n, m->H2, m->d, sc, m->dH2, m->part, m->part3, m->lchunk)
+                     tgt, n, m->H2, m->d, sc, m->dH2b, m->part, m->part3, m->lchunk)
     if (m->H2 <= 256)
       FSNE_HEAD(1);
     else if (m->H2 <= 512)
@@ -818,7 +853,7 @@ fsne_status backward(fsne_mlp* m, int n, int accumulate, bool adam_step_on,
                        dim3(256), 0, s, m->dOb, m->H2b, n, m->H2, m->d, m->part3);
     MCHK(m, hipGetLastError());
     hipLaunchKernelGGL(k_back_out, dim3(1024), dim3(256), 0, s, m->dOb, P.W3, m->H2b, n, m->H2,
-                       m->d, m->dH2);
+                       m->d, m->dH2, m->dH2b);
     MCHK(m, hipGetLastError());
     hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((m->H2 + 255) / 256), (unsigned)nchunk),
                        dim3(256), 0, s, m->dH2, n, m->H2, m->part);
@@ -826,16 +861,18 @@ fsne_status backward(fsne_mlp* m, int n, int accumulate, bool adam_step_on,
   }
   // W2 gradient dH2^T H1 as split-K partials
   int S2 = 1, S1 = 1;
-  MCHK(m, gemm(s, m->dH2, 1, m->H2, m->H1b, m->H1, 1, nullptr, m->H1, m->H2, m->H1, n, 0,
-               nullptr, nullptr, 0, m->ws2, &S2));
+  MCHK(m, gemm(s, m->dH2b, 1, m->H2, m->H1b, m->H1, 1, nullptr, nullptr, m->H1, m->H2, m->H1,
+               n, 0, nullptr, nullptr, 0, m->ws2, &S2));
   // dH1 = (dH2 W2) where H1 > 0, with its column sums per 64-row block (b1)
-  MCHK(m, gemm(s, m->dH2, m->H2, 1, P.W2, m->H1, 1, m->dH1, m->H1, n, m->H1, m->H2,
+  MCHK(m, gemm(s, m->dH2b, m->H2, 1, m->W2b, m->H1, 1, nullptr, m->dH1b, m->H1, n, m->H1, m->H2,
                kEpiMask | kEpiColSum, nullptr, m->H1b, m->H1, nullptr, nullptr, m->colpart));
   // W1 gradient dH1^T X as split-K partials
-  MCHK(m, gemm(s, m->dH1, 1, m->H1, X, m->D, 1, nullptr, m->D, m->H1, m->D, n, 0,
+  MCHK(m, gemm(s, m->dH1b, 1, m->H1, X, m->D, 1, nullptr, nullptr, m->D, m->H1, m->D, n, 0,
                nullptr, nullptr, 0, m->ws, &S1));
   FinishArgs f{};
   f.P = m->P;
+  f.W1b = m->W1b;
+  f.W2b = m->W2b;
   f.M = m->Mo;
   f.V = m->Vo;
   f.G = m->G;
@@ -894,6 +931,35 @@ fsne_status upload_batch(fsne_mlp* m, const void* X, const float* T, int64_t n) 
     MCHK(m, hipMemcpyAsync(m->Tb, T, sizeof(float) * n * m->d, hipMemcpyHostToDevice, m->stream));
   return FSNE_OK;
 }
+
+// Adam steps over opts.epochs passes of batches (rows: the context's points
+// as bfloat16, or null: gathered per batch).
+fsne_status train_epochs(fsne_mlp* m, fsne_ctx* ctx, const uint16_t* rows, int64_t N, int64_t B,
+                         int64_t nb) {
+  for (int e = 0; e < m->opts.epochs; ++e) {
+    const int64_t off = ((int64_t)e * 104729) % N;
+    const int last = e == m->opts.epochs - 1;
+    for (int64_t b = 0; b < nb; ++b) {
+      const int n = (int)std::min<int64_t>(B, N - b * B);
+      const int64_t row0 = (off + b * B) % N;
+      // bfloat16 rows of a batch that does not wrap around are read in place
+      const uint16_t* xin = rows && row0 + n <= N ? rows + row0 * m->D : nullptr;
+      // with the fused loss kernel the targets are read there from Y
+      Targets tgt{};
+      if (m->fused_head) tgt = Targets{nullptr, ctx->Y, N, off + b * B, ctx->DP, m->ymean, m->ystd};
+      if (!xin || !m->fused_head) {
+        hipLaunchKernelGGL(k_gather, dim3(1024), dim3(256), 0, m->stream, ctx->X, ctx->xdtype,
+                           m->D, N, off + b * B, n, ctx->Y, ctx->DP, m->d, m->ymean, m->ystd,
+                           xin ? nullptr : m->Xb, m->Tb);
+        MCHK(m, hipGetLastError());
+      }
+      MTRY(forward(m, n, false, xin));
+      MTRY(backward(m, n, last, true, xin, tgt));
+    }
+  }
+  return FSNE_OK;
+}
+
 
 float loss_of(fsne_mlp* m, int64_t cnt) {
   float part[kLossBlocks];
@@ -957,8 +1023,11 @@ fsne_status fsne_mlp_create(const fsne_ctx* ctx, const fsne_mlp_opts* opts, fsne
       (st = malloc_dev(m, &m->ymean, m->d)) || (st = malloc_dev(m, &m->ystd, m->d)) ||
       (st = malloc_dev(m, &m->Xb, B * m->D)) || (st = malloc_dev(m, &m->Tb, B * m->d)) ||
       (st = malloc_dev(m, &m->H1b, B * m->H1)) || (st = malloc_dev(m, &m->H2b, B * m->H2)) ||
+      (st = malloc_dev(m, &m->dH1b, B * m->H1)) || (st = malloc_dev(m, &m->dH2b, B * m->H2)) ||
+      (st = malloc_dev(m, &m->W1b, (size_t)m->H1 * m->D)) ||
+      (st = malloc_dev(m, &m->W2b, (size_t)m->H2 * m->H1)) ||
       (st = malloc_dev(m, &m->Ob, B * m->d)) || (st = malloc_dev(m, &m->dOb, B * m->d)) ||
-      (st = malloc_dev(m, &m->dH1, B * m->H1)) || (st = malloc_dev(m, &m->dH2, B * m->H2)) ||
+      (st = malloc_dev(m, &m->dH2, B * m->H2)) ||
       (st = malloc_dev(m, &m->lpart, kLossBlocks)) ||
       (st = malloc_dev(m, &m->ws, (size_t)kMaxSplit * m->H1 * m->D)) ||
       (st = malloc_dev(m, &m->ws2, (size_t)kMaxSplit * m->H2 * m->H1)) ||
@@ -1008,34 +1077,40 @@ fsne_status fsne_mlp_train(fsne_mlp* m, fsne_ctx* ctx, float* final_loss) {
   const int64_t B = m->opts.batch;
   const int64_t nb = (N + B - 1) / B;
   MCHK(m, hipMemsetAsync(m->lpart, 0, sizeof(float) * kLossBlocks, m->stream));
-  for (int e = 0; e < m->opts.epochs; ++e) {
-    const int64_t off = ((int64_t)e * 104729) % N;
-    const int last = e == m->opts.epochs - 1;
-    for (int64_t b = 0; b < nb; ++b) {
-      const int n = (int)std::min<int64_t>(B, N - b * B);
-      const int64_t row0 = (off + b * B) % N;
-      // FP32 rows that do not wrap around are read where they are
-      const float* xin = ctx->xdtype == FSNE_F32 && (m->D & 3) == 0 && row0 + n <= N
-                             ? static_cast<const float*>(ctx->X) + row0 * m->D
-                             : nullptr;
-      // with the fused loss kernel the targets are read there from Y
-      Targets tgt{};
-      if (m->fused_head) tgt = Targets{nullptr, ctx->Y, N, off + b * B, ctx->DP, m->ymean, m->ystd};
-      if (!xin || !m->fused_head) {
-        hipLaunchKernelGGL(k_gather, dim3(1024), dim3(256), 0, m->stream, ctx->X, ctx->xdtype,
-                           m->D, N, off + b * B, n, ctx->Y, ctx->DP, m->d, m->ymean, m->ystd,
-                           xin ? nullptr : m->Xb, m->Tb);
-        MCHK(m, hipGetLastError());
+  // The product operands are bfloat16: BF16 rows are read in place, FP32
+  // rows are rounded once into a copy held for this call (every epoch reads
+  // each row twice), or, if that copy cannot be allocated, per batch.
+  const uint16_t* rows = nullptr;
+  uint16_t* copy = nullptr;
+  if ((m->D & 7) == 0) {
+    if (ctx->xdtype == FSNE_BF16) {
+      rows = static_cast<const uint16_t*>(ctx->X);
+    } else if (m->opts.epochs > 1 &&
+               hipMalloc(reinterpret_cast<void**>(&copy), sizeof(uint16_t) * N * m->D) == hipSuccess) {
+      hipLaunchKernelGGL(k_to_bf16, dim3(4096), dim3(256), 0, m->stream,
+                         static_cast<const float*>(ctx->X), copy, N * m->D);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) {
+        (void)hipFree(copy);
+        return mfail(m, FSNE_EHIP, std::string("k_to_bf16: ") + hipGetErrorString(e));
       }
-      MTRY(forward(m, n, false, xin));
-      MTRY(backward(m, n, last, true, xin, tgt));
+      rows = copy;
+    } else {
+      (void)hipGetLastError();   // a failed allocation leaves its error behind
     }
   }
+  const fsne_status st = train_epochs(m, ctx, rows, N, B, nb);
+  if (copy) {
+    (void)hipStreamSynchronize(m->stream);
+    (void)hipFree(copy);
+  }
+  MTRY(st);
   // mean squared error over the last epoch (each of the N rows once)
   if (final_loss) *final_loss = m->opts.epochs > 0 ? loss_of(m, N * m->d) : NAN;
   MCHK(m, hipStreamSynchronize(m->stream));
   return FSNE_OK;
 }
+
 
 fsne_status fsne_mlp_predict(fsne_mlp* m, const void* X, int64_t n, float* Y) {
   if (!m) return FSNE_EINVAL;
@@ -1068,7 +1143,10 @@ fsne_status fsne_mlp_get_params(fsne_mlp* m, float* params, float* ymean, float*
 fsne_status fsne_mlp_set_params(fsne_mlp* m, const float* params, const float* ymean,
                                 const float* ystd) {
   if (!m) return FSNE_EINVAL;
-  if (params) MCHK(m, hipMemcpyAsync(m->P, params, sizeof(float) * m->np, hipMemcpyHostToDevice, m->stream));
+  if (params) {
+    MCHK(m, hipMemcpyAsync(m->P, params, sizeof(float) * m->np, hipMemcpyHostToDevice, m->stream));
+    m->wdirty = true;
+  }
   if (ymean) MCHK(m, hipMemcpyAsync(m->ymean, ymean, sizeof(float) * m->d, hipMemcpyHostToDevice, m->stream));
   if (ystd) MCHK(m, hipMemcpyAsync(m->ystd, ystd, sizeof(float) * m->d, hipMemcpyHostToDevice, m->stream));
   MCHK(m, hipStreamSynchronize(m->stream));
@@ -1105,8 +1183,8 @@ void fsne_mlp_destroy(fsne_mlp* m) {
   if (!m) return;
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   void* bufs[] = {m->P, m->G, m->Mo, m->Vo, m->ymean, m->ystd, m->Xb, m->Tb, m->H1b, m->H2b,
-                  m->Ob, m->dOb, m->dH1, m->dH2, m->lpart, m->ws, m->ws2, m->part, m->part3,
-                  m->colpart, m->lchunk, m->xstage};
+                  m->Ob, m->dOb, m->dH1b, m->dH2, m->dH2b, m->W1b, m->W2b, m->lpart, m->ws,
+                  m->ws2, m->part, m->part3, m->colpart, m->lchunk, m->xstage};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (m->stream) (void)hipStreamDestroy(m->stream);
