@@ -1227,6 +1227,10 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
   constexpr int LP = (HL + RPI - 1) / RPI;      // passes over the HD list
   constexpr bool PRE_H = !LONG_H && LP * VEC <= 8;   // HD rows kept in registers
   constexpr bool PRE_E = Geo::CACHE;            // entry rows kept in registers
+  // negative samples' rows loaded with the first loads only for narrow rows:
+  // at d = 16 their registers cost the kernel its eighth wave per SIMD
+  // (70 against 64 VGPRs), which was worth more than the early load
+  constexpr bool PRE_N = DP <= 8;
   __shared__ LdLds<HS> lds_all[kWavesPerBlock];
   LdLds<HS>& S = lds_all[threadIdx.x / kWave];
   const int32_t i = (int32_t)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
@@ -1280,8 +1284,8 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
         load_chunk<VEC>(yrow + (int64_t)id * DP, er[p]);
     }
   }
-  float yn[VEC];
-  {
+  float yn[PRE_N ? VEC : 1];
+  if constexpr (PRE_N) {
     const int id = __shfl(jn, rg & (kWave - 1));
     if (nneg <= RPI && rg < nneg) load_chunk<VEC>(yrow + (int64_t)id * DP, yn);
   }
@@ -1470,9 +1474,9 @@ __global__ __launch_bounds__(kBlock) void k_ld_grad(StepArgs a) {
 #pragma unroll
     for (int v = 0; v < VEC; ++v) yj[v] = yi[v];
     if (id >= 0) {
-      if (nneg <= RPI) {
+      if (PRE_N && nneg <= RPI) {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) yj[v] = yn[v];
+        for (int v = 0; v < (PRE_N ? VEC : 1); ++v) yj[v] = yn[v];
       } else {
         load_chunk<VEC>(yrow + (int64_t)id * DP, yj);
       }
