@@ -931,6 +931,43 @@ def mlp_flops(D, H1, H2, d, n):
     return fwd + bwd
 
 
+def mlp_train_run(F, args):
+    """Training time of the placement network alone (784 -> 512 -> 512 -> 2,
+    default options: 5 epochs, batches of 4096, Adam) on the online-use
+    workload's 500,000 styled image-like rows, with targets from the
+    embedding's initial placement (the time does not depend on them); two
+    trainings from a new network each."""
+    import numpy as np
+    import torch
+
+    from inputs.generators import CONFIGS, RUN_SEED, image_styles, y_init
+
+    cfg = CONFIGS["dynamic_500k"]
+    N0 = cfg["N"]
+    rng = np.random.default_rng(cfg["data_seed"] + 11)
+    X, _ = image_styles(rng.permutation(np.arange(N0) % 10), seed=cfg["data_seed"],
+                        proto_seed=CONFIGS["image_70k"]["data_seed"])
+    hp = F.fsne_default_hparams(perplexity=10.0, lr=N0 / 48.0, n_neg=16)
+    emb = F.Embedding(X, y_init(N0, cfg["d"]), cfg["d"], cfg["K_hd"], cfg["K_ld"], seed=RUN_SEED,
+                      hp=hp)
+    o = F.fsne_mlp_default_opts()
+    flops = o.epochs * mlp_flops(X.shape[1], o.hidden1, o.hidden2, cfg["d"], N0)
+    out = {"metric": "placement network training seconds", "config": {
+        "workload": "500,000 styled image-like rows, 784 -> 512 -> 512 -> 2, 5 epochs, "
+                    "batches of 4096"}, "runs": []}
+    for _ in range(2):
+        net = F.Mlp(emb, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net.train(emb)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        net.close()
+        out["runs"].append({"seconds": round(t, 4), "TFLOPps": round(flops / t / 1e12, 1)})
+    emb.close()
+    return out
+
+
 def dynamic_run(F, args):
     """Online use with learned placement.
 
@@ -1127,6 +1164,8 @@ def main():
                     default=[10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000])
     ap.add_argument("--large", action="store_true",
                     help="run the 4M-point BF16 workload instead")
+    ap.add_argument("--mlp-train", action="store_true",
+                    help="time the placement network's training alone")
     ap.add_argument("--large-steps-only", action="store_true",
                     help="with --large: only the step timings (no 500-iteration runs)")
     ap.add_argument("--reorder-every", type=int, default=25,
@@ -1201,6 +1240,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.dynamic:
         print(json.dumps(dynamic_run(F, args)))
+        return
+    if args.mlp_train:
+        print(json.dumps(mlp_train_run(F, args)))
         return
     if args.feedback:
         print(json.dumps(feedback_run(F, args)))
