@@ -259,6 +259,109 @@ def cpu_baseline(X, cfg, Y0, seed, n_one=200_000):
                                         "count"}}
 
 
+def cpu_baseline_configs(args):
+    """The cpu_baseline leg over the method's workloads: the FP64 oracle on
+    every host thread and on one.  blobs_2k: its whole 500-iteration run
+    under the coin with the standard schedule; image_70k (alpha 1): its
+    first 100 iterations under the coin (5 on one thread); manifold_1m (FP32
+    rows) and zipf_4m (BF16 rows): HD-refining and LD-only iterations after
+    an untimed init, on one thread over a uniform sample of the rows (the
+    first rows of the shuffled set) scaled to N by the point count.  Each
+    timed part prints a progress line to stderr."""
+    import numpy as np
+
+    from inputs.generators import RUN_SEED, f32_to_bf16_bits, make_workload, y_init
+    from oracle import oracle as O
+
+    threads = O.num_threads()
+
+    def log(msg):
+        print(f"[cpu_baseline] {msg}", file=sys.stderr, flush=True)
+
+    def hyper(cfg, N, t, hd_mode):
+        early = t < 250
+        return O.Hyper(alpha=cfg["alpha"], perplexity=cfg["perplexity"], lr=float(N / 12.0),
+                       momentum=0.5 if early else 0.8, attr=12.0 if early else 1.0,
+                       n_neg=cfg["n_neg"], hd_mode=hd_mode)
+
+    def state(X, cfg, Y0):
+        N = X.shape[0]
+        return O.OracleState(X, cfg["d"], cfg["K_hd"], cfg["K_ld"], RUN_SEED, Y0).init(
+            hyper(cfg, N, 0, 0))
+
+    def coin_run(X, cfg, n_iter):
+        N = X.shape[0]
+        S = state(X, cfg, y_init(N, cfg["d"]))
+        fired, t0 = 0, time.perf_counter()
+        for t in range(n_iter):
+            fired += S.step(hyper(cfg, N, t, 0))["fired"]
+        return time.perf_counter() - t0, fired
+
+    def fixed_iters(X, cfg, n_hd, n_ld):
+        N = X.shape[0]
+        S = state(X, cfg, y_init(N, cfg["d"]))
+        t0 = time.perf_counter()
+        for t in range(n_hd):
+            S.step(hyper(cfg, N, t, 1))
+            log(f"  HD-refining iteration {t + 1} of {n_hd} done")
+        t1 = time.perf_counter()
+        for t in range(n_ld):
+            S.step(hyper(cfg, N, n_hd + t, 2))
+        t2 = time.perf_counter()
+        return (t1 - t0) / max(n_hd, 1), (t2 - t1) / max(n_ld, 1)
+
+    out = {"metric": "oracle seconds per iteration per workload (FP64 C, OpenMP over points)",
+           "cores": threads, "workloads": {}}
+    W = out["workloads"]
+    try:
+        # configuration 1: the whole run
+        X, _, cfg = make_workload("blobs_2k")
+        for nt in (threads, 1):
+            O.set_num_threads(nt)
+            dt, fired = coin_run(X, cfg, cfg["n_iter"])
+            W.setdefault("blobs_2k", {})[f"threads_{nt}"] = {
+                "iterations": cfg["n_iter"], "refinements": fired, "seconds": round(dt, 3),
+                "s_per_iter": round(dt / cfg["n_iter"], 5)}
+            log(f"blobs_2k {nt} threads: {dt:.2f} s")
+        # configuration 2 at alpha 1: the first iterations of the run
+        X, _, cfg = make_workload("image_70k")
+        cfg["alpha"] = 1.0
+        for nt, n in ((threads, 100), (1, 5)):
+            O.set_num_threads(nt)
+            dt, fired = coin_run(X, cfg, n)
+            W.setdefault("image_70k", {})[f"threads_{nt}"] = {
+                "iterations": n, "refinements": fired, "seconds": round(dt, 3),
+                "s_per_iter": round(dt / n, 4)}
+            log(f"image_70k {nt} threads: {dt:.2f} s")
+        del X
+        # configurations 3 and 5: HD-refining and LD-only iterations
+        for name, bf16, n_fix, n_one, sample in (("manifold_1m", False, 5, 2, 200_000),
+                                                 ("zipf_4m", True, 3, 2, 200_000)):
+            X, _, cfg = make_workload(name)
+            if bf16:
+                X = f32_to_bf16_bits(X)
+            N = X.shape[0]
+            log(f"{name}: rows ready")
+            O.set_num_threads(threads)
+            hd, ld = fixed_iters(X, cfg, n_fix, n_fix)
+            W[name] = {"rows": "BF16" if bf16 else "FP32", f"threads_{threads}": {
+                "hd_iterations": n_fix, "ld_iterations": n_fix, "s_per_hd_iter": round(hd, 3),
+                "s_per_ld_iter": round(ld, 3), "points": N}}
+            log(f"{name} {threads} threads: HD {hd:.2f} s, LD {ld:.2f} s per iteration")
+            O.set_num_threads(1)
+            ns = min(sample, N)
+            hd1, ld1 = fixed_iters(np.ascontiguousarray(X[:ns]), cfg, n_one, n_one)
+            W[name]["threads_1"] = {
+                "hd_iterations": n_one, "ld_iterations": n_one, "points": ns,
+                "s_per_hd_iter_scaled": round(hd1 * N / ns, 2),
+                "s_per_ld_iter_scaled": round(ld1 * N / ns, 2)}
+            log(f"{name} 1 thread ({ns} rows): HD {hd1:.2f} s, LD {ld1:.2f} s per iteration")
+            del X
+    finally:
+        O.set_num_threads(threads)
+    return out
+
+
 def feedback_run(F, args):
     """Quality of the HD lists over the iterations with the embedding held
     fixed (learning rate 0: the LD side gives no feedback) and optimised, at
@@ -965,7 +1068,52 @@ def mlp_train_run(F, args):
         net.close()
         out["runs"].append({"seconds": round(t, 4), "TFLOPps": round(flops / t / 1e12, 1)})
     emb.close()
+    out["library_products"] = library_products(X.shape[1], o.hidden1, o.hidden2, o.batch)
     return out
+
+
+def library_products(D, H1, H2, B, reps=200):
+    """For comparison only: the network's five products of one batch as plain
+    library products (torch.mm on BF16 operands, which ROCm serves with
+    hipBLASLt), without the fused bias, ReLU, mask and column sums, timed with
+    events over back-to-back calls; and one large square product to show the
+    library's rate where the shape allows it."""
+    import torch
+
+    dev = "cuda"
+    g = torch.Generator(device=dev).manual_seed(5)
+
+    def rnd(*shape):
+        return torch.randn(*shape, device=dev, dtype=torch.bfloat16, generator=g)
+
+    X, H1m, dH2, dH1 = rnd(B, D), rnd(B, H1), rnd(B, H2), rnd(B, H1)
+    W1t, W2t, W2 = rnd(D, H1), rnd(H1, H2), rnd(H2, H1)
+    dH2t, dH1t = dH2.t().contiguous(), dH1.t().contiguous()
+    S = rnd(8192, 8192)
+    cases = [
+        (f"H1 = X W1^T ({B} x {H1} x {D})", lambda: torch.mm(X, W1t), 2 * B * H1 * D),
+        (f"H2 = H1 W2^T ({B} x {H2} x {H1})", lambda: torch.mm(H1m, W2t), 2 * B * H2 * H1),
+        (f"W2 gradient dH2^T H1 ({H2} x {H1} x {B})", lambda: torch.mm(dH2t, H1m),
+         2 * B * H2 * H1),
+        (f"dH1 = dH2 W2 ({B} x {H1} x {H2})", lambda: torch.mm(dH2, W2), 2 * B * H2 * H1),
+        (f"W1 gradient dH1^T X ({H1} x {D} x {B})", lambda: torch.mm(dH1t, X), 2 * B * H1 * D),
+        ("square 8192 x 8192 x 8192", lambda: torch.mm(S, S), 2 * 8192 ** 3),
+    ]
+    res = []
+    for name, fn, fl in cases:
+        n = 20 if name.startswith("square") else reps
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / n * 1e3
+        res.append({"product": name, "us": round(us, 2), "TFLOPps": round(fl / us / 1e6, 1)})
+    return res
 
 
 def dynamic_run(F, args):
@@ -1149,6 +1297,8 @@ def main():
     ap.add_argument("--queries", type=int, default=1000)
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-configs", action="store_true",
+                    help="the CPU baseline (FP64 oracle) over every workload, alone")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device to device (counter calibration)")
     ap.add_argument("--no-dynamic", action="store_true", help="skip the online-use experiment")
@@ -1211,6 +1361,9 @@ def main():
         return
     if args.summarize_profile:
         summarize_profile(args)
+        return
+    if args.cpu_baseline_configs:
+        print(json.dumps(cpu_baseline_configs(args)))
         return
     if args.copy_probe:
         import torch
