@@ -431,6 +431,22 @@ __device__ __forceinline__ void remember_rejections(int32_t* __restrict__ row, i
 // HD lists and the LD lists of iteration t, their distances, merge into the
 // sorted list, flag, and recalibration of beta_i when the list changed.
 // ---------------------------------------------------------------------------
+// The cuts an HD refinement leaves for the affinity pass that follows it:
+// the distances at ranks Kh/2 - 1, Kh/4 - 1 and 3Kh/4 - 1 of the point's new
+// list, where the membership scan halves its range (zero unless Kh is a
+// multiple of 8).  One 16-byte read of them replaces two dependent reads
+// of the list's distances.
+__device__ __forceinline__ void write_list_cuts(float4* cuts, int32_t i, const float* row,
+                                                int Kh) {
+  float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if ((Kh & 7) == 0) {
+    c.x = row[Kh / 2 - 1];
+    c.y = row[Kh / 4 - 1];
+    c.z = row[3 * Kh / 4 - 1];
+  }
+  cuts[i] = c;
+}
+
 template <typename TX, int VEC, int CH, bool SCREEN>
 __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
   const Scalars* sc = a.sc;
@@ -526,6 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
     remember_rejections(a.memo + (int64_t)i * kMemo, a.memo_w, memo, screened_out, rejected,
                         S.lst);
   }
+  if (lane == 0) write_list_cuts(a.cuts, i, S.row, Kh);
   if (changed) {
     const float sorted = lane < Kh ? S.row[lane] : 0.0f;
     const float4 r = calibrate_row(sorted, Kh, a.h, a.rec[i].x);
@@ -809,6 +826,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
     const int rejected = (live && hl < ncand && !enter) ? key_id(ck) : -1;
     remember_rejections2<MW>(a.memo, i, live, memo, screened_out, rejected, S.lst);
   }
+  if (live && hl == 0) write_list_cuts(a.cuts, i, S.row + hb, Kh);
   if (__ballot(changed) != 0ull) {
     const float sorted = hl < Kh ? S.row[hb + hl] : 0.0f;
     const float4 r = calibrate_row_half(sorted, Kh, a.h, live ? a.rec[i].x : 0.0f, changed);
@@ -959,6 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine_long(StepArgs a) {
     const int rejected = (lane < n && !enter) ? key_id(ck) : -1;
     remember_rejections(a.memo + (int64_t)i * kMemo, a.memo_w, memo, -1, rejected, S.lst);
   }
+  if (lane == 0) write_list_cuts(a.cuts, i, S.row, Kh);
   if (changed) {
     const float4 r = calibrate_row_lds(S.row, Kh, a.h, a.rec[i].x);
     if (lane == 0) a.rec[i] = r;
@@ -1025,7 +1044,8 @@ __global__ __launch_bounds__(kBlock) void k_init_lists_long(const TX* __restrict
 //   p_{i|j} = exp(-beta_j (d2 - m_j)) invS_j if i is in j's HD list, else 0.
 // standalone = 1: run regardless of the coin, on the current lists.
 // ---------------------------------------------------------------------------
-constexpr int kPsymHalvings = 2;   // range halvings of the membership scan
+constexpr int kPsymHalvings = 2;   // range halvings of the membership scan (the cuts
+                                    // a refinement leaves cover two)
 
 __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
   const Scalars* sc = a.sc;
@@ -1063,9 +1083,11 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
         // an injected state, hence the band): i can only be in the part of
         // j's list its distance falls in, found by halving the range while
         // the parts stay whole 4-entry groups; near a cut both are kept.
+        // (the cuts come from the refinement: Kh/2, then Kh/4 or 3Kh/4)
+        const float4 cj = a.cuts[j];
         for (int h = 0; h < kPsymHalvings && ((hi - lo) & 7) == 0; ++h) {
           const int m = (lo + hi) >> 1;
-          const float cut = hd[(int64_t)j * Kh + m - 1];
+          const float cut = h == 0 ? cj.x : lo == 0 ? cj.y : cj.z;
           if (d2 < cut * (1.0f - 1e-5f))
             hi = m;
           else if (d2 > cut * (1.0f + 1e-5f))
