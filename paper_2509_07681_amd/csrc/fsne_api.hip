@@ -98,7 +98,7 @@ StepArgs make_args(const fsne_ctx* c) {
     a.ld_idx[b] = c->ld_idx[b];
   }
   a.rec = c->rec;
-  a.cuts = c->cuts;
+  a.psh = c->psh;
   a.P = c->P;
   a.flags = c->flags;
   a.Y = c->Y;
@@ -303,7 +303,7 @@ fsne_status alloc_state(fsne_ctx* c) {
     TRY(dalloc(c, &c->ld_idx[b], cap * c->Kl));
   }
   TRY(dalloc(c, &c->rec, cap));
-  TRY(dalloc(c, &c->cuts, cap));
+  TRY(dalloc(c, &c->psh, 2 * cap));
   TRY(dalloc(c, &c->flags, cap));
   TRY(dalloc(c, &c->moved, cap));
   TRY(dalloc(c, &c->memo, cap * fsne::kMemo));

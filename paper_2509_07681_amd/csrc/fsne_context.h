@@ -28,7 +28,7 @@ struct fsne_ctx {
   float* hd_d2[2] = {nullptr, nullptr};
   int32_t* ld_idx[2] = {nullptr, nullptr};
   float4* rec = nullptr;
-  float4* cuts = nullptr;    // cap: list cuts a refinement leaves for the affinity pass
+  float4* psh = nullptr;     // cap x 2: record and list cuts a refinement leaves for the affinity pass
   uint8_t* flags = nullptr;
   uint8_t* moved = nullptr;
   int32_t* memo = nullptr;   // cap x kMemo rejected HD candidates, -1 = empty

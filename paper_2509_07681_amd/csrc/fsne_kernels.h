@@ -24,10 +24,10 @@ struct StepArgs {
   float* hd_d2[2];
   int32_t* ld_idx[2];
   float4* rec;              // per point {beta, m, r, invS}
-  // per point, written by each HD refinement for the affinity pass that
-  // follows it: distances at ranks Kh/2-1, Kh/4-1, 3Kh/4-1 of the new list
-  // (0 unless Kh is a multiple of 8), then 0
-  float4* cuts;
+  // two per point, written by each HD refinement for the affinity pass that
+  // follows it: the record, then the distances at ranks Kh/2-1, Kh/4-1,
+  // 3Kh/4-1 of the new list (0 unless Kh is a multiple of 8) and 0
+  float4* psh;
   float* P;                 // N x Kh
   uint8_t* flags;           // N
   float* Y;                 // N x DP

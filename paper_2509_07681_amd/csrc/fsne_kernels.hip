@@ -431,20 +431,23 @@ __device__ __forceinline__ void remember_rejections(int32_t* __restrict__ row, i
 // HD lists and the LD lists of iteration t, their distances, merge into the
 // sorted list, flag, and recalibration of beta_i when the list changed.
 // ---------------------------------------------------------------------------
-// The cuts an HD refinement leaves for the affinity pass that follows it:
-// the distances at ranks Kh/2 - 1, Kh/4 - 1 and 3Kh/4 - 1 of the point's new
-// list, where the membership scan halves its range (zero unless Kh is a
-// multiple of 8).  One 16-byte read of them replaces two dependent reads
-// of the list's distances.
-__device__ __forceinline__ void write_list_cuts(float4* cuts, int32_t i, const float* row,
-                                                int Kh) {
+// What an HD refinement leaves for the affinity pass that follows it, 32
+// bytes per point: the point's calibration record, then the distances at
+// ranks Kh/2 - 1, Kh/4 - 1 and 3Kh/4 - 1 of its new list, where the
+// membership scan halves its range (zero unless Kh is a multiple of 8).  The
+// pass reads the record half for every entry it recomputes and the cut half
+// only where it scans, from the line the first read brought in: one line per
+// neighbour instead of the record's, two of its distances' and its list's.
+__device__ __forceinline__ void write_psym_head(float4* psh, int32_t i, const float4& rec,
+                                                const float* row, int Kh) {
   float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if ((Kh & 7) == 0) {
     c.x = row[Kh / 2 - 1];
     c.y = row[Kh / 4 - 1];
     c.z = row[3 * Kh / 4 - 1];
   }
-  cuts[i] = c;
+  psh[2 * (int64_t)i] = rec;
+  psh[2 * (int64_t)i + 1] = c;
 }
 
 template <typename TX, int VEC, int CH, bool SCREEN>
@@ -542,12 +545,13 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine(StepArgs a) {
     remember_rejections(a.memo + (int64_t)i * kMemo, a.memo_w, memo, screened_out, rejected,
                         S.lst);
   }
-  if (lane == 0) write_list_cuts(a.cuts, i, S.row, Kh);
+  float4 r = a.rec[i];
   if (changed) {
     const float sorted = lane < Kh ? S.row[lane] : 0.0f;
-    const float4 r = calibrate_row(sorted, Kh, a.h, a.rec[i].x);
+    r = calibrate_row(sorted, Kh, a.h, r.x);
     if (lane == 0) a.rec[i] = r;
   }
+  if (lane == 0) write_psym_head(a.psh, i, r, S.row, Kh);
 }
 
 // ---------------------------------------------------------------------------
@@ -826,12 +830,14 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine2(StepArgs a) {
     const int rejected = (live && hl < ncand && !enter) ? key_id(ck) : -1;
     remember_rejections2<MW>(a.memo, i, live, memo, screened_out, rejected, S.lst);
   }
-  if (live && hl == 0) write_list_cuts(a.cuts, i, S.row + hb, Kh);
+  float4 r = live ? a.rec[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if (__ballot(changed) != 0ull) {
     const float sorted = hl < Kh ? S.row[hb + hl] : 0.0f;
-    const float4 r = calibrate_row_half(sorted, Kh, a.h, live ? a.rec[i].x : 0.0f, changed);
+    const float4 rn = calibrate_row_half(sorted, Kh, a.h, r.x, changed);
+    if (changed) r = rn;
     if (changed && hl == 0) a.rec[i] = r;
   }
+  if (live && hl == 0) write_psym_head(a.psh, i, r, S.row + hb, Kh);
 }
 
 // ---------------------------------------------------------------------------
@@ -977,11 +983,12 @@ __global__ __launch_bounds__(kBlock) void k_hd_refine_long(StepArgs a) {
     const int rejected = (lane < n && !enter) ? key_id(ck) : -1;
     remember_rejections(a.memo + (int64_t)i * kMemo, a.memo_w, memo, -1, rejected, S.lst);
   }
-  if (lane == 0) write_list_cuts(a.cuts, i, S.row, Kh);
+  float4 r = a.rec[i];
   if (changed) {
-    const float4 r = calibrate_row_lds(S.row, Kh, a.h, a.rec[i].x);
+    r = calibrate_row_lds(S.row, Kh, a.h, r.x);
     if (lane == 0) a.rec[i] = r;
   }
+  if (lane == 0) write_psym_head(a.psh, i, r, S.row, Kh);
 }
 
 // Initial lists for K_hd > 64: the rule of k_init_lists, the HD list sorted
@@ -1044,8 +1051,8 @@ __global__ __launch_bounds__(kBlock) void k_init_lists_long(const TX* __restrict
 //   p_{i|j} = exp(-beta_j (d2 - m_j)) invS_j if i is in j's HD list, else 0.
 // standalone = 1: run regardless of the coin, on the current lists.
 // ---------------------------------------------------------------------------
-constexpr int kPsymHalvings = 2;   // range halvings of the membership scan (the cuts
-                                    // a refinement leaves cover two)
+constexpr int kPsymHalvings = 2;   // range halvings of the membership scan
+static_assert(kPsymHalvings == 2, "the list cuts a refinement leaves cover two halvings");
 
 __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
   const Scalars* sc = a.sc;
@@ -1067,7 +1074,9 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
   if (!standalone && !(a.flags[i] & 1u) && !(a.flags[j] & 1u)) return;
   const float d2 = hd[q];
   const float4 ri = a.rec[i];
-  const float4 rj = a.rec[j];
+  // after a refinement j's record comes from the line that also holds its
+  // list cuts (the same values as rec[j])
+  const float4 rj = standalone ? a.rec[j] : a.psh[2 * (int64_t)j];
   const float pji = expf(-ri.x * (d2 - ri.y)) * ri.w;
   // Every stored HD distance comes from the same symmetric FP32 computation,
   // so i can only be in j's sorted list if d2 <= r_j (j's largest distance);
@@ -1084,7 +1093,7 @@ __global__ __launch_bounds__(kBlock) void k_psym(StepArgs a, int standalone) {
         // j's list its distance falls in, found by halving the range while
         // the parts stay whole 4-entry groups; near a cut both are kept.
         // (the cuts come from the refinement: Kh/2, then Kh/4 or 3Kh/4)
-        const float4 cj = a.cuts[j];
+        const float4 cj = a.psh[2 * (int64_t)j + 1];
         for (int h = 0; h < kPsymHalvings && ((hi - lo) & 7) == 0; ++h) {
           const int m = (lo + hi) >> 1;
           const float cut = h == 0 ? cj.x : lo == 0 ? cj.y : cj.z;
