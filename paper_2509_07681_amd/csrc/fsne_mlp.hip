@@ -233,7 +233,19 @@ __device__ __forceinline__ void tile_load(const uint16_t* __restrict__ P, int64_
   }
 }
 
-// Stores the tile into LDS columns k0 .. k0+63, laid out [row][k].
+// Column of element k of tile row `row` in LDS.  A tile stored by the
+// transposing path below (8 rows of one thread, a word each, rows 8 apart
+// across lanes) has the 16-byte chunks of each row (8 k each) permuted by
+// XOR with bits 3..5 of the row, so that those stores spread over all banks
+// instead of hitting 4 of them; a tile stored row-contiguous keeps the plain
+// layout, whose 16-byte stores and MFMA operand reads are conflict-free.
+template <bool KC>
+__device__ __forceinline__ int tile_col(int row, int k) {
+  if constexpr (KC) return k;
+  return (((k >> 3) ^ ((row >> 3) & 7)) << 3) | (k & 7);
+}
+
+// Stores the tile into LDS columns k0 .. k0+63, laid out [row][tile_col(k)].
 template <bool KC, int TP>
 __device__ __forceinline__ void tile_store(uint16_t (*L)[TP], int k0, const uint4* v) {
   const int tid = threadIdx.x;
@@ -241,13 +253,15 @@ __device__ __forceinline__ void tile_store(uint16_t (*L)[TP], int k0, const uint
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int idx = tid + 256 * j;
-      *reinterpret_cast<uint4*>(&L[idx >> 3][k0 + ((idx & 7) << 3)]) = v[j];
+      const int row = idx >> 3;
+      *reinterpret_cast<uint4*>(&L[row][tile_col<KC>(row, k0 + ((idx & 7) << 3))]) = v[j];
     }
   } else {
     const int k = (tid >> 3) << 1, r = (tid & 7) << 3;
 #pragma unroll
     for (int i = 0; i < 8; ++i)
-      *reinterpret_cast<uint32_t*>(&L[r + i][k0 + k]) = half_of(v[0], i) | (half_of(v[1], i) << 16);
+      *reinterpret_cast<uint32_t*>(&L[r + i][tile_col<KC>(r + i, k0 + k)]) =
+          half_of(v[0], i) | (half_of(v[1], i) << 16);
   }
 }
 
@@ -298,8 +312,9 @@ __global__ __launch_bounds__(256) void k_gemm_v(GemmArgs g) {
     for (int s = 0; s < TK; s += 16) {
       if (s < steps) {
         const int kk = s + (lane >> 5) * 8;
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm * 32 + (lane & 31)][kk]);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn * 32 + (lane & 31)][kk]);
+        const int ra = wm * 32 + (lane & 31), rb = wn * 32 + (lane & 31);
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[ra][tile_col<AK>(ra, kk)]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[rb][tile_col<BK>(rb, kk)]);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
       }
     }
