@@ -1164,9 +1164,11 @@ __device__ __forceinline__ void load_chunk(const float* __restrict__ p, float* r
 // summed pairwise as a balanced binary tree with the components in index
 // order at the leaves (padding components are zero and change nothing).  A
 // lane holds VEC consecutive components, the row's G lanes hold the row in
-// order, so the lane's pairs come first, then lanes are paired by xor
-// butterflies (x + y = y + x exactly, so both lanes of a pair get the same
-// node); every lane of the group ends with the total.
+// order, so the lane's pairs come first, then neighbouring lanes, quads,
+// 8-lane and 16-lane groups are added by DPP exchanges inside the row
+// (x + y = y + x exactly, so both sides of a pair get the same node); every
+// lane of the group ends with the total.  G <= 16, so no exchange leaves a
+// row and none goes through LDS.
 template <int DP>
 __device__ __forceinline__ float ld_decision_d2(const float* yi, const float* yj, int q) {
 #pragma clang fp contract(off)
@@ -1182,8 +1184,8 @@ __device__ __forceinline__ float ld_decision_d2(const float* yi, const float* yj
     s = (sq[0] + sq[1]) + (sq[2] + sq[3]);
   else
     s = sq[0] + sq[1];
-#pragma unroll
-  for (int m = 1; m < Geo::G; m <<= 1) s = s + __shfl_xor(s, m);
+  static_assert(Geo::G <= 16, "a row group stays within a DPP row");
+  s = group_sum_dpp(s, Geo::G);
   (void)q;
   return s;
 }
