@@ -436,8 +436,9 @@ __device__ __forceinline__ void remember_rejections(int32_t* __restrict__ row, i
 // ranks Kh/2 - 1, Kh/4 - 1 and 3Kh/4 - 1 of its new list, where the
 // membership scan halves its range (zero unless Kh is a multiple of 8).  The
 // pass reads the record half for every entry it recomputes and the cut half
-// only where it scans, from the line the first read brought in: one line per
-// neighbour instead of the record's, two of its distances' and its list's.
+// only where it scans, from the line the first read brought in, so a
+// neighbour's record and cuts cost one line where the record and two of its
+// list's distances took two or three.
 __device__ __forceinline__ void write_psym_head(float4* psh, int32_t i, const float4& rec,
                                                 const float* row, int Kh) {
   float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
